@@ -1,0 +1,1078 @@
+/*
+ * tusq_oracle.c -- plain CPU oracle for noisy statevector simulation with
+ * error tallying, error commutation, pruning and depth-first tree traversal.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no source,
+ * header, table or helper with the GPU engine; both read the same circuit
+ * description and nothing else.
+ *
+ * Everything is deliberately simple: complex128 amplitudes, one gate at a
+ * time, left-to-right FP64 sums, and the error-commutation stage implemented
+ * literally with one stack per qubit.  Where the paper (TUSQ, arXiv
+ * 2508.04880) leaves a choice open, the reading taken is stated next to the
+ * code; the list of readings is kept with the project's design notes.
+ *
+ * Paper map for the citations below:
+ *   Sec. II, Eq. (1)        statevector update psi' = U psi
+ *   Sec. II (depolarising)  rho' = (1-p) rho + p/3 (X rho X + Y rho Y + Z rho Z);
+ *                           read as a weighted mixture of fixed-Pauli circuits
+ *   Sec. III-A.1            error realisations (ERs): sample every channel
+ *                           per shot; tally identical ERs
+ *   Sec. III-A.2/3          ER commutation rules 1-6 and the per-qubit stack
+ *                           greedy algorithm
+ *   Sec. III-A.4, Eq. (2)   pruning with alpha, beta; S_final
+ *   Sec. III-B              DFTT: forward = U, backtrack = U^-1
+ *   Sec. III-B.1            T_dftt = 2|E|, T_naive = N_l * h
+ *
+ * Parity status: every function here is pinned by tests against values
+ * that do not come from this file (published Philox vectors, density-matrix
+ * simulation, closed forms, brute-force operator identities), except the
+ * pruning selection stream, which follows a reading of the paper's
+ * "randomly sample" and is pinned only by its invariants.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Gate kinds (the oracle's own numbering; the Python wrapper maps names).   */
+enum { OK_U3 = 0, OK_RX, OK_RY, OK_RZ, OK_H, OK_S, OK_SDG, OK_T, OK_TDG,
+       OK_X, OK_Y, OK_Z, OK_CX, OK_NKINDS };
+
+/* Pauli codes: I=0, X=1, Y=2, Z=3. */
+
+typedef struct {
+    uint32_t n, G;
+    const uint8_t *kind;
+    const uint32_t *q0, *q1;
+    const double *params;   /* 3 per gate */
+    const uint8_t *nprob;   /* 0, 3 or 15 per gate */
+    const double *probs;    /* concatenated channel probabilities */
+} oc_circuit;
+
+static int oracle_threads = 1;
+void oc_set_threads(int t) { oracle_threads = t > 0 ? t : 1; }
+int oc_get_threads(void) { return oracle_threads; }
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from Salmon, Moraes, Dror and Shaw, "Parallel random       */
+/* numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two 32x32->64        */
+/* multiplies with the key bumped by the Weyl constants between rounds.      */
+void oc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* One 64-bit value: counter (sub, primary, aux, stream), key = seed; half 0
+ * is words 0|1<<32, half 1 is words 2|3<<32.  Streams: 0 error sampling,
+ * 1 pruning selection, 2 shot sampling. */
+static uint64_t draw64(uint64_t seed, uint32_t sub, uint32_t primary, uint32_t aux,
+                       uint32_t stream, int half)
+{
+    uint32_t ctr[4] = {sub, primary, aux, stream};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t o[4];
+    oc_philox(ctr, key, o);
+    if (half == 0) return (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+    return (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+}
+
+/* Integer cumulative thresholds of a Pauli channel: S_k is the plain
+ * left-to-right double sum p_1 + ... + p_k; C_k = floor(S_k * 2^64), or
+ * 2^64 - 1 once S_k reaches 1.  A uniform u64 u selects the smallest k with
+ * u < C_k, and the identity when u >= C_m. */
+void oc_thresholds(const double *p, int m, uint64_t *C)
+{
+    double s = 0.0;
+    for (int k = 0; k < m; ++k) {
+        s = s + p[k];
+        C[k] = (s >= 1.0) ? UINT64_MAX : (uint64_t)ldexp(s, 64);
+    }
+}
+
+static int pick_outcome(uint64_t u, const uint64_t *C, int m)
+{
+    for (int k = 0; k < m; ++k)
+        if (u < C[k]) return k + 1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Prepared circuit: channel table.                                         */
+typedef struct {
+    const oc_circuit *c;
+    uint32_t C;            /* number of channels */
+    int32_t *gate_chan;    /* per gate: channel index or -1 */
+    uint32_t *chan_gate;   /* per channel: gate index */
+    uint8_t *chan_m;       /* 3 or 15 */
+    uint64_t *chan_thr;    /* 15 per channel */
+} prep_t;
+
+static int is_two_qubit(uint8_t k) { return k == OK_CX; }
+
+static int validate(const oc_circuit *c)
+{
+    size_t off = 0;
+    for (uint32_t g = 0; g < c->G; ++g) {
+        if (c->kind[g] >= OK_NKINDS) return -1;
+        if (c->q0[g] >= c->n) return -1;
+        if (is_two_qubit(c->kind[g]) && (c->q1[g] >= c->n || c->q1[g] == c->q0[g])) return -1;
+        int m = c->nprob[g];
+        if (m != 0 && m != (is_two_qubit(c->kind[g]) ? 15 : 3)) return -1;
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) {
+            double p = c->probs[off + k];
+            if (!(p >= 0.0)) return -1;
+            s += p;
+        }
+        if (s > 1.0 + 1e-12) return -1;
+        off += m;
+    }
+    return 0;
+}
+
+static int prep_init(prep_t *P, const oc_circuit *c)
+{
+    memset(P, 0, sizeof(*P));
+    P->c = c;
+    if (validate(c)) return -1;
+    P->gate_chan = malloc(sizeof(int32_t) * (c->G + 1));
+    uint32_t C = 0;
+    for (uint32_t g = 0; g < c->G; ++g) C += c->nprob[g] ? 1 : 0;
+    P->C = C;
+    P->chan_gate = malloc(sizeof(uint32_t) * (C + 1));
+    P->chan_m = malloc(C + 1);
+    P->chan_thr = malloc(sizeof(uint64_t) * 15 * (C + 1));
+    size_t off = 0;
+    uint32_t ch = 0;
+    for (uint32_t g = 0; g < c->G; ++g) {
+        int m = c->nprob[g];
+        if (m) {
+            P->gate_chan[g] = (int32_t)ch;
+            P->chan_gate[ch] = g;
+            P->chan_m[ch] = (uint8_t)m;
+            oc_thresholds(c->probs + off, m, P->chan_thr + 15 * (size_t)ch);
+            ++ch;
+        } else {
+            P->gate_chan[g] = -1;
+        }
+        off += m;
+    }
+    return 0;
+}
+
+static void prep_free(prep_t *P)
+{
+    free(P->gate_chan); free(P->chan_gate); free(P->chan_m); free(P->chan_thr);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ER sampling (Sec. III-A.1): every channel sampled for every shot.  Shot j,
+ * channel c uses counter (c >> 1, j, 0, stream 0), half c & 1.  A raw ER is
+ * the list of (channel, outcome) with a non-identity outcome. */
+static int sample_shot(const prep_t *P, uint64_t seed, uint32_t shot, uint32_t *chan,
+                       uint8_t *out)
+{
+    int cnt = 0;
+    for (uint32_t c = 0; c < P->C; ++c) {
+        uint64_t u = draw64(seed, c >> 1, shot, 0, 0, (int)(c & 1));
+        int k = pick_outcome(u, P->chan_thr + 15 * (size_t)c, P->chan_m[c]);
+        if (k) { chan[cnt] = c; out[cnt] = (uint8_t)k; ++cnt; }
+    }
+    return cnt;
+}
+
+int oc_sample_shot(const oc_circuit *c, uint64_t seed, uint32_t shot, uint32_t *chan,
+                   uint8_t *out, uint32_t *n_out)
+{
+    prep_t P;
+    if (prep_init(&P, c)) return -1;
+    *n_out = (uint32_t)sample_shot(&P, seed, shot, chan, out);
+    prep_free(&P);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* ER commutation (Sec. III-A.2/3), implemented literally: one stack per
+ * qubit holding noiseless gates (value >= 0: the gate index) and noisy Pauli
+ * gates (value < 0: -code).  A noisy Pauli on a stack top moves past a
+ * noiseless gate when the paper's rules let it:
+ *   rule 2: through a noiseless Pauli gate;
+ *   rule 3: X through RX, Y through RY, Z through RZ;
+ *   rules 4-6: through CX, becoming its conjugate (X_c -> X_c X_t,
+ *              Z_t -> Z_c Z_t, Y_c -> Y_c X_t, Y_t -> Z_c Y_t).
+ * Any other gate keeps the noisy gate below it.  A new noisy gate merges with
+ * a noisy stack top (rule 1, products taken up to phase); a product equal to
+ * the identity disappears.  Reading: gates outside rules 1-6 (U3, H, S, T ...)
+ * block, and a Pauli left below gate g is reported at "slot g", i.e. just
+ * before g; those still on top at the end are at slot G. */
+
+typedef struct { int32_t *data; uint32_t size; uint32_t cap; } stack_t_;
+
+static int pauli_mul(int a, int b)
+{
+    /* symplectic (x, z): X=(1,0) Y=(1,1) Z=(0,1); product up to phase */
+    int ax = (a == 1 || a == 2), az = (a == 2 || a == 3);
+    int bx = (b == 1 || b == 2), bz = (b == 2 || b == 3);
+    int x = ax ^ bx, z = az ^ bz;
+    if (x && !z) return 1;
+    if (x && z) return 2;
+    if (!x && z) return 3;
+    return 0;
+}
+
+/* Conjugate the pair (P on control, Q on target) through CX. */
+static void cx_conjugate(int pc, int pt, int *oc, int *ot)
+{
+    int rc = 0, rt = 0;
+    /* X on control -> X_c X_t ; Z on control -> Z_c */
+    /* X on target  -> X_t     ; Z on target  -> Z_c Z_t */
+    int cx = (pc == 1 || pc == 2), cz = (pc == 2 || pc == 3);
+    int tx = (pt == 1 || pt == 2), tz = (pt == 2 || pt == 3);
+    if (cx) { rc = pauli_mul(rc, 1); rt = pauli_mul(rt, 1); }
+    if (cz) { rc = pauli_mul(rc, 3); }
+    if (tx) { rt = pauli_mul(rt, 1); }
+    if (tz) { rc = pauli_mul(rc, 3); rt = pauli_mul(rt, 3); }
+    *oc = rc; *ot = rt;
+}
+
+static int passes_1q(uint8_t kind, int p)
+{
+    switch (kind) {
+    case OK_X: case OK_Y: case OK_Z: return 1;      /* rule 2 */
+    case OK_RX: return p == 1;                       /* rule 3 */
+    case OK_RY: return p == 2;
+    case OK_RZ: return p == 3;
+    default: return 0;
+    }
+}
+
+static void push(stack_t_ *s, int32_t v) { s->data[s->size++] = v; }
+static int32_t top(const stack_t_ *s) { return s->size ? s->data[s->size - 1] : INT32_MAX; }
+
+static void noisy_arrive(stack_t_ *s, int p)
+{
+    if (!p) return;
+    int32_t t = top(s);
+    if (s->size && t < 0) {
+        int r = pauli_mul(-t, p);
+        if (r) s->data[s->size - 1] = -r;
+        else s->size--;
+    } else {
+        push(s, -p);
+    }
+}
+
+/* Event key: (slot << 32) | (qubit << 8) | pauli -- integer order equals
+ * (slot, qubit, pauli) order. */
+#define EVKEY(slot, q, p) (((uint64_t)(slot) << 32) | ((uint64_t)(q) << 8) | (uint64_t)(p))
+#define EV_SLOT(k) ((uint32_t)((k) >> 32))
+#define EV_QUBIT(k) ((uint32_t)(((k) >> 8) & 0xFFFFFFu))
+#define EV_PAULI(k) ((int)((k) & 0xFFu))
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+typedef struct {
+    stack_t_ *st;  /* n stacks */
+    int32_t *pool;
+} stacks_t;
+
+static void stacks_alloc(stacks_t *S, const oc_circuit *c)
+{
+    S->st = calloc(c->n, sizeof(stack_t_));
+    size_t *cnt = calloc(c->n, sizeof(size_t));
+    for (uint32_t g = 0; g < c->G; ++g) {
+        cnt[c->q0[g]]++;
+        if (is_two_qubit(c->kind[g])) cnt[c->q1[g]]++;
+    }
+    size_t tot = 0;
+    for (uint32_t q = 0; q < c->n; ++q) tot += 2 * cnt[q] + 2;
+    S->pool = malloc(sizeof(int32_t) * tot);
+    size_t off = 0;
+    for (uint32_t q = 0; q < c->n; ++q) {
+        S->st[q].data = S->pool + off;
+        S->st[q].cap = (uint32_t)(2 * cnt[q] + 2);
+        off += 2 * cnt[q] + 2;
+    }
+    free(cnt);
+}
+
+static void stacks_free(stacks_t *S) { free(S->st); free(S->pool); }
+
+/* Returns the number of canonical events written to keys (capacity n*(G+1)). */
+static int commute_one(const prep_t *P, stacks_t *S, int nraw, const uint32_t *chan,
+                       const uint8_t *outc, uint64_t *keys)
+{
+    const oc_circuit *c = P->c;
+    for (uint32_t q = 0; q < c->n; ++q) S->st[q].size = 0;
+    int ri = 0;
+    for (uint32_t g = 0; g < c->G; ++g) {
+        uint8_t k = c->kind[g];
+        if (is_two_qubit(k)) {
+            stack_t_ *sc = &S->st[c->q0[g]], *stt = &S->st[c->q1[g]];
+            int pc = 0, pt = 0;
+            if (sc->size && top(sc) < 0) { pc = -top(sc); sc->size--; }
+            if (stt->size && top(stt) < 0) { pt = -top(stt); stt->size--; }
+            push(sc, (int32_t)g);
+            push(stt, (int32_t)g);
+            int oc, ot;
+            cx_conjugate(pc, pt, &oc, &ot);
+            if (oc) push(sc, -oc);
+            if (ot) push(stt, -ot);
+        } else {
+            stack_t_ *s = &S->st[c->q0[g]];
+            if (s->size && top(s) < 0 && passes_1q(k, -top(s))) {
+                int32_t p = top(s);
+                s->size--;
+                push(s, (int32_t)g);
+                push(s, p);
+            } else {
+                push(s, (int32_t)g);
+            }
+        }
+        /* noisy gate that follows gate g */
+        int32_t ch = P->gate_chan[g];
+        if (ch >= 0 && ri < nraw && chan[ri] == (uint32_t)ch) {
+            int o = outc[ri++];
+            if (is_two_qubit(k)) {
+                noisy_arrive(&S->st[c->q0[g]], o >> 2);
+                noisy_arrive(&S->st[c->q1[g]], o & 3);
+            } else {
+                noisy_arrive(&S->st[c->q0[g]], o);
+            }
+        }
+    }
+    int ne = 0;
+    for (uint32_t q = 0; q < c->n; ++q) {
+        stack_t_ *s = &S->st[q];
+        for (uint32_t i = 0; i < s->size; ++i) {
+            if (s->data[i] < 0) {
+                uint32_t slot = c->G;
+                for (uint32_t j = i + 1; j < s->size; ++j)
+                    if (s->data[j] >= 0) { slot = (uint32_t)s->data[j]; break; }
+                keys[ne++] = EVKEY(slot, q, -s->data[i]);
+            }
+        }
+    }
+    qsort(keys, (size_t)ne, sizeof(uint64_t), cmp_u64);
+    return ne;
+}
+
+/* Without commutation, a raw ER's Paulis sit right after their gate, i.e.
+ * at slot g + 1 (before the next gate in circuit order); several on one
+ * qubit at one slot are impossible because each gate has one channel. */
+static int no_commute_one(const prep_t *P, int nraw, const uint32_t *chan,
+                          const uint8_t *outc, uint64_t *keys)
+{
+    const oc_circuit *c = P->c;
+    int ne = 0;
+    for (int i = 0; i < nraw; ++i) {
+        uint32_t g = P->chan_gate[chan[i]];
+        int o = outc[i];
+        if (is_two_qubit(c->kind[g])) {
+            if (o >> 2) keys[ne++] = EVKEY(g + 1, c->q0[g], o >> 2);
+            if (o & 3) keys[ne++] = EVKEY(g + 1, c->q1[g], o & 3);
+        } else {
+            keys[ne++] = EVKEY(g + 1, c->q0[g], o);
+        }
+    }
+    qsort(keys, (size_t)ne, sizeof(uint64_t), cmp_u64);
+    return ne;
+}
+
+int oc_commute(const oc_circuit *c, uint32_t nraw, const uint32_t *chan, const uint8_t *outc,
+               int commute, uint32_t *slot, uint32_t *qubit, uint8_t *pauli, uint32_t *n_out)
+{
+    prep_t P;
+    if (prep_init(&P, c)) return -1;
+    uint64_t *keys = malloc(sizeof(uint64_t) * ((size_t)c->n * (c->G + 2) + 2 * nraw + 1));
+    int ne;
+    if (commute) {
+        stacks_t S;
+        stacks_alloc(&S, c);
+        ne = commute_one(&P, &S, (int)nraw, chan, outc, keys);
+        stacks_free(&S);
+    } else {
+        ne = no_commute_one(&P, (int)nraw, chan, outc, keys);
+    }
+    for (int i = 0; i < ne; ++i) {
+        slot[i] = EV_SLOT(keys[i]); qubit[i] = EV_QUBIT(keys[i]); pauli[i] = (uint8_t)EV_PAULI(keys[i]);
+    }
+    *n_out = (uint32_t)ne;
+    free(keys);
+    prep_free(&P);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Leaf order: lexicographic over event keys, an exhausted list ranking above
+ * every event (so the noiseless leaf is last).  This is a depth-first order
+ * of the token trie, because at a given position an event token comes
+ * before the gate token of the same slot. */
+static int leaf_cmp(const uint64_t *a, uint64_t na, const uint64_t *b, uint64_t nb)
+{
+    uint64_t i = 0;
+    for (;; ++i) {
+        if (i == na && i == nb) return 0;
+        if (i == na) return 1;
+        if (i == nb) return -1;
+        if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+    }
+}
+
+typedef struct {
+    uint32_t n, G;
+    uint64_t S;
+    uint64_t n_leaves;
+    uint64_t *ev_off;
+    uint64_t *ev_key;
+    uint64_t *count, *shots, *wnum, *wden;
+    uint64_t stats[8]; /* raw unique, canonical unique, sig, insig, s_I, D, s_max, kept */
+    uint64_t n_raw;
+    uint32_t *raw_shot, *raw_chan;
+    uint8_t *raw_out;
+} oc_tree;
+
+/* sort contexts (sorting is single threaded) */
+static const uint64_t *g_off;
+static const uint64_t *g_key;
+static const uint64_t *g_raw_off;
+static const uint64_t *g_raw_code;
+
+static int cmp_raw(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    uint64_t na = g_raw_off[a + 1] - g_raw_off[a], nb = g_raw_off[b + 1] - g_raw_off[b];
+    const uint64_t *x = g_raw_code + g_raw_off[a], *y = g_raw_code + g_raw_off[b];
+    for (uint64_t i = 0; i < na && i < nb; ++i)
+        if (x[i] != y[i]) return x[i] < y[i] ? -1 : 1;
+    if (na != nb) return na < nb ? -1 : 1;
+    return (a > b) - (a < b);
+}
+
+static int cmp_leaf_idx(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    int r = leaf_cmp(g_key + g_off[a], g_off[a + 1] - g_off[a], g_key + g_off[b],
+                     g_off[b + 1] - g_off[b]);
+    if (r) return r;
+    return (a > b) - (a < b);
+}
+
+/* Uniform integer in [0, m) from stream 1 by rejection: draw with counter
+ * (t, attempt, 0, 1), half 0; accept when below 2^64 - (2^64 mod m). */
+static uint64_t bounded(uint64_t seed, uint32_t t, uint64_t m)
+{
+    uint64_t rem = (0 - m) % m;  /* 2^64 mod m */
+    for (uint32_t attempt = 0;; ++attempt) {
+        uint64_t v = draw64(seed, t, attempt, 0, 1, 0);
+        if (rem == 0 || v < (0 - rem)) return v % m;
+    }
+}
+
+void oc_tree_free(oc_tree *t)
+{
+    if (!t) return;
+    free(t->ev_off); free(t->ev_key); free(t->count); free(t->shots); free(t->wnum);
+    free(t->wden); free(t->raw_shot); free(t->raw_chan); free(t->raw_out);
+    free(t);
+}
+
+/* Build the tree of circuits to simulate: sample, tally, commute, re-tally,
+ * prune (Sec. III-A), then order the leaves depth-first. */
+oc_tree *oc_ecm(const oc_circuit *c, uint64_t S, uint64_t seed, int commute, int prune,
+                uint32_t a_num, uint32_t a_den, uint32_t beta)
+{
+    if (S == 0 || S > 0xFFFFFFFFull || a_den == 0) return NULL;
+    prep_t P;
+    if (prep_init(&P, c)) return NULL;
+    oc_tree *T = calloc(1, sizeof(oc_tree));
+    T->n = c->n; T->G = c->G; T->S = S;
+
+    /* 1. raw ERs, per shot (blocks of shots per thread, concatenated in
+     *    shot order) */
+    int nth = oracle_threads;
+    uint64_t *cnt = calloc(S + 1, sizeof(uint64_t));
+    uint64_t **buf = calloc((size_t)nth, sizeof(uint64_t *));
+    uint64_t *bufn = calloc((size_t)nth, sizeof(uint64_t));
+#pragma omp parallel num_threads(nth)
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        uint64_t lo = S * (uint64_t)tid / (uint64_t)nth, hi = S * (uint64_t)(tid + 1) / (uint64_t)nth;
+        uint64_t cap = 1024, len = 0;
+        uint64_t *b = malloc(sizeof(uint64_t) * cap);
+        uint32_t *ch = malloc(sizeof(uint32_t) * (P.C + 1));
+        uint8_t *oo = malloc(P.C + 1);
+        for (uint64_t j = lo; j < hi; ++j) {
+            int k = sample_shot(&P, seed, (uint32_t)j, ch, oo);
+            cnt[j] = (uint64_t)k;
+            if (len + (uint64_t)k > cap) {
+                while (len + (uint64_t)k > cap) cap *= 2;
+                b = realloc(b, sizeof(uint64_t) * cap);
+            }
+            for (int i = 0; i < k; ++i) b[len++] = ((uint64_t)ch[i] << 8) | oo[i];
+        }
+        buf[tid] = b; bufn[tid] = len;
+        free(ch); free(oo);
+    }
+    uint64_t *raw_off = malloc(sizeof(uint64_t) * (S + 1));
+    raw_off[0] = 0;
+    for (uint64_t j = 0; j < S; ++j) raw_off[j + 1] = raw_off[j] + cnt[j];
+    uint64_t nraw = raw_off[S];
+    uint64_t *raw_code = malloc(sizeof(uint64_t) * (nraw + 1));
+    {
+        uint64_t o = 0;
+        for (int t = 0; t < nth; ++t) {
+            memcpy(raw_code + o, buf[t], sizeof(uint64_t) * bufn[t]);
+            o += bufn[t];
+            free(buf[t]);
+        }
+    }
+    free(buf); free(bufn); free(cnt);
+    T->n_raw = nraw;
+    T->raw_shot = malloc(sizeof(uint32_t) * (nraw + 1));
+    T->raw_chan = malloc(sizeof(uint32_t) * (nraw + 1));
+    T->raw_out = malloc(nraw + 1);
+    for (uint64_t j = 0; j < S; ++j)
+        for (uint64_t i = raw_off[j]; i < raw_off[j + 1]; ++i) {
+            T->raw_shot[i] = (uint32_t)j;
+            T->raw_chan[i] = (uint32_t)(raw_code[i] >> 8);
+            T->raw_out[i] = (uint8_t)(raw_code[i] & 0xFF);
+        }
+
+    /* 2. tally raw ERs: sort shots by their ER, count runs */
+    uint64_t *ord = malloc(sizeof(uint64_t) * S);
+    for (uint64_t j = 0; j < S; ++j) ord[j] = j;
+    g_raw_off = raw_off; g_raw_code = raw_code;
+    qsort(ord, S, sizeof(uint64_t), cmp_raw);
+    uint64_t U = 0;
+    uint64_t *urep = malloc(sizeof(uint64_t) * S), *ucount = malloc(sizeof(uint64_t) * S);
+    for (uint64_t i = 0; i < S; ++i) {
+        uint64_t j = ord[i];
+        int same = 0;
+        if (U) {
+            uint64_t r = urep[U - 1];
+            uint64_t na = raw_off[j + 1] - raw_off[j], nb = raw_off[r + 1] - raw_off[r];
+            same = (na == nb) && !memcmp(raw_code + raw_off[j], raw_code + raw_off[r], na * 8);
+        }
+        if (same) ucount[U - 1]++;
+        else { urep[U] = j; ucount[U] = 1; ++U; }
+    }
+    free(ord);
+    T->stats[0] = U;
+
+    /* 3. canonical ER of every unique raw ER */
+    uint64_t *cn = calloc(U + 1, sizeof(uint64_t));
+    uint64_t **ck = calloc(U + 1, sizeof(uint64_t *));
+#pragma omp parallel num_threads(nth)
+    {
+        stacks_t St;
+        if (commute) stacks_alloc(&St, c);
+        uint64_t *keys = malloc(sizeof(uint64_t) * ((size_t)c->n * (c->G + 2) + 2 * P.C + 2));
+        uint32_t *ch = malloc(sizeof(uint32_t) * (P.C + 1));
+        uint8_t *oo = malloc(P.C + 1);
+#pragma omp for schedule(dynamic, 256)
+        for (uint64_t u = 0; u < U; ++u) {
+            uint64_t r = urep[u];
+            int k = (int)(raw_off[r + 1] - raw_off[r]);
+            for (int i = 0; i < k; ++i) {
+                ch[i] = (uint32_t)(raw_code[raw_off[r] + i] >> 8);
+                oo[i] = (uint8_t)(raw_code[raw_off[r] + i] & 0xFF);
+            }
+            int ne = commute ? commute_one(&P, &St, k, ch, oo, keys)
+                             : no_commute_one(&P, k, ch, oo, keys);
+            cn[u] = (uint64_t)ne;
+            ck[u] = malloc(sizeof(uint64_t) * (ne + 1));
+            memcpy(ck[u], keys, sizeof(uint64_t) * ne);
+        }
+        if (commute) stacks_free(&St);
+        free(keys); free(ch); free(oo);
+    }
+    free(raw_off); free(raw_code); free(urep);
+
+    /* 4. re-tally canonical ERs, in leaf order */
+    uint64_t *coff = malloc(sizeof(uint64_t) * (U + 1));
+    coff[0] = 0;
+    for (uint64_t u = 0; u < U; ++u) coff[u + 1] = coff[u] + cn[u];
+    uint64_t *ckey = malloc(sizeof(uint64_t) * (coff[U] + 1));
+    for (uint64_t u = 0; u < U; ++u) { memcpy(ckey + coff[u], ck[u], cn[u] * 8); free(ck[u]); }
+    free(ck); free(cn);
+    uint64_t *lord = malloc(sizeof(uint64_t) * (U + 1));
+    for (uint64_t u = 0; u < U; ++u) lord[u] = u;
+    g_off = coff; g_key = ckey;
+    qsort(lord, U, sizeof(uint64_t), cmp_leaf_idx);
+    uint64_t L = 0;
+    uint64_t *lrep = malloc(sizeof(uint64_t) * (U + 1)), *lcnt = malloc(sizeof(uint64_t) * (U + 1));
+    for (uint64_t i = 0; i < U; ++i) {
+        uint64_t u = lord[i];
+        if (L && leaf_cmp(ckey + coff[u], coff[u + 1] - coff[u], ckey + coff[lrep[L - 1]],
+                          coff[lrep[L - 1] + 1] - coff[lrep[L - 1]]) == 0) {
+            lcnt[L - 1] += ucount[u];
+        } else {
+            lrep[L] = u; lcnt[L] = ucount[u]; ++L;
+        }
+    }
+    free(lord); free(ucount);
+    T->stats[1] = L;
+
+    /* 5. pruning (Sec. III-A.4).  Significant iff a_den*s >= a_num*s_max.
+     *    If more than beta leaves are insignificant, beta of them are drawn
+     *    uniformly without replacement (partial Fisher-Yates on stream 1) and
+     *    given the insignificant shots s_I in proportion to their counts. */
+    uint8_t *keep = calloc(L + 1, 1);
+    uint64_t *shots = calloc(L + 1, sizeof(uint64_t)), *wnum = calloc(L + 1, sizeof(uint64_t)),
+             *wden = calloc(L + 1, sizeof(uint64_t));
+    uint64_t smax = 0;
+    for (uint64_t i = 0; i < L; ++i) if (lcnt[i] > smax) smax = lcnt[i];
+    T->stats[6] = smax;
+    uint64_t nsig = 0, nins = 0;
+    uint64_t *ins = malloc(sizeof(uint64_t) * (L + 1));
+    for (uint64_t i = 0; i < L; ++i) {
+        int sig = !prune || ((uint64_t)a_den * lcnt[i] >= (uint64_t)a_num * smax);
+        if (sig) { keep[i] = 1; shots[i] = lcnt[i]; wnum[i] = lcnt[i]; wden[i] = S; ++nsig; }
+        else ins[nins++] = i;
+    }
+    T->stats[2] = nsig; T->stats[3] = nins;
+    if (nins <= beta) {
+        for (uint64_t t = 0; t < nins; ++t) {
+            uint64_t i = ins[t];
+            keep[i] = 1; shots[i] = lcnt[i]; wnum[i] = lcnt[i]; wden[i] = S;
+        }
+        uint64_t sI = 0;
+        for (uint64_t t = 0; t < nins; ++t) sI += lcnt[ins[t]];
+        T->stats[4] = sI; T->stats[5] = sI;
+    } else {
+        uint64_t *a = malloc(sizeof(uint64_t) * nins);
+        for (uint64_t t = 0; t < nins; ++t) a[t] = t;
+        for (uint32_t t = 0; t < beta; ++t) {
+            uint64_t r = bounded(seed, t, nins - t);
+            uint64_t tmp = a[t]; a[t] = a[t + r]; a[t + r] = tmp;
+        }
+        qsort(a, beta, sizeof(uint64_t), cmp_u64);
+        uint64_t sI = 0, D = 0;
+        for (uint64_t t = 0; t < nins; ++t) sI += lcnt[ins[t]];
+        for (uint32_t t = 0; t < beta; ++t) D += lcnt[ins[a[t]]];
+        T->stats[4] = sI; T->stats[5] = D;
+        uint64_t *rem = malloc(sizeof(uint64_t) * beta);
+        uint64_t given = 0;
+        for (uint32_t t = 0; t < beta; ++t) {
+            uint64_t i = ins[a[t]];
+            uint64_t num = sI * lcnt[i];
+            keep[i] = 1; wnum[i] = num; wden[i] = D * S;
+            shots[i] = num / D; rem[t] = num % D; given += shots[i];
+        }
+        /* largest remainder; ties go to the earlier leaf */
+        uint64_t left = sI - given;
+        uint8_t *got = calloc(beta, 1);
+        for (uint64_t u = 0; u < left; ++u) {
+            int64_t best = -1;
+            for (uint32_t t = 0; t < beta; ++t)
+                if (!got[t] && (best < 0 || rem[t] > rem[best])) best = t;
+            got[best] = 1;
+            shots[ins[a[best]]] += 1;
+        }
+        free(got); free(rem); free(a);
+    }
+    free(ins);
+
+    uint64_t nk = 0, nev = 0;
+    for (uint64_t i = 0; i < L; ++i) if (keep[i]) { ++nk; nev += coff[lrep[i] + 1] - coff[lrep[i]]; }
+    T->stats[7] = nk;
+    T->n_leaves = nk;
+    T->ev_off = malloc(sizeof(uint64_t) * (nk + 1));
+    T->ev_key = malloc(sizeof(uint64_t) * (nev + 1));
+    T->count = malloc(sizeof(uint64_t) * (nk + 1));
+    T->shots = malloc(sizeof(uint64_t) * (nk + 1));
+    T->wnum = malloc(sizeof(uint64_t) * (nk + 1));
+    T->wden = malloc(sizeof(uint64_t) * (nk + 1));
+    uint64_t li = 0, eo = 0;
+    T->ev_off[0] = 0;
+    for (uint64_t i = 0; i < L; ++i) {
+        if (!keep[i]) continue;
+        uint64_t u = lrep[i], ne = coff[u + 1] - coff[u];
+        memcpy(T->ev_key + eo, ckey + coff[u], ne * 8);
+        eo += ne;
+        T->ev_off[li + 1] = eo;
+        T->count[li] = lcnt[i]; T->shots[li] = shots[i]; T->wnum[li] = wnum[i]; T->wden[li] = wden[i];
+        ++li;
+    }
+    free(keep); free(shots); free(wnum); free(wden); free(lrep); free(lcnt); free(coff); free(ckey);
+    prep_free(&P);
+    return T;
+}
+
+uint64_t oc_tree_num_leaves(const oc_tree *t) { return t->n_leaves; }
+uint64_t oc_tree_num_events(const oc_tree *t) { return t->ev_off[t->n_leaves]; }
+uint64_t oc_tree_num_raw(const oc_tree *t) { return t->n_raw; }
+void oc_tree_stats(const oc_tree *t, uint64_t out[8]) { memcpy(out, t->stats, sizeof(t->stats)); }
+
+void oc_tree_leaves(const oc_tree *t, uint64_t *ev_off, uint32_t *slot, uint32_t *qubit,
+                    uint8_t *pauli, uint64_t *count, uint64_t *shots, uint64_t *wnum, uint64_t *wden)
+{
+    memcpy(ev_off, t->ev_off, sizeof(uint64_t) * (t->n_leaves + 1));
+    uint64_t ne = t->ev_off[t->n_leaves];
+    for (uint64_t i = 0; i < ne; ++i) {
+        slot[i] = EV_SLOT(t->ev_key[i]); qubit[i] = EV_QUBIT(t->ev_key[i]);
+        pauli[i] = (uint8_t)EV_PAULI(t->ev_key[i]);
+    }
+    memcpy(count, t->count, sizeof(uint64_t) * t->n_leaves);
+    memcpy(shots, t->shots, sizeof(uint64_t) * t->n_leaves);
+    memcpy(wnum, t->wnum, sizeof(uint64_t) * t->n_leaves);
+    memcpy(wden, t->wden, sizeof(uint64_t) * t->n_leaves);
+}
+
+void oc_tree_raw(const oc_tree *t, uint32_t *shot, uint32_t *chan, uint8_t *outc)
+{
+    memcpy(shot, t->raw_shot, sizeof(uint32_t) * t->n_raw);
+    memcpy(chan, t->raw_chan, sizeof(uint32_t) * t->n_raw);
+    memcpy(outc, t->raw_out, t->n_raw);
+}
+
+/* Tree byte format (little endian):
+ *   u32 magic 0x51535554, u32 version 1, u32 n, u32 G, u64 shots, u64 leaves,
+ *   per leaf: u64 count, u64 shots, u64 wnum, u64 wden, u32 n_events,
+ *             n_events x (u32 slot, u32 qubit, u8 pauli). */
+static size_t put(uint8_t *b, size_t cap, size_t at, const void *v, size_t k)
+{
+    if (b && at + k <= cap) memcpy(b + at, v, k);
+    return at + k;
+}
+
+size_t oc_tree_serialize(const oc_tree *t, uint8_t *buf, size_t cap)
+{
+    size_t at = 0;
+    uint32_t h[4] = {0x51535554u, 1u, t->n, t->G};
+    at = put(buf, cap, at, h, 16);
+    at = put(buf, cap, at, &t->S, 8);
+    at = put(buf, cap, at, &t->n_leaves, 8);
+    for (uint64_t i = 0; i < t->n_leaves; ++i) {
+        at = put(buf, cap, at, &t->count[i], 8);
+        at = put(buf, cap, at, &t->shots[i], 8);
+        at = put(buf, cap, at, &t->wnum[i], 8);
+        at = put(buf, cap, at, &t->wden[i], 8);
+        uint32_t ne = (uint32_t)(t->ev_off[i + 1] - t->ev_off[i]);
+        at = put(buf, cap, at, &ne, 4);
+        for (uint64_t e = t->ev_off[i]; e < t->ev_off[i + 1]; ++e) {
+            uint32_t s = EV_SLOT(t->ev_key[e]), q = EV_QUBIT(t->ev_key[e]);
+            uint8_t p = (uint8_t)EV_PAULI(t->ev_key[e]);
+            at = put(buf, cap, at, &s, 4);
+            at = put(buf, cap, at, &q, 4);
+            at = put(buf, cap, at, &p, 1);
+        }
+    }
+    return at;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Statevector simulation (Sec. II, Eq. (1)), complex128.  Gate matrices:    */
+/*   U3(t,f,l) = [[cos t/2, -e^{il} sin t/2], [e^{if} sin t/2, e^{i(f+l)} cos t/2]]
+ *   RX(t) = exp(-i t X / 2), RY(t) = exp(-i t Y / 2), RZ(t) = exp(-i t Z / 2)
+ *   H, S = diag(1, i), T = diag(1, e^{i pi/4}), their daggers, X, Y, Z.
+ * Bit q of a basis index is qubit q.  CX(c, t) flips t where c is 1.        */
+typedef double complex cplx;
+
+static void gate_matrix(uint8_t kind, const double *pr, cplx m[4])
+{
+    double t = pr ? pr[0] : 0.0;
+    switch (kind) {
+    case OK_U3: {
+        double ct = cos(pr[0] / 2), st = sin(pr[0] / 2);
+        m[0] = ct; m[1] = -cexp(I * pr[2]) * st;
+        m[2] = cexp(I * pr[1]) * st; m[3] = cexp(I * (pr[1] + pr[2])) * ct;
+        break;
+    }
+    case OK_RX: m[0] = cos(t / 2); m[1] = -I * sin(t / 2); m[2] = -I * sin(t / 2); m[3] = cos(t / 2); break;
+    case OK_RY: m[0] = cos(t / 2); m[1] = -sin(t / 2); m[2] = sin(t / 2); m[3] = cos(t / 2); break;
+    case OK_RZ: m[0] = cexp(-I * t / 2); m[1] = 0; m[2] = 0; m[3] = cexp(I * t / 2); break;
+    case OK_H: m[0] = M_SQRT1_2; m[1] = M_SQRT1_2; m[2] = M_SQRT1_2; m[3] = -M_SQRT1_2; break;
+    case OK_S: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = I; break;
+    case OK_SDG: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = -I; break;
+    case OK_T: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = cexp(I * M_PI / 4); break;
+    case OK_TDG: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = cexp(-I * M_PI / 4); break;
+    case OK_X: m[0] = 0; m[1] = 1; m[2] = 1; m[3] = 0; break;
+    case OK_Y: m[0] = 0; m[1] = -I; m[2] = I; m[3] = 0; break;
+    case OK_Z: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = -1; break;
+    default: m[0] = 1; m[1] = 0; m[2] = 0; m[3] = 1; break;
+    }
+}
+
+static void apply_1q(cplx *psi, uint32_t n, uint32_t q, const cplx m[4])
+{
+    uint64_t N = 1ull << n, bit = 1ull << q;
+#pragma omp parallel for num_threads(oracle_threads) schedule(static) if (N >= (1ull << 16))
+    for (uint64_t i = 0; i < N; ++i) {
+        if (i & bit) continue;
+        cplx a0 = psi[i], a1 = psi[i | bit];
+        psi[i] = m[0] * a0 + m[1] * a1;
+        psi[i | bit] = m[2] * a0 + m[3] * a1;
+    }
+}
+
+static void apply_cx(cplx *psi, uint32_t n, uint32_t qc, uint32_t qt)
+{
+    uint64_t N = 1ull << n, bc = 1ull << qc, bt = 1ull << qt;
+#pragma omp parallel for num_threads(oracle_threads) schedule(static) if (N >= (1ull << 16))
+    for (uint64_t i = 0; i < N; ++i) {
+        if (!(i & bc) || (i & bt)) continue;
+        cplx tmp = psi[i]; psi[i] = psi[i | bt]; psi[i | bt] = tmp;
+    }
+}
+
+/* Pauli error gates; exact in floating point (swaps, negations, *i). */
+static void apply_pauli(cplx *psi, uint32_t n, uint32_t q, int p)
+{
+    uint64_t N = 1ull << n, bit = 1ull << q;
+#pragma omp parallel for num_threads(oracle_threads) schedule(static) if (N >= (1ull << 16))
+    for (uint64_t i = 0; i < N; ++i) {
+        if (i & bit) continue;
+        cplx a0 = psi[i], a1 = psi[i | bit];
+        if (p == 1) { psi[i] = a1; psi[i | bit] = a0; }
+        else if (p == 2) { psi[i] = -I * a1; psi[i | bit] = I * a0; }
+        else { psi[i | bit] = -a1; }
+    }
+}
+
+static void apply_gate(const oc_circuit *c, uint32_t g, cplx *psi, int inverse)
+{
+    if (c->kind[g] == OK_CX) { apply_cx(psi, c->n, c->q0[g], c->q1[g]); return; }
+    cplx m[4];
+    gate_matrix(c->kind[g], c->params + 3 * (size_t)g, m);
+    if (inverse) {
+        cplx d[4] = {conj(m[0]), conj(m[2]), conj(m[1]), conj(m[3])};
+        apply_1q(psi, c->n, c->q0[g], d);
+    } else {
+        apply_1q(psi, c->n, c->q0[g], m);
+    }
+}
+
+static void reset_state(cplx *psi, uint32_t n)
+{
+    uint64_t N = 1ull << n;
+    for (uint64_t i = 0; i < N; ++i) psi[i] = 0;
+    psi[0] = 1;
+}
+
+/* Token list of a leaf: for s = 0..G, its events at slot s (qubit order),
+ * then gate s.  Token t >= 0 is gate t; t < 0 is event (-t - 1). */
+static uint64_t leaf_tokens(const oc_circuit *c, const uint64_t *keys, uint64_t ne, int64_t *tok)
+{
+    uint64_t k = 0, e = 0;
+    for (uint32_t s = 0; s <= c->G; ++s) {
+        while (e < ne && EV_SLOT(keys[e]) == s) { tok[k++] = -(int64_t)e - 1; ++e; }
+        if (s < c->G) tok[k++] = (int64_t)s;
+    }
+    return k;
+}
+
+typedef struct { uint64_t fwd_gates, inv_gates, fwd_paulis, inv_paulis, resets, leaves, draws,
+                          ret_gates, ret_paulis; } counters_t;
+
+static void apply_token(const oc_circuit *c, const uint64_t *keys, int64_t t, cplx *psi,
+                        int inverse, counters_t *ct)
+{
+    if (t >= 0) {
+        apply_gate(c, (uint32_t)t, psi, inverse);
+        if (inverse) ct->inv_gates++; else ct->fwd_gates++;
+    } else {
+        uint64_t k = keys[-t - 1];
+        apply_pauli(psi, c->n, EV_QUBIT(k), EV_PAULI(k));
+        if (inverse) ct->inv_paulis++; else ct->fwd_paulis++;
+    }
+}
+
+/* Depth (in tokens) of the deepest node shared by two leaves: with j the
+ * first differing event index and b the smaller slot of the two events there
+ * (an exhausted list has none), the shared prefix is gates [0, b) plus the
+ * first j events: b + j tokens. */
+static uint64_t shared_depth(const oc_circuit *c, const uint64_t *a, uint64_t na, const uint64_t *b,
+                             uint64_t nb)
+{
+    uint64_t j = 0;
+    while (j < na && j < nb && a[j] == b[j]) ++j;
+    uint64_t sa = j < na ? EV_SLOT(a[j]) : (uint64_t)c->G + 1;
+    uint64_t sb = j < nb ? EV_SLOT(b[j]) : (uint64_t)c->G + 1;
+    uint64_t bslot = sa < sb ? sa : sb;
+    if (bslot > c->G) bslot = c->G;
+    return bslot + j;
+}
+
+int oc_trajectory(const oc_circuit *c, uint32_t ne, const uint32_t *slot, const uint32_t *qubit,
+                  const uint8_t *pauli, uint64_t max_tokens, double *state_out)
+{
+    if (validate(c)) return -1;
+    uint64_t *keys = malloc(sizeof(uint64_t) * (ne + 1));
+    for (uint32_t i = 0; i < ne; ++i) keys[i] = EVKEY(slot[i], qubit[i], pauli[i]);
+    for (uint32_t i = 1; i < ne; ++i) if (keys[i] <= keys[i - 1]) { free(keys); return -1; }
+    int64_t *tok = malloc(sizeof(int64_t) * (c->G + ne + 1));
+    uint64_t nt = leaf_tokens(c, keys, ne, tok);
+    if (max_tokens && max_tokens < nt) nt = max_tokens;
+    cplx *psi = (cplx *)state_out;
+    reset_state(psi, c->n);
+    counters_t ct = {0};
+    for (uint64_t i = 0; i < nt; ++i) apply_token(c, keys, tok[i], psi, 0, &ct);
+    free(tok); free(keys);
+    return 0;
+}
+
+/* Compute to depth d, keep that state, continue to the leaf, then undo back
+ * to depth d with inverse gates in reverse order; report max |difference|. */
+int oc_roundtrip(const oc_circuit *c, uint32_t ne, const uint32_t *slot, const uint32_t *qubit,
+                 const uint8_t *pauli, uint64_t depth, double *maxdiff)
+{
+    if (validate(c)) return -1;
+    uint64_t N = 1ull << c->n;
+    uint64_t *keys = malloc(sizeof(uint64_t) * (ne + 1));
+    for (uint32_t i = 0; i < ne; ++i) keys[i] = EVKEY(slot[i], qubit[i], pauli[i]);
+    int64_t *tok = malloc(sizeof(int64_t) * (c->G + ne + 1));
+    uint64_t nt = leaf_tokens(c, keys, ne, tok);
+    if (depth > nt) depth = nt;
+    cplx *psi = malloc(sizeof(cplx) * N), *saved = malloc(sizeof(cplx) * N);
+    reset_state(psi, c->n);
+    counters_t ct = {0};
+    for (uint64_t i = 0; i < depth; ++i) apply_token(c, keys, tok[i], psi, 0, &ct);
+    memcpy(saved, psi, sizeof(cplx) * N);
+    for (uint64_t i = depth; i < nt; ++i) apply_token(c, keys, tok[i], psi, 0, &ct);
+    for (uint64_t i = nt; i > depth; --i) apply_token(c, keys, tok[i - 1], psi, 1, &ct);
+    double m = 0;
+    for (uint64_t i = 0; i < N; ++i) { double d = cabs(psi[i] - saved[i]); if (d > m) m = d; }
+    *maxdiff = m;
+    free(psi); free(saved); free(tok); free(keys);
+    return 0;
+}
+
+/* Index drawn for uniform target x in [0, norm): the smallest i whose
+ * left-to-right prefix sum cdf[i] exceeds x (binary search over the
+ * monotone prefix array); if rounding leaves none, the last index with
+ * non-zero probability. */
+static uint64_t draw_index(const double *cdf, uint64_t N, double x)
+{
+    uint64_t lo = 0, hi = N;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (cdf[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    if (lo < N) return lo;
+    uint64_t i = N - 1;
+    while (i > 0 && cdf[i] == cdf[i - 1]) --i;
+    return i;
+}
+
+/* Traversal policies: 0 = plain DFTT (undo the previous leaf to the shared
+ * node with inverse gates, then go down; Sec. III-B), 1 = naive (every leaf
+ * from |0...0>), 2 = hybrid (undo only when that costs strictly fewer tokens
+ * than recomputing the leaf from the root).
+ * Leaf l draws shots[l] samples: draw d uses stream 2, counter
+ * (d >> 1, l, 0), half d & 1; u = (v >> 11) * 2^-53; target u * norm.
+ * counters: fwd gates, inv gates, fwd paulis, inv paulis, resets, leaves,
+ * draws, then the gates and paulis a final return to the root would undo. */
+int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, uint64_t lb,
+           uint64_t le, double *dist, uint64_t *samples, uint64_t *counters, double *norms)
+{
+    if (validate(c)) return -1;
+    if (le == 0 && lb == 0) le = t->n_leaves;
+    if (lb > le || le > t->n_leaves) return -1;
+    uint64_t N = 1ull << c->n;
+    cplx *psi = malloc(sizeof(cplx) * N);
+    double *cdf = samples ? malloc(sizeof(double) * N) : NULL;
+    size_t cap = (size_t)c->G + (size_t)c->n * ((size_t)c->G + 1) + 1;
+    int64_t *ta = malloc(sizeof(int64_t) * cap);
+    int64_t *tb = malloc(sizeof(int64_t) * cap);
+    counters_t ct = {0};
+    if (dist) for (uint64_t i = 0; i < N; ++i) dist[i] = 0.0;
+    uint64_t so = 0, na = 0, nka = 0;
+    const uint64_t *ka = NULL;
+    for (uint64_t l = lb; l < le; ++l) {
+        const uint64_t *kb = t->ev_key + t->ev_off[l];
+        uint64_t nkb = t->ev_off[l + 1] - t->ev_off[l];
+        uint64_t nb = leaf_tokens(c, kb, nkb, tb);
+        uint64_t from = 0;
+        int reset = 1;
+        if (l > lb && traversal != 1) {
+            uint64_t d = shared_depth(c, ka, nka, kb, nkb);
+            if (traversal == 0 || (na - d) + (nb - d) < nb) {
+                for (uint64_t i = na; i > d; --i) apply_token(c, ka, ta[i - 1], psi, 1, &ct);
+                from = d;
+                reset = 0;
+            }
+        }
+        if (reset) { reset_state(psi, c->n); ct.resets++; }
+        for (uint64_t i = from; i < nb; ++i) apply_token(c, kb, tb[i], psi, 0, &ct);
+        ct.leaves++;
+        double w = (double)t->wnum[l] / (double)t->wden[l];
+        double nrm = 0.0;
+        for (uint64_t i = 0; i < N; ++i) {
+            double pr = creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]);
+            nrm = nrm + pr;
+            if (dist) dist[i] = dist[i] + w * pr;
+            if (cdf) cdf[i] = nrm;
+        }
+        if (norms) norms[l - lb] = nrm;
+        if (samples) {
+            for (uint64_t d = 0; d < t->shots[l]; ++d) {
+                uint64_t v = draw64(seed, (uint32_t)(d >> 1), (uint32_t)l, 0, 2, (int)(d & 1));
+                double u = (double)(v >> 11) * 0x1p-53;
+                samples[so++] = draw_index(cdf, N, u * nrm);
+                ct.draws++;
+            }
+        }
+        int64_t *tmp = ta; ta = tb; tb = tmp;
+        na = nb; ka = kb; nka = nkb;
+    }
+    if (le > lb) { ct.ret_gates = c->G; ct.ret_paulis = nka; }
+    free(psi); free(cdf); free(ta); free(tb);
+    if (counters) memcpy(counters, &ct, sizeof(ct));
+    return 0;
+}
+
+/* Per-draw margin to the nearest CDF boundary of the drawn index, in the
+ * same units as the target (used by tests to excuse draws that rounding in
+ * a different summation order could legitimately move). */
+int oc_leaf_margins(const oc_circuit *c, const double *state, uint64_t seed, uint64_t leaf,
+                    uint64_t shots, uint64_t *idx_out, double *margin_out)
+{
+    uint64_t N = 1ull << c->n;
+    const cplx *psi = (const cplx *)state;
+    double *cdf = malloc(sizeof(double) * N);
+    double nrm = 0.0;
+    for (uint64_t i = 0; i < N; ++i) {
+        nrm = nrm + (creal(psi[i]) * creal(psi[i]) + cimag(psi[i]) * cimag(psi[i]));
+        cdf[i] = nrm;
+    }
+    for (uint64_t d = 0; d < shots; ++d) {
+        uint64_t v = draw64(seed, (uint32_t)(d >> 1), (uint32_t)leaf, 0, 2, (int)(d & 1));
+        double x = (double)(v >> 11) * 0x1p-53 * nrm;
+        uint64_t i = draw_index(cdf, N, x);
+        double lo = i ? cdf[i - 1] : 0.0;
+        double m1 = fabs(x - lo), m2 = fabs(cdf[i] - x);
+        idx_out[d] = i;
+        margin_out[d] = m1 < m2 ? m1 : m2;
+    }
+    free(cdf);
+    return 0;
+}

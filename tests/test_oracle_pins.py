@@ -1,0 +1,516 @@
+"""Pins for the CPU oracle: each test checks it against something that does
+not come from the oracle itself (published RNG vectors, the paper's worked
+numbers and closed forms, density-matrix simulation, brute-force operator
+identities, exact enumeration)."""
+
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dms
+from workloads import Circuit, bell_pair, brickwork, random_small_circuit
+from workloads.circuits import depol1, depol2
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+
+def _read_golden(golden_dir, name):
+    rows = []
+    with open(f"{golden_dir}/{name}") as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+# --------------------------------------------------------------------------
+# Random numbers and channel thresholds
+
+def test_philox_known_answer_vectors(golden_dir):
+    rows = _read_golden(golden_dir, "philox4x32_10_kat.txt")
+    assert len(rows) == 3
+    for r in rows:
+        vals = [int(x, 16) for x in r]
+        assert oracle.philox(vals[0:4], vals[4:6]) == tuple(vals[6:10])
+
+
+def test_thresholds_exact_and_identity():
+    assert oracle.thresholds([0.0, 0.0, 0.0]) == [0, 0, 0]
+    # 0.25 is exact in binary: C = 2^62 * k
+    assert oracle.thresholds([0.25, 0.25, 0.25]) == [1 << 62, 2 << 62, 3 << 62]
+    assert oracle.thresholds([0.5, 0.5]) == [1 << 63, 2**64 - 1]
+
+
+def _single_channel_counts(p, shots, seed):
+    c = Circuit(1)
+    c.add("H", (0,), (), depol1(p))
+    t = oracle.ecm(c, shots, seed, do_commute=False, prune=False)
+    counts = {0: 0, 1: 0, 2: 0, 3: 0}
+    for leaf in range(t.n_leaves):
+        ev = t.events(leaf)
+        counts[ev[0][2] if ev else 0] += int(t.count[leaf])
+    return counts
+
+
+def test_worked_sampling_example_frequencies(golden_dir):
+    row = [r for r in _read_golden(golden_dir, "closed_forms.txt") if r[0] == "depol_example"][0]
+    S = 200_000
+    counts = _single_channel_counts(0.1, S, seed=11)
+    exp = {0: 0.9, 1: 0.1 / 3, 2: 0.1 / 3, 3: 0.1 / 3}
+    assert "I=0.9" in row
+    for k, p in exp.items():
+        sigma = math.sqrt(S * p * (1 - p))
+        assert abs(counts[k] - S * p) < 5 * sigma, (k, counts[k], S * p)
+
+
+def test_zero_noise_gives_single_noiseless_leaf():
+    c = brickwork(4, 3, 0.0, 0.0, seed=1)
+    c2 = Circuit(4)
+    for k, q, p in zip(c.kinds, c.qubits, c.params):
+        c2.add(k, q, p, depol1(0.0) if len(q) == 1 else depol2(0.0))
+    t = oracle.ecm(c2, 1000, seed=5)
+    assert t.n_leaves == 1 and t.events(0) == [] and int(t.count[0]) == 1000
+    dist, _, _, _ = oracle.run(c2, t, seed=5, want_samples=False)
+    psi = dms.circuit_unitary(c)[:, 0]
+    np.testing.assert_allclose(dist, np.abs(psi) ** 2, atol=1e-13)
+
+
+def test_hamming_weight_histogram_matches_binomial():
+    # Fig. 2C set-up: ERs of length 20 at p = 1%.
+    C, p, S = 20, 0.01, 100_000
+    c = Circuit(20)
+    for q in range(C):
+        c.add("U3", (q,), (0.3, 0.2, 0.1), depol1(p))
+    t = oracle.ecm(c, S, seed=3, do_commute=False, prune=False)
+    shot, _, _ = t.raw_events()
+    w = np.bincount(np.bincount(shot, minlength=S), minlength=8)
+    for k in range(5):
+        pk = math.comb(C, k) * p ** k * (1 - p) ** (C - k)
+        sigma = math.sqrt(S * pk * (1 - pk)) + 1
+        assert abs(w[k] - S * pk) < 5 * sigma, (k, w[k], S * pk)
+    # the paper calls weight > 2 "zero"; the binomial value is ~1.0e-3
+    tail = 1 - sum(math.comb(C, k) * p ** k * (1 - p) ** (C - k) for k in range(3))
+    assert 0.9e-3 < tail < 1.1e-3
+    assert abs(w[3:].sum() - S * tail) < 5 * math.sqrt(S * tail) + 1
+
+
+def test_er_draws_are_per_shot_reproducible():
+    c = brickwork(5, 4, 0.05, 0.1, seed=2)
+    t = oracle.ecm(c, 300, seed=99, do_commute=False, prune=False)
+    shot, chan, out = t.raw_events()
+    for j in (0, 17, 299):
+        ch, o = oracle.sample_shot(c, 99, j)
+        np.testing.assert_array_equal(ch, chan[shot == j])
+        np.testing.assert_array_equal(o, out[shot == j])
+
+
+# --------------------------------------------------------------------------
+# Commutation rules (Sec. III-A.2, rules 1-6), checked by matrix products
+
+def _pauli_of(m2):
+    """Identify a 4x4 matrix as phase * (P_a on qubit 0 (x) P_b on qubit 1)."""
+    for a in range(4):
+        for b in range(4):
+            P = dms.pauli_full(2, [(0, a), (1, b)])
+            if dms.equal_up_to_phase(m2, P):
+                return a, b
+    return None
+
+
+def test_cx_conjugation_table_matches_matrix_products():
+    CX = dms.cx_full(2, 0, 1)
+    for a in range(4):
+        for b in range(4):
+            if a == 0 and b == 0:
+                continue
+            P = dms.pauli_full(2, [(0, a), (1, b)])
+            want = _pauli_of(CX @ P @ CX.conj().T)
+            assert want is not None
+            # circuit: noisy U3 on q0 and q1, noiseless CX, then blocking U3s
+            c = Circuit(2)
+            c.add("U3", (0,), (0.1, 0.2, 0.3), depol1(0.1))
+            c.add("U3", (1,), (0.4, 0.5, 0.6), depol1(0.1))
+            c.add("CX", (0, 1))
+            c.add("U3", (0,), (0.7, 0.8, 0.9))
+            c.add("U3", (1,), (1.0, 1.1, 1.2))
+            chan, outc = [], []
+            if a:
+                chan.append(0); outc.append(a)
+            if b:
+                chan.append(1); outc.append(b)
+            ev = oracle.commute(c, chan, outc)
+            got = {q: p for (_, q, p) in ev}
+            assert (got.get(0, 0), got.get(1, 0)) == want, (a, b)
+            for s, q, _ in ev:
+                assert s == 3 + q  # blocked right before the U3 on its qubit
+
+
+@pytest.mark.parametrize("rot", ["RX", "RY", "RZ"])
+def test_axis_rules_and_blocking(rot):
+    theta = 0.7
+    R = dms.gate_2x2(rot, [theta])
+    axis = {"RX": 1, "RY": 2, "RZ": 3}[rot]
+    for p in (1, 2, 3):
+        commutes = np.allclose(R @ dms.PAULIS[p] @ R.conj().T, dms.PAULIS[p])
+        assert commutes == (p == axis)
+        c = Circuit(1)
+        c.add("H", (0,), (), depol1(0.1))
+        c.add(rot, (0,), (theta,))
+        c.add("H", (0,))
+        ev = oracle.commute(c, [0], [p])
+        assert ev == [(2 if commutes else 1, 0, p)]
+
+
+def test_paulis_pass_noiseless_paulis_and_others_block():
+    for g in ("X", "Y", "Z"):
+        c = Circuit(1)
+        c.add("U3", (0,), (0.1, 0.2, 0.3), depol1(0.1))
+        c.add(g, (0,))
+        for p in (1, 2, 3):
+            assert oracle.commute(c, [0], [p]) == [(2, 0, p)]
+    for g in ("U3", "H", "S", "SDG", "T", "TDG"):
+        c = Circuit(1)
+        c.add("H", (0,), (), depol1(0.1))
+        c.add(g, (0,), (0.3, 0.2, 0.1))
+        assert oracle.commute(c, [0], [1]) == [(1, 0, 1)]
+
+
+def test_merge_rule_and_identity_vanishes():
+    c = Circuit(1)
+    c.add("U3", (0,), (0.1, 0.2, 0.3), depol1(0.1))
+    c.add("X", (0,), (), depol1(0.1))
+    c.add("Z", (0,), (), depol1(0.1))
+    assert oracle.commute(c, [0, 1], [1, 3]) == [(3, 0, 2)]  # X then Z -> Y
+    assert oracle.commute(c, [0, 1], [2, 2]) == []            # Y Y = I
+
+
+def test_fig4b_example_merges():
+    # H then CX, errors X after H versus XX after CX: same canonical ER.
+    c = bell_pair(0.1, 0.1)
+    e1 = oracle.commute(c, [0], [1])
+    e2 = oracle.commute(c, [1], [4 * 1 + 1])
+    assert e1 == e2 == [(2, 0, 1), (2, 1, 1)]
+
+
+def test_fig4c_example_does_not_merge():
+    # X through RZ(theta) would become RZ(-theta): the X must stay put.
+    theta = 0.9
+    RZ = dms.gate_2x2("RZ", [theta])
+    RZm = dms.gate_2x2("RZ", [-theta])
+    np.testing.assert_allclose(dms.PX @ RZ, RZm @ dms.PX, atol=1e-14)
+    c = Circuit(1)
+    c.add("H", (0,), (), depol1(0.1))
+    c.add("RZ", (0,), (theta,), depol1(0.1))
+    c.add("H", (0,))
+    assert oracle.commute(c, [0], [1]) == [(1, 0, 1)]
+    assert oracle.commute(c, [1], [1]) == [(2, 0, 1)]
+    assert oracle.commute(c, [0, 1], [1, 1]) == [(1, 0, 1), (2, 0, 1)]
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_commuted_er_is_the_same_operator(seed):
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(1, 5))
+    kinds = ("U3", "RX", "RY", "RZ", "H", "S", "T", "X", "Y", "Z", "CX", "CX", "CX")
+    c = random_small_circuit(n, int(rng.integers(4, 14)), seed, p1=0.4, p2=0.6, kinds=kinds)
+    for shot in range(6):
+        chan, outc = oracle.sample_shot(c, seed, shot)
+        raw = oracle.commute(c, chan, outc, do_commute=False)
+        can = oracle.commute(c, chan, outc, do_commute=True)
+        assert dms.equal_up_to_phase(dms.circuit_unitary(c, raw), dms.circuit_unitary(c, can))
+        assert len(set((s, q) for s, q, _ in can)) == len(can)
+        assert can == sorted(can)
+
+
+# --------------------------------------------------------------------------
+# Statevector and the mixture: density-matrix equality, closed forms
+
+def _small_noisy(seed, n):
+    rng = np.random.default_rng(100 + seed)
+    c = Circuit(n)
+    n1 = 0
+    n2 = 0
+    for _ in range(7):
+        if n >= 2 and rng.random() < 0.3 and n2 < 1:
+            a, b = rng.choice(n, 2, replace=False)
+            c.add("CX", (int(a), int(b)), (), depol2(0.2))
+            n2 += 1
+        else:
+            k = ["U3", "RX", "RY", "RZ", "H", "S", "T", "SDG", "TDG"][int(rng.integers(9))]
+            noisy = n1 < 4
+            c.add(k, (int(rng.integers(n)),), rng.random(3) * 6.28,
+                  depol1(0.3) if noisy else None)
+            n1 += noisy
+    return c
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_weighted_trajectories_equal_density_matrix(seed):
+    n = 2 + seed % 3
+    c = _small_noisy(seed, n)
+    rho = dms.density_matrix(c)
+    mix = np.zeros(1 << n)
+    wsum = 0.0
+    for p, ev in dms.enumerate_ers(c):
+        psi = oracle.trajectory(c, ev)
+        mix += p * np.abs(psi) ** 2
+        wsum += p
+        # the commuted ER gives the same distribution
+        if p > 0 and ev:
+            chan = []
+            outc = []
+            gch = {g: i for i, g in enumerate(g for g, x in enumerate(c.noise) if x is not None)}
+            per_gate = {}
+            for s, q, pa in ev:
+                per_gate.setdefault(s - 1, {})[q] = pa
+            for g, qp in sorted(per_gate.items()):
+                qs = c.qubits[g]
+                if len(qs) == 1:
+                    k = qp[qs[0]]
+                else:
+                    k = 4 * qp.get(qs[0], 0) + qp.get(qs[1], 0)
+                chan.append(gch[g]); outc.append(k)
+            can = oracle.commute(c, chan, outc)
+            np.testing.assert_allclose(np.abs(oracle.trajectory(c, can)) ** 2,
+                                       np.abs(psi) ** 2, atol=1e-12)
+    assert abs(wsum - 1.0) < 1e-12
+    np.testing.assert_allclose(mix, np.real(np.diag(rho)), atol=1e-12)
+
+
+def test_noiseless_trajectory_matches_kron_unitary():
+    for seed in range(5):
+        c = random_small_circuit(4, 25, seed, p1=0, p2=0)
+        psi = oracle.trajectory(c, [])
+        want = dms.circuit_unitary(c)[:, 0]
+        np.testing.assert_allclose(psi, want, atol=1e-13)
+
+
+@pytest.mark.parametrize("p", [0.0, 0.01, 0.3, 0.9])
+def test_bell_closed_form(p, golden_dir):
+    c = bell_pair(0.0, p) if p > 0 else bell_pair(0.0, 0.0)
+    mix = np.zeros(4)
+    for pr, ev in dms.enumerate_ers(c):
+        mix += pr * np.abs(oracle.trajectory(c, ev)) ** 2
+    want = np.array([(1 - 8 * p / 15) / 2, 4 * p / 15, 4 * p / 15, (1 - 8 * p / 15) / 2])
+    np.testing.assert_allclose(mix, want, atol=1e-14)
+
+
+@pytest.mark.parametrize("p", [0.05, 0.5])
+def test_h_depolarizing_is_half_half(p):
+    c = Circuit(1)
+    c.add("H", (0,), (), depol1(p))
+    mix = np.zeros(2)
+    for pr, ev in dms.enumerate_ers(c):
+        mix += pr * np.abs(oracle.trajectory(c, ev)) ** 2
+    np.testing.assert_allclose(mix, [0.5, 0.5], atol=1e-15)
+    # and through the whole pipeline with sampled ERs
+    t = oracle.ecm(c, 5000, seed=1, prune=False)
+    dist, _, _, _ = oracle.run(c, t, seed=1, want_samples=False)
+    np.testing.assert_allclose(dist, [0.5, 0.5], atol=1e-14)
+
+
+def test_norm_preserved_and_uncompute_returns():
+    c = brickwork(6, 8, 0.05, 0.05, seed=4)
+    t = oracle.ecm(c, 500, seed=4, prune=False)
+    for leaf in range(0, t.n_leaves, max(1, t.n_leaves // 7)):
+        ev = t.events(leaf)
+        psi = oracle.trajectory(c, ev)
+        assert abs(np.vdot(psi, psi).real - 1.0) < 1e-13
+        for depth in (0, 5, 40, c.n_gates // 2, c.n_gates + len(ev)):
+            assert oracle.roundtrip(c, ev, depth) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# The pipeline: lossless result equals the plain definition; modes agree
+
+def _definition_distribution(c, S, seed):
+    """(1/S) sum over shots of |U_{e_j}|0>|^2, each shot's raw ER placed
+    right after its gate (no tallying, no commutation, no tree)."""
+    t = oracle.ecm(c, S, seed, do_commute=False, prune=False)
+    shot, chan, outc = t.raw_events()
+    per = {}
+    for j in range(S):
+        m = shot == j
+        key = tuple(zip(chan[m].tolist(), outc[m].tolist()))
+        per[key] = per.get(key, 0) + 1
+    acc = np.zeros(1 << c.n)
+    for key, cnt in per.items():
+        ev = oracle.commute(c, [k[0] for k in key], [k[1] for k in key], do_commute=False)
+        acc += cnt * np.abs(oracle.trajectory(c, ev)) ** 2
+    return acc / S
+
+
+@pytest.mark.parametrize("fam", ["brick", "random"])
+def test_lossless_pipeline_equals_definition(fam):
+    if fam == "brick":
+        c = brickwork(5, 6, 0.02, 0.05, seed=8)
+    else:
+        c = random_small_circuit(5, 40, 8, p1=0.03, p2=0.05)
+    S, seed = 3000, 21
+    want = _definition_distribution(c, S, seed)
+    for commute in (False, True):
+        t = oracle.ecm(c, S, seed, do_commute=commute, prune=False)
+        assert int(t.count.sum()) == S
+        for trav in ("dftt", "naive", "hybrid"):
+            dist, _, _, _ = oracle.run(c, t, seed, traversal=trav, want_samples=False)
+            np.testing.assert_allclose(dist, want, atol=1e-12)
+
+
+def test_commutation_only_merges():
+    c = random_small_circuit(5, 60, 3, p1=0.03, p2=0.05,
+                             kinds=("RX", "RZ", "CX", "CX", "X", "H"))
+    t0 = oracle.ecm(c, 4000, 5, do_commute=False, prune=False)
+    t1 = oracle.ecm(c, 4000, 5, do_commute=True, prune=False)
+    assert t1.n_leaves < t0.n_leaves
+    assert t1.stats["raw_unique"] == t0.n_leaves
+
+
+def test_convergence_to_density_matrix():
+    c = brickwork(4, 3, 0.02, 0.06, seed=12)
+    rho = np.real(np.diag(dms.density_matrix(c)))
+    S = 40_000
+    t = oracle.ecm(c, S, seed=77, prune=False)
+    dist, _, _, _ = oracle.run(c, t, 77, want_samples=False)
+    # each probability is a mean of S bounded per-shot values: within a few sigma/sqrt(S)
+    assert np.max(np.abs(dist - rho)) < 5 * 0.5 / math.sqrt(S)
+
+
+# --------------------------------------------------------------------------
+# DFTT operation counts (Sec. III-B.1)
+
+def test_full_bary_tree_counts(golden_dir):
+    row = [r for r in _read_golden(golden_dir, "closed_forms.txt") if r[0] == "bary"][0]
+    vals = dict(x.split("=") for x in row[1:])
+    b, h = int(vals["b"]), int(vals["h"])
+    c = Circuit(1)
+    for _ in range(h):
+        c.add("U3", (0,), (0.3, 0.5, 0.7), depol1(0.75))   # I, X, Y, Z each 1/4
+    t = oracle.ecm(c, 20_000, seed=1, prune=False)
+    assert t.n_leaves == b ** h == int(vals["Nl"])
+    E = sum(b ** k for k in range(1, h + 1))
+    assert E == int(vals["E"])
+    assert h == round(math.log((b - 1) * E + b, b) - 1)
+    assert b ** h == (1 - 1 / b) * E + 1
+    _, _, ct, _ = oracle.run(c, t, 1, traversal="dftt", want_dist=False, want_samples=False)
+    fwd = ct["fwd_gates"] + ct["fwd_paulis"]
+    back = ct["inv_gates"] + ct["inv_paulis"] + ct["ret_gates"] + ct["ret_paulis"]
+    # each (gate, outcome) edge is one gate or one Pauli token per sibling
+    assert fwd == E and back == E and fwd + back == int(vals["Tdftt"])
+    assert t.n_leaves * h == int(vals["Tnaive"])
+    _, _, cn, _ = oracle.run(c, t, 1, traversal="naive", want_dist=False, want_samples=False)
+    assert cn["resets"] == t.n_leaves and cn["inv_gates"] == 0
+
+
+def _trie_nodes(c, t, lb=0, le=None):
+    le = le or t.n_leaves
+    nodes = set()
+    for leaf in range(lb, le):
+        ev = t.events(leaf)
+        toks = []
+        e = 0
+        for s in range(c.n_gates + 1):
+            while e < len(ev) and ev[e][0] == s:
+                toks.append(("e",) + ev[e]); e += 1
+            if s < c.n_gates:
+                toks.append(("g", s))
+        for d in range(1, len(toks) + 1):
+            nodes.add(tuple(toks[:d]))
+    return nodes
+
+
+def test_dftt_forward_tokens_equal_trie_size():
+    c = brickwork(5, 5, 0.03, 0.06, seed=9)
+    t = oracle.ecm(c, 2000, seed=9, prune=False)
+    nodes = _trie_nodes(c, t)
+    _, _, ct, _ = oracle.run(c, t, 9, traversal="dftt", want_dist=False, want_samples=False)
+    assert ct["fwd_gates"] + ct["fwd_paulis"] == len(nodes)
+    assert ct["inv_gates"] + ct["inv_paulis"] + ct["ret_gates"] + ct["ret_paulis"] == len(nodes)
+    _, _, cn, _ = oracle.run(c, t, 9, traversal="naive", want_dist=False, want_samples=False)
+    lengths = sum(c.n_gates + len(t.events(l)) for l in range(t.n_leaves))
+    assert cn["fwd_gates"] + cn["fwd_paulis"] == lengths
+    _, _, chy, _ = oracle.run(c, t, 9, traversal="hybrid", want_dist=False, want_samples=False)
+    tot = lambda x: x["fwd_gates"] + x["fwd_paulis"] + x["inv_gates"] + x["inv_paulis"]
+    assert tot(chy) <= min(tot(ct), tot(cn))
+
+
+# --------------------------------------------------------------------------
+# Pruning (Sec. III-A.4, Eq. (2))
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_pruning_invariants(seed):
+    c = brickwork(6, 10, 0.01, 0.03, seed=seed)
+    S = 20_000
+    tl = oracle.ecm(c, S, seed, prune=False)
+    tp = oracle.ecm(c, S, seed, prune=True, alpha=(1, 100), beta=50)
+    smax = int(tl.count.max())
+    sig = int((100 * tl.count >= smax).sum())
+    ins = tl.n_leaves - sig
+    assert tp.stats["significant"] == sig and tp.stats["insignificant"] == ins
+    assert tp.n_leaves == sig + min(50, ins)                       # Eq. (2)
+    assert sum(Fraction(int(a), int(b)) for a, b in zip(tp.wnum, tp.wden)) == 1
+    assert int(tp.shots.sum()) == S
+    ins_mask = 100 * tp.count < smax
+    w_ins = sum(Fraction(int(a), int(b)) for a, b, m in zip(tp.wnum, tp.wden, ins_mask) if m)
+    assert w_ins == Fraction(tp.stats["s_insig"], S)
+    # leaves kept are a subset of the lossless leaves, in the same order
+    lossless = [tuple(tl.events(i)) for i in range(tl.n_leaves)]
+    kept = [tuple(tp.events(i)) for i in range(tp.n_leaves)]
+    pos = [lossless.index(k) for k in kept]
+    assert pos == sorted(pos)
+    # apportioned shots are floor or ceil of the exact share
+    for a, b, s, m in zip(tp.wnum, tp.wden, tp.shots, ins_mask):
+        if m:
+            exact = Fraction(int(a), int(b)) * S
+            assert math.floor(exact) <= int(s) <= math.ceil(exact)
+
+
+def test_pruning_off_limits_are_lossless():
+    c = brickwork(6, 10, 0.01, 0.03, seed=5)
+    S = 5000
+    tl = oracle.ecm(c, S, 5, prune=False)
+    ta = oracle.ecm(c, S, 5, prune=True, alpha=(0, 100), beta=1)
+    tb = oracle.ecm(c, S, 5, prune=True, alpha=(1, 100), beta=10 ** 6)
+    assert tl.serialize() == ta.serialize() == tb.serialize()
+
+
+def test_pruned_keeps_exactly_beta_insignificant():
+    c = brickwork(4, 6, 0.02, 0.05, seed=2)
+    for s in range(20):
+        t = oracle.ecm(c, 3000, 1000 + s, prune=True, alpha=(1, 20), beta=5)
+        n_ins = sum(1 for i in range(t.n_leaves) if 20 * int(t.count[i]) < t.stats["s_max"])
+        assert n_ins == min(5, t.stats["insignificant"])
+
+
+# --------------------------------------------------------------------------
+# Shot sampling (leaf-level inverse CDF)
+
+def test_samples_follow_leaf_distribution():
+    c = brickwork(4, 4, 0.0, 0.0, seed=6)
+    t = oracle.ecm(c, 200_000, seed=6)
+    assert t.n_leaves == 1
+    dist, samples, ct, norms = oracle.run(c, t, 6)
+    assert ct["draws"] == 200_000 and len(samples) == 200_000
+    h = np.bincount(samples.astype(np.int64), minlength=16) / 200_000
+    sig = np.sqrt(dist * (1 - dist) / 200_000) + 1e-9
+    assert np.all(np.abs(h - dist) < 5 * sig)
+    assert abs(norms[0] - 1) < 1e-13
+
+
+def test_sample_indices_and_margins_consistent():
+    c = brickwork(5, 5, 0.02, 0.05, seed=7)
+    t = oracle.ecm(c, 3000, seed=7)
+    _, samples, _, _ = oracle.run(c, t, 7)
+    off = 0
+    for leaf in range(t.n_leaves):
+        k = int(t.shots[leaf])
+        psi = oracle.trajectory(c, t.events(leaf))
+        idx, mar = oracle.leaf_margins(c, psi, 7, leaf, k)
+        np.testing.assert_array_equal(idx, samples[off:off + k])
+        probs = np.abs(psi[idx.astype(np.int64)]) ** 2
+        assert np.all(probs > 0)
+        off += k
