@@ -1,0 +1,237 @@
+/*
+ * tusq.h -- C ABI of the MI355X (gfx950) noisy statevector engine.
+ *
+ * The engine implements the noisy-simulation method of TUSQ (Dangwal,
+ * Oberoi, Sailopal, Shah, Chong; arXiv 2508.04880): the problem statement of
+ * its Fig. 3 (inputs: a circuit in a 1-qubit + CNOT basis with Pauli noise
+ * channels, a shot count and the pruning knobs alpha and beta; output: the
+ * averaged output distribution, sampled as shots), the Error
+ * Characterisation Module of Sec. III-A (error realisation (ER) sampling,
+ * ER tallying, ER commutation, pruning with Eq. (2)) as host code, and the
+ * Depth First Tree Traversal of Sec. III-B as HIP kernels.
+ *
+ * Conventions shared by every call:
+ *   - Return value: TUSQ_OK (0) or a negative TUSQ_E* status.  No C++
+ *     exception crosses this boundary.  tusq_last_error() returns a
+ *     thread-local message describing the last failure on the calling
+ *     thread (valid until the next failing call on that thread).
+ *   - Ownership: every *_create / *_build / run call that hands out an
+ *     object has a matching *_destroy; passing NULL to a destroy is a no-op.
+ *     The library owns the device memory it allocates; caller buffers are
+ *     only read or written during the call, except for *_device variants,
+ *     which enqueue work on the caller's HIP stream.
+ *   - Bit order: bit q of a basis index or of a sampled bitstring is
+ *     qubit q (little endian).  n_qubits <= 34 on one device.
+ *   - Threading: circuits, trees and results may be used from any thread
+ *     but not concurrently; a context is thread safe for
+ *     tusq_submit / tusq_poll / tusq_wait / tusq_cancel.
+ */
+#ifndef TUSQ_ABI_H_
+#define TUSQ_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TUSQ_ABI_VERSION 1u
+
+/* status codes */
+#define TUSQ_OK 0
+#define TUSQ_EINVAL (-1)        /* bad argument: qubit out of range or repeated,
+                                   probabilities negative / NaN / summing above
+                                   1 + 1e-12, unknown gate kind, noise of the
+                                   wrong arity, buffer too small, ...          */
+#define TUSQ_ENOMEM (-2)        /* host allocation failed, or the job can
+                                   never fit the context's HBM budget        */
+#define TUSQ_EUNSUPPORTED (-3)  /* request outside what the engine does     */
+#define TUSQ_EDEVICE (-4)       /* a HIP call failed                          */
+#define TUSQ_EBUSY (-5)         /* job not finished (tusq_poll)               */
+#define TUSQ_ECANCELED (-6)     /* job was cancelled                          */
+
+/* gate kinds (Sec. III-A.3: circuits are in a 1-qubit + CNOT basis).
+ * Matrices (no paper fixes them; these are the usual ones):
+ *   U3(t, f, l) = [[cos t/2, -e^{il} sin t/2], [e^{if} sin t/2, e^{i(f+l)} cos t/2]]
+ *   RX/RY/RZ(t) = exp(-i t P / 2);  S = diag(1, i);  T = diag(1, e^{i pi/4});
+ *   SDG, TDG their adjoints; CX(c, t) flips t where c is 1.               */
+enum {
+    TUSQ_U3 = 0, TUSQ_RX, TUSQ_RY, TUSQ_RZ, TUSQ_H, TUSQ_S, TUSQ_SDG, TUSQ_T,
+    TUSQ_TDG, TUSQ_X, TUSQ_Y, TUSQ_Z, TUSQ_CX, TUSQ_NUM_KINDS
+};
+
+/* amplitude precision of the sweeps; reductions are always FP64 */
+enum { TUSQ_C128 = 0, TUSQ_C64 = 1 };
+
+/* traversal policy between consecutive leaves (Sec. III-B):
+ *   DFTT   undo the previous leaf back to the deepest shared node with
+ *          inverse gates, then compute the new leaf from there;
+ *   NAIVE  recompute every leaf from |0...0> ("DFTT switched off");
+ *   HYBRID undo only when that costs strictly fewer gate and Pauli
+ *          applications than recomputing from the root.                     */
+enum { TUSQ_DFTT = 0, TUSQ_NAIVE = 1, TUSQ_HYBRID = 2 };
+
+/* what a run returns */
+#define TUSQ_WANT_DIST 1u      /* FP64 averaged distribution, 2^n values */
+#define TUSQ_WANT_SAMPLES 2u   /* one u64 bitstring per shot             */
+#define TUSQ_WANT_NORMS 4u     /* FP64 norm of every leaf state          */
+
+typedef struct tusq_ctx tusq_ctx;
+typedef struct tusq_circuit tusq_circuit;
+typedef struct tusq_tree tusq_tree;
+typedef struct tusq_result tusq_result;
+
+typedef struct {
+    uint64_t shots;            /* S (1 .. 2^32 - 1)                            */
+    uint64_t seed;             /* Philox4x32-10 key for ER sampling (stream 0),
+                                  pruning selection (1) and shot sampling (2) */
+    uint32_t alpha_num;        /* significance: alpha_den * s_i >=            */
+    uint32_t alpha_den;        /*   alpha_num * s_max (Sec. III-A.4)          */
+    uint32_t beta;             /* insignificant circuits kept (Eq. (2))       */
+    uint32_t precision;        /* TUSQ_C128 | TUSQ_C64                        */
+    uint32_t traversal;        /* TUSQ_DFTT | TUSQ_NAIVE | TUSQ_HYBRID        */
+    uint32_t commute;          /* ER commutation on/off (Sec. III-A.2)         */
+    uint32_t prune;            /* pruning on/off                               */
+    double drift_bound;        /* C64 only: recompute a leaf from the root in
+                                  complex128 when |norm - 1| exceeds this     */
+    uint32_t max_passes_between_recompute; /* C64 only: also recompute after
+                                  this many sweeps since the last exact state
+                                  (0 = never)                                  */
+    uint64_t leaf_begin;       /* run leaves [leaf_begin, leaf_end) of the    */
+    uint64_t leaf_end;         /*   depth-first leaf list (0, 0 = all)        */
+    uint32_t want;             /* TUSQ_WANT_* bitmask                          */
+    uint32_t fusion_max_qubits;/* qubits per fused sweep tile (0 = auto)      */
+    uint32_t fusion_max_ops;   /* dense ops per fused sweep (0 = auto)        */
+    uint32_t fusion_low_qubits;/* low qubits every tile keeps (0 = auto)      */
+    uint32_t profile;          /* 1: time every sweep with HIP events         */
+    int32_t debug_fail_at_step;/* >= 0: fail with TUSQ_EDEVICE before that
+                                  schedule step (tests of error paths)        */
+    uint32_t host_threads;     /* host threads for the ECM (0 = all cores)    */
+} tusq_opts;
+
+typedef struct {
+    uint64_t fwd_gates, inv_gates;      /* gate applications (forward / undo)    */
+    uint64_t fwd_paulis, inv_paulis;    /* Pauli error applications              */
+    uint64_t resets, leaves, draws;
+    uint64_t ret_gates, ret_paulis;     /* a final return to the root would undo
+                                           these (the paper's 2|E| counts it)   */
+    uint64_t passes_fwd, passes_inv;    /* fused HBM sweeps                       */
+    uint64_t leaf_sweeps;               /* leaf accumulation sweeps               */
+    uint64_t recomputes, recompute_passes;
+    uint64_t sweep_bytes;               /* algorithmic bytes of all sweeps        */
+    uint64_t pass_events;               /* sweeps timed with events (profile)    */
+    double pass_seconds;                /* their summed device time               */
+    double host_ecm_seconds, host_plan_seconds, device_seconds;
+    double max_norm_drift;              /* max |norm - 1| over leaves (FP64)     */
+} tusq_counters;
+
+typedef struct {
+    uint64_t n_leaves, n_events, n_raw_events;
+    uint64_t raw_unique, canonical_unique, significant, insignificant;
+    uint64_t s_insig, d_selected, s_max;
+} tusq_tree_info;
+
+const char *tusq_last_error(void);
+uint32_t tusq_abi_version(void);
+
+/* alpha = 1/100, beta = 100 (the paper's defaults, Sec. III-A.4 and V-B),
+ * C128, plain DFTT, commutation and pruning on, drift_bound 1e-6, all
+ * leaves, want = DIST | SAMPLES, automatic fusion, host_threads 0.       */
+void tusq_opts_default(tusq_opts *opts);
+
+/* ---- circuits ----------------------------------------------------------- */
+int tusq_circuit_create(uint32_t n_qubits, tusq_circuit **out);
+/* Append a gate.  qubits: 1 entry (2 for CX: control, target); params: 3
+ * doubles (U3: theta, phi, lambda; RX/RY/RZ: angle first), may be NULL for
+ * parameterless kinds.  gate_index_out (may be NULL) receives its index.   */
+int tusq_circuit_gate(tusq_circuit *c, uint32_t kind, const uint32_t *qubits,
+                      const double *params, uint32_t *gate_index_out);
+/* Attach a Pauli channel right after gate gate_index (Sec. II, Eq. (4) form):
+ * 1-qubit gate: n_probs = 3, (pX, pY, pZ);  CX: n_probs = 15, entry k - 1 for
+ * the Pauli k = 4a + b (a on the control, b on the target, I=0 X=1 Y=2 Z=3).
+ * The identity takes the remaining probability.  One channel per gate.      */
+int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double *probs,
+                             uint32_t n_probs);
+int tusq_circuit_destroy(tusq_circuit *c);
+
+/* ---- host-only error characterisation (no GPU needed) -------------------- */
+/* Sample every channel for every shot (Philox4x32-10: shot j, channel c uses
+ * counter (c >> 1, j, 0, 0), half c & 1, against integer thresholds of the
+ * cumulative probabilities), tally identical ERs, push every error right by
+ * rules 1-6 to its canonical position (just before the first gate it cannot
+ * pass), re-tally, prune (Eq. (2)) and order the leaves depth first.       */
+int tusq_ecm_build(const tusq_circuit *c, const tusq_opts *opts, tusq_tree **out);
+int tusq_tree_get_info(const tusq_tree *t, tusq_tree_info *out);
+/* Byte image of the tree (little endian): u32 0x51535554, u32 1, u32 n,
+ * u32 G, u64 shots, u64 leaves, then per leaf u64 count, u64 shots,
+ * u64 weight numerator, u64 weight denominator, u32 n_events and n_events x
+ * (u32 slot, u32 qubit, u8 pauli).  With buf == NULL only *len_out is set. */
+int tusq_tree_serialize(const tusq_tree *t, uint8_t *buf, size_t cap, size_t *len_out);
+/* Raw (pre-commutation) events sorted by (shot, channel); cap = entries. */
+int tusq_tree_raw_events(const tusq_tree *t, uint32_t *shot, uint32_t *channel,
+                         uint8_t *outcome, uint64_t cap, uint64_t *n_out);
+int tusq_tree_destroy(tusq_tree *t);
+/* Schedule and fuse without a device; fills the host-side counters a run
+ * with these options would report (gate / Pauli applications, sweeps).     */
+int tusq_plan_counters(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *opts,
+                       tusq_counters *out);
+/* Dump the fused sweeps of a plan (for inspection): for sweep i, its tile
+ * qubits and dense ops.  Returns the number of sweeps in *n_passes; arrays
+ * may be NULL to query sizes.  qubits: 16 per sweep (unused = 0xFFFFFFFF);
+ * op: (first op, op count) per sweep; ops: (local a, local b or 0xFF, matrix
+ * offset in complex numbers) per op; mats: complex128 entries.           */
+int tusq_plan_dump(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *opts,
+                   uint64_t *n_steps, int64_t *steps, uint64_t *n_passes, uint32_t *qubits,
+                   uint64_t *op_range, uint64_t *n_ops, uint32_t *ops, uint64_t *n_mats,
+                   double *mats);
+
+/* ---- device execution ----------------------------------------------------- */
+/* A context owns device buffers, streams and the HBM accounting of one GPU.
+ * hbm_budget_bytes = 0 means the device's free memory at creation.         */
+int tusq_ctx_create(int hip_device, uint64_t hbm_budget_bytes, tusq_ctx **out);
+int tusq_ctx_destroy(tusq_ctx *ctx);
+
+/* Run one job to completion: ECM on the host, then the depth-first walk on
+ * the device on hip_stream (a hipStream_t; NULL = the context's stream).
+ * Synchronises before returning.                                           */
+int tusq_run(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *opts, void *hip_stream,
+             tusq_result **out);
+/* Same, for a tree built earlier with tusq_ecm_build (host stages untimed). */
+int tusq_run_tree(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t,
+                  const tusq_opts *opts, void *hip_stream, tusq_result **out);
+
+/* Serving: asynchronous jobs admitted by HBM need (state + recompute buffer
+ * + FP64 accumulator + sampler scratch) against the context budget.  Jobs
+ * that arrive while others run are admitted as memory and execution lanes
+ * free up and run concurrently on separate streams in bounded chunks.     */
+int tusq_submit(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *opts,
+                uint64_t *job_id);
+int tusq_poll(tusq_ctx *ctx, uint64_t job_id, int *state_out); /* 0 queued, 1 running,
+                                                                   2 done, 3 failed,
+                                                                   4 cancelled */
+int tusq_wait(tusq_ctx *ctx, uint64_t job_id, tusq_result **out);
+int tusq_cancel(tusq_ctx *ctx, uint64_t job_id);
+/* Timestamps (seconds, context clock) of a finished job: submitted, admitted,
+ * finished. */
+int tusq_job_times(tusq_ctx *ctx, uint64_t job_id, double *submitted, double *admitted,
+                   double *finished);
+
+/* Batching: many small independent jobs (n <= 16) in one persistent,
+ * graph-captured launch; work units (job, leaf range) are taken from a
+ * device queue.  outs[i] receives job i's result.                          */
+int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *opts,
+                   size_t n_jobs, tusq_result **outs);
+
+/* ---- results --------------------------------------------------------------- */
+int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len);
+int tusq_result_samples(const tusq_result *r, uint64_t *out, uint64_t len);
+int tusq_result_norms(const tusq_result *r, double *out, uint64_t len);
+int tusq_result_counters(const tusq_result *r, tusq_counters *out);
+int tusq_result_num_samples(const tusq_result *r, uint64_t *out);
+int tusq_result_destroy(tusq_result *r);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TUSQ_ABI_H_ */

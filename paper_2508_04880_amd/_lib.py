@@ -1,0 +1,333 @@
+"""ctypes binding of ``libtusq.so`` (declared in ``include/tusq.h``).
+
+Argument marshalling only: every step of the simulation runs in the native
+library (host ECM in C++, sweeps and reductions in HIP kernels).  Importing
+this module fails loudly when the library has not been built; there is no
+fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtusq.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2508_04880_amd.build` (or __graft_entry__.build())")
+
+lib = C.CDLL(LIB_PATH)
+
+TUSQ_OK = 0
+TUSQ_EINVAL, TUSQ_ENOMEM, TUSQ_EUNSUPPORTED, TUSQ_EDEVICE, TUSQ_EBUSY, TUSQ_ECANCELED = (
+    -1, -2, -3, -4, -5, -6)
+KINDS = {name: i for i, name in enumerate(
+    ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX"))}
+C128, C64 = 0, 1
+DFTT, NAIVE, HYBRID = 0, 1, 2
+WANT_DIST, WANT_SAMPLES, WANT_NORMS = 1, 2, 4
+TRAVERSALS = {"dftt": DFTT, "naive": NAIVE, "hybrid": HYBRID}
+PRECISIONS = {"c128": C128, "c64": C64}
+
+
+class tusq_opts(C.Structure):
+    _fields_ = [("shots", C.c_uint64), ("seed", C.c_uint64),
+                ("alpha_num", C.c_uint32), ("alpha_den", C.c_uint32), ("beta", C.c_uint32),
+                ("precision", C.c_uint32), ("traversal", C.c_uint32),
+                ("commute", C.c_uint32), ("prune", C.c_uint32),
+                ("drift_bound", C.c_double), ("max_passes_between_recompute", C.c_uint32),
+                ("leaf_begin", C.c_uint64), ("leaf_end", C.c_uint64),
+                ("want", C.c_uint32), ("fusion_max_qubits", C.c_uint32),
+                ("fusion_max_ops", C.c_uint32), ("fusion_low_qubits", C.c_uint32),
+                ("profile", C.c_uint32), ("debug_fail_at_step", C.c_int32),
+                ("host_threads", C.c_uint32)]
+
+
+class tusq_counters(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in (
+        "fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws",
+        "ret_gates", "ret_paulis", "passes_fwd", "passes_inv", "leaf_sweeps", "recomputes",
+        "recompute_passes", "sweep_bytes", "pass_events")] + \
+        [(k, C.c_double) for k in ("pass_seconds", "host_ecm_seconds", "host_plan_seconds",
+                                   "device_seconds", "max_norm_drift")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class tusq_tree_info(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in (
+        "n_leaves", "n_events", "n_raw_events", "raw_unique", "canonical_unique",
+        "significant", "insignificant", "s_insig", "d_selected", "s_max")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+P = C.c_void_p
+_SIGS = {
+    "tusq_last_error": (C.c_char_p, []),
+    "tusq_abi_version": (C.c_uint32, []),
+    "tusq_opts_default": (None, [P]),
+    "tusq_circuit_create": (C.c_int, [C.c_uint32, P]),
+    "tusq_circuit_gate": (C.c_int, [P, C.c_uint32, P, P, P]),
+    "tusq_circuit_pauli_noise": (C.c_int, [P, C.c_uint32, P, C.c_uint32]),
+    "tusq_circuit_destroy": (C.c_int, [P]),
+    "tusq_ecm_build": (C.c_int, [P, P, P]),
+    "tusq_tree_get_info": (C.c_int, [P, P]),
+    "tusq_tree_serialize": (C.c_int, [P, P, C.c_size_t, P]),
+    "tusq_tree_raw_events": (C.c_int, [P, P, P, P, C.c_uint64, P]),
+    "tusq_tree_destroy": (C.c_int, [P]),
+    "tusq_plan_counters": (C.c_int, [P, P, P, P]),
+    "tusq_plan_dump": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P]),
+    "tusq_ctx_create": (C.c_int, [C.c_int, C.c_uint64, P]),
+    "tusq_ctx_destroy": (C.c_int, [P]),
+    "tusq_run": (C.c_int, [P, P, P, P, P]),
+    "tusq_run_tree": (C.c_int, [P, P, P, P, P, P]),
+    "tusq_submit": (C.c_int, [P, P, P, P]),
+    "tusq_poll": (C.c_int, [P, C.c_uint64, P]),
+    "tusq_wait": (C.c_int, [P, C.c_uint64, P]),
+    "tusq_cancel": (C.c_int, [P, C.c_uint64]),
+    "tusq_job_times": (C.c_int, [P, C.c_uint64, P, P, P]),
+    "tusq_run_batch": (C.c_int, [P, P, P, C.c_size_t, P]),
+    "tusq_result_distribution": (C.c_int, [P, P, C.c_uint64]),
+    "tusq_result_samples": (C.c_int, [P, P, C.c_uint64]),
+    "tusq_result_norms": (C.c_int, [P, P, C.c_uint64]),
+    "tusq_result_counters": (C.c_int, [P, P]),
+    "tusq_result_num_samples": (C.c_int, [P, P]),
+    "tusq_result_destroy": (C.c_int, [P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class TusqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tusq error {code}: {msg}")
+        self.code = code
+
+
+def check(rc: int) -> None:
+    if rc != TUSQ_OK:
+        raise TusqError(rc, lib.tusq_last_error().decode(errors="replace"))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def tusq_opts_default(**kw) -> tusq_opts:
+    o = tusq_opts()
+    lib.tusq_opts_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
+        if k == "traversal" and isinstance(v, str):
+            v = TRAVERSALS[v]
+        if k == "alpha":
+            o.alpha_num, o.alpha_den = v
+            continue
+        setattr(o, k, v)
+    return o
+
+
+class Circuit:
+    """Native circuit handle built from a ``workloads.Circuit``."""
+
+    def __init__(self, circ):
+        self.n = circ.n
+        self.n_gates = circ.n_gates
+        h = C.c_void_p()
+        check(lib.tusq_circuit_create(C.c_uint32(circ.n), C.byref(h)))
+        self.h = h
+        q = (C.c_uint32 * 2)()
+        pr = (C.c_double * 3)()
+        for kind, qs, params, noise in zip(circ.kinds, circ.qubits, circ.params, circ.noise):
+            q[0] = qs[0]
+            q[1] = qs[1] if len(qs) > 1 else 0
+            for i in range(3):
+                pr[i] = params[i]
+            gi = C.c_uint32()
+            check(lib.tusq_circuit_gate(self.h, C.c_uint32(KINDS[kind]), q, pr, C.byref(gi)))
+            if noise is not None:
+                arr = (C.c_double * len(noise))(*noise)
+                check(lib.tusq_circuit_pauli_noise(self.h, gi, arr, C.c_uint32(len(noise))))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.tusq_circuit_destroy(self.h)
+            self.h = None
+
+
+class Tree:
+    def __init__(self, circuit: Circuit, opts: tusq_opts):
+        h = C.c_void_p()
+        check(lib.tusq_ecm_build(circuit.h, C.byref(opts), C.byref(h)))
+        self.h = h
+        self.circuit = circuit
+
+    def info(self) -> dict:
+        i = tusq_tree_info()
+        check(lib.tusq_tree_get_info(self.h, C.byref(i)))
+        return i.as_dict()
+
+    def serialize(self) -> bytes:
+        n = C.c_size_t()
+        check(lib.tusq_tree_serialize(self.h, None, 0, C.byref(n)))
+        buf = (C.c_uint8 * n.value)()
+        check(lib.tusq_tree_serialize(self.h, buf, n, C.byref(n)))
+        return bytes(buf)
+
+    def raw_events(self):
+        n = C.c_uint64()
+        check(lib.tusq_tree_raw_events(self.h, None, None, None, 0, C.byref(n)))
+        k = n.value
+        shot = np.zeros(max(k, 1), np.uint32)
+        chan = np.zeros(max(k, 1), np.uint32)
+        out = np.zeros(max(k, 1), np.uint8)
+        check(lib.tusq_tree_raw_events(self.h, _ptr(shot), _ptr(chan), _ptr(out),
+                                       C.c_uint64(max(k, 1)), C.byref(n)))
+        return shot[:k], chan[:k], out[:k]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.tusq_tree_destroy(self.h)
+            self.h = None
+
+
+def tusq_ecm_build(circuit: Circuit, opts: tusq_opts) -> Tree:
+    return Tree(circuit, opts)
+
+
+def tusq_plan_counters(circuit: Circuit, tree: Tree, opts: tusq_opts) -> dict:
+    c = tusq_counters()
+    check(lib.tusq_plan_counters(circuit.h, tree.h, C.byref(opts), C.byref(c)))
+    return c.as_dict()
+
+
+def tusq_plan_dump(circuit: Circuit, tree: Tree, opts: tusq_opts) -> dict:
+    ns, npas, nops, nmat = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+    check(lib.tusq_plan_dump(circuit.h, tree.h, C.byref(opts), C.byref(ns), None, C.byref(npas),
+                             None, None, C.byref(nops), None, C.byref(nmat), None))
+    steps = np.zeros((max(ns.value, 1), 2), np.int64)
+    qubits = np.zeros((max(npas.value, 1), 16), np.uint32)
+    oprange = np.zeros((max(npas.value, 1), 2), np.uint64)
+    ops = np.zeros((max(nops.value, 1), 3), np.uint32)
+    mats = np.zeros((max(nmat.value, 1), 2), np.float64)
+    check(lib.tusq_plan_dump(circuit.h, tree.h, C.byref(opts), C.byref(ns), _ptr(steps),
+                             C.byref(npas), _ptr(qubits), _ptr(oprange), C.byref(nops), _ptr(ops),
+                             C.byref(nmat), _ptr(mats)))
+    return {"steps": steps[: ns.value], "qubits": qubits[: npas.value],
+            "op_range": oprange[: npas.value], "ops": ops[: nops.value],
+            "mats": mats[: nmat.value, 0] + 1j * mats[: nmat.value, 1]}
+
+
+class Result:
+    def __init__(self, h, n: int):
+        self.h = h
+        self.n = n
+
+    def counters(self) -> dict:
+        c = tusq_counters()
+        check(lib.tusq_result_counters(self.h, C.byref(c)))
+        return c.as_dict()
+
+    def distribution(self) -> np.ndarray:
+        out = np.zeros(1 << self.n, np.float64)
+        check(lib.tusq_result_distribution(self.h, _ptr(out), C.c_uint64(out.size)))
+        return out
+
+    def samples(self) -> np.ndarray:
+        k = C.c_uint64()
+        check(lib.tusq_result_num_samples(self.h, C.byref(k)))
+        out = np.zeros(max(k.value, 1), np.uint64)
+        check(lib.tusq_result_samples(self.h, _ptr(out), k))
+        return out[: k.value]
+
+    def norms(self, count: int) -> np.ndarray:
+        out = np.zeros(max(count, 1), np.float64)
+        check(lib.tusq_result_norms(self.h, _ptr(out), C.c_uint64(count)))
+        return out[:count]
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.tusq_result_destroy(self.h)
+            self.h = None
+
+
+class Context:
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = C.c_void_p()
+        check(lib.tusq_ctx_create(C.c_int(device), C.c_uint64(hbm_budget), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            check(lib.tusq_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tusq_ctx_create(device: int = 0, hbm_budget: int = 0) -> Context:
+    return Context(device, hbm_budget)
+
+
+def tusq_run(ctx: Context, circuit: Circuit, opts: tusq_opts, stream: Optional[int] = None) -> Result:
+    h = C.c_void_p()
+    check(lib.tusq_run(ctx.h, circuit.h, C.byref(opts), C.c_void_p(stream or 0), C.byref(h)))
+    return Result(h, circuit.n)
+
+
+def tusq_run_tree(ctx: Context, circuit: Circuit, tree: Tree, opts: tusq_opts,
+                  stream: Optional[int] = None) -> Result:
+    h = C.c_void_p()
+    check(lib.tusq_run_tree(ctx.h, circuit.h, tree.h, C.byref(opts), C.c_void_p(stream or 0),
+                            C.byref(h)))
+    return Result(h, circuit.n)
+
+
+def tusq_submit(ctx: Context, circuit: Circuit, opts: tusq_opts) -> int:
+    j = C.c_uint64()
+    check(lib.tusq_submit(ctx.h, circuit.h, C.byref(opts), C.byref(j)))
+    return j.value
+
+
+def tusq_poll(ctx: Context, job: int) -> int:
+    s = C.c_int()
+    check(lib.tusq_poll(ctx.h, C.c_uint64(job), C.byref(s)))
+    return s.value
+
+
+def tusq_wait(ctx: Context, job: int, n: int) -> Result:
+    h = C.c_void_p()
+    check(lib.tusq_wait(ctx.h, C.c_uint64(job), C.byref(h)))
+    return Result(h, n)
+
+
+def tusq_cancel(ctx: Context, job: int) -> None:
+    check(lib.tusq_cancel(ctx.h, C.c_uint64(job)))
+
+
+def tusq_job_times(ctx: Context, job: int):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    check(lib.tusq_job_times(ctx.h, C.c_uint64(job), C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def tusq_run_batch(ctx: Context, circuits, opts: tusq_opts):
+    arr = (C.c_void_p * len(circuits))(*[c.h.value for c in circuits])
+    outs = (C.c_void_p * len(circuits))()
+    check(lib.tusq_run_batch(ctx.h, arr, C.byref(opts), C.c_size_t(len(circuits)), outs))
+    return [Result(C.c_void_p(outs[i]), circuits[i].n) for i in range(len(circuits))]

@@ -1,0 +1,435 @@
+// capi.cpp -- the extern "C" boundary: argument validation, ownership and
+// status codes; no exception crosses it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "engine.hpp"
+#include "exec.hpp"
+#include "serve.hpp"
+
+using namespace tusq;
+
+namespace {
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        f();
+        return TUSQ_OK;
+    } catch (const Error &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return TUSQ_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return TUSQ_EINVAL;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return TUSQ_EINVAL;
+    }
+}
+
+void need(bool ok, const char *msg) {
+    if (!ok) fail(TUSQ_EINVAL, msg);
+}
+
+void check_opts(const tusq_opts *o) {
+    need(o != nullptr, "opts is NULL");
+    need(o->shots >= 1 && o->shots <= 0xFFFFFFFFull, "shots must be in [1, 2^32)");
+    need(o->alpha_den > 0, "alpha_den must be positive");
+    need(o->precision == TUSQ_C128 || o->precision == TUSQ_C64, "unknown precision");
+    need(o->traversal <= TUSQ_HYBRID, "unknown traversal");
+    need(!(o->leaf_begin > o->leaf_end && o->leaf_end != 0), "leaf_begin > leaf_end");
+    need(o->drift_bound >= 0.0, "drift_bound must be >= 0");
+}
+}  // namespace
+
+extern "C" {
+
+const char *tusq_last_error(void) { return g_last_error.c_str(); }
+uint32_t tusq_abi_version(void) { return TUSQ_ABI_VERSION; }
+
+void tusq_opts_default(tusq_opts *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->shots = 1000;
+    o->seed = 1;
+    o->alpha_num = 1;
+    o->alpha_den = 100;
+    o->beta = 100;
+    o->precision = TUSQ_C128;
+    o->traversal = TUSQ_DFTT;
+    o->commute = 1;
+    o->prune = 1;
+    o->drift_bound = 1e-6;
+    o->max_passes_between_recompute = 0;
+    o->want = TUSQ_WANT_DIST | TUSQ_WANT_SAMPLES;
+    o->debug_fail_at_step = -1;
+}
+
+int tusq_circuit_create(uint32_t n, tusq_circuit **out) {
+    return guarded([&] {
+        need(out != nullptr, "out is NULL");
+        need(n >= 1 && n <= 34, "n_qubits must be in [1, 34]");
+        auto *c = new tusq_circuit;
+        c->c.n = n;
+        *out = c;
+    });
+}
+
+int tusq_circuit_gate(tusq_circuit *c, uint32_t kind, const uint32_t *qubits, const double *params,
+                      uint32_t *gate_index_out) {
+    return guarded([&] {
+        need(c && qubits, "circuit or qubits is NULL");
+        need(kind < TUSQ_NUM_KINDS, "unknown gate kind");
+        Gate g{};
+        g.kind = static_cast<uint8_t>(kind);
+        g.q[0] = qubits[0];
+        g.q[1] = is_cx(g.kind) ? qubits[1] : 0;
+        need(g.q[0] < c->c.n, "qubit out of range");
+        if (is_cx(g.kind)) need(g.q[1] < c->c.n && g.q[1] != g.q[0], "CX qubits out of range or equal");
+        for (int i = 0; i < 3; ++i) {
+            g.p[i] = params ? params[i] : 0.0;
+            need(std::isfinite(g.p[i]), "non-finite gate parameter");
+        }
+        g.chan = -1;
+        need(c->c.gates.size() < 0xFFFFFFF0u, "too many gates");
+        c->c.gates.push_back(g);
+        c->c.dirty = true;
+        if (gate_index_out) *gate_index_out = static_cast<uint32_t>(c->c.gates.size() - 1);
+    });
+}
+
+int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double *probs,
+                             uint32_t n_probs) {
+    return guarded([&] {
+        need(c && probs, "circuit or probs is NULL");
+        need(gate_index < c->c.gates.size(), "gate index out of range");
+        Gate &g = c->c.gates[gate_index];
+        need(g.chan < 0, "gate already has a channel");
+        need(n_probs == (is_cx(g.kind) ? 15u : 3u), "wrong number of probabilities for the gate");
+        double s = 0.0;
+        Channel ch{};
+        ch.m = static_cast<uint8_t>(n_probs);
+        for (uint32_t k = 0; k < n_probs; ++k) {
+            need(probs[k] >= 0.0 && std::isfinite(probs[k]), "probability negative or not finite");
+            ch.prob[k] = probs[k];
+            s += probs[k];
+        }
+        need(s <= 1.0 + 1e-12, "probabilities sum above 1");
+        g.chan = static_cast<int32_t>(c->c.chans.size());
+        c->c.chans.push_back(ch);
+        c->c.dirty = true;
+    });
+}
+
+int tusq_circuit_destroy(tusq_circuit *c) {
+    delete c;
+    return TUSQ_OK;
+}
+
+int tusq_ecm_build(const tusq_circuit *c, const tusq_opts *o, tusq_tree **out) {
+    return guarded([&] {
+        need(c && out, "circuit or out is NULL");
+        check_opts(o);
+        auto *cc = const_cast<tusq_circuit *>(c);
+        cc->c.finalize();
+        auto *t = new tusq_tree;
+        try {
+            t->t = build_tree(cc->c, *o);
+        } catch (...) {
+            delete t;
+            throw;
+        }
+        *out = t;
+    });
+}
+
+int tusq_tree_get_info(const tusq_tree *t, tusq_tree_info *out) {
+    return guarded([&] {
+        need(t && out, "tree or out is NULL");
+        *out = t->t.info;
+    });
+}
+
+int tusq_tree_serialize(const tusq_tree *t, uint8_t *buf, size_t cap, size_t *len_out) {
+    return guarded([&] {
+        need(t && len_out, "tree or len_out is NULL");
+        const auto b = serialize_tree(t->t);
+        *len_out = b.size();
+        if (buf) {
+            need(cap >= b.size(), "buffer too small");
+            std::memcpy(buf, b.data(), b.size());
+        }
+    });
+}
+
+int tusq_tree_raw_events(const tusq_tree *t, uint32_t *shot, uint32_t *channel, uint8_t *outcome,
+                         uint64_t cap, uint64_t *n_out) {
+    return guarded([&] {
+        need(t && n_out, "tree or n_out is NULL");
+        const uint64_t n = t->t.raw_shot.size();
+        *n_out = n;
+        if (shot || channel || outcome) {
+            need(cap >= n, "buffer too small");
+            if (shot) std::memcpy(shot, t->t.raw_shot.data(), n * 4);
+            if (channel) std::memcpy(channel, t->t.raw_chan.data(), n * 4);
+            if (outcome) std::memcpy(outcome, t->t.raw_out.data(), n);
+        }
+    });
+}
+
+int tusq_tree_destroy(tusq_tree *t) {
+    delete t;
+    return TUSQ_OK;
+}
+
+int tusq_plan_counters(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o,
+                       tusq_counters *out) {
+    return guarded([&] {
+        need(c && t && out, "NULL argument");
+        check_opts(o);
+        auto *cc = const_cast<tusq_circuit *>(c);
+        cc->c.finalize();
+        need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
+        const double t0 = now_seconds();
+        Plan p = build_plan(cc->c, t->t, *o, false);
+        p.counters.host_plan_seconds = now_seconds() - t0;
+        *out = p.counters;
+    });
+}
+
+int tusq_plan_dump(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o, uint64_t *n_steps,
+                   int64_t *steps, uint64_t *n_passes, uint32_t *qubits, uint64_t *op_range,
+                   uint64_t *n_ops, uint32_t *ops, uint64_t *n_mats, double *mats) {
+    return guarded([&] {
+        need(c && t && n_steps && n_passes && n_ops && n_mats, "NULL argument");
+        check_opts(o);
+        auto *cc = const_cast<tusq_circuit *>(c);
+        cc->c.finalize();
+        need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
+        Plan p = build_plan(cc->c, t->t, *o, false);
+        *n_steps = p.steps.size();
+        *n_passes = p.passes.size();
+        *n_ops = p.ops.size();
+        *n_mats = p.mats.size();
+        if (steps)
+            for (size_t i = 0; i < p.steps.size(); ++i) {
+                steps[2 * i] = p.steps[i].kind;
+                steps[2 * i + 1] = static_cast<int64_t>(p.steps[i].id);
+            }
+        if (qubits)
+            for (size_t i = 0; i < p.passes.size(); ++i)
+                for (int j = 0; j < 16; ++j) qubits[16 * i + j] = j < static_cast<int>(p.passes[i].k) ? p.passes[i].q[j] : 0xFFFFFFFFu;
+        if (op_range)
+            for (size_t i = 0; i < p.passes.size(); ++i) {
+                op_range[2 * i] = p.passes[i].op_begin;
+                op_range[2 * i + 1] = p.passes[i].op_end - p.passes[i].op_begin;
+            }
+        if (ops)
+            for (size_t i = 0; i < p.ops.size(); ++i) {
+                ops[3 * i] = p.ops[i].a;
+                ops[3 * i + 1] = p.ops[i].b;
+                ops[3 * i + 2] = p.ops[i].mat;
+            }
+        if (mats)
+            for (size_t i = 0; i < p.mats.size(); ++i) {
+                mats[2 * i] = p.mats[i].real();
+                mats[2 * i + 1] = p.mats[i].imag();
+            }
+    });
+}
+
+int tusq_ctx_create(int hip_device, uint64_t hbm_budget_bytes, tusq_ctx **out) {
+    return guarded([&] {
+        need(out != nullptr, "out is NULL");
+        auto *c = new tusq_ctx;
+        try {
+            c->c = new Ctx(hip_device, hbm_budget_bytes);
+        } catch (...) {
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+int tusq_ctx_destroy(tusq_ctx *ctx) {
+    if (!ctx) return TUSQ_OK;
+    return guarded([&] {
+        serving_shutdown(*ctx->c);
+        delete ctx->c;
+        delete ctx;
+    });
+}
+
+static void run_common(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *given,
+                       const tusq_opts *o, void *stream, tusq_result **out) {
+    need(ctx && c && out, "NULL argument");
+    check_opts(o);
+    auto *cc = const_cast<tusq_circuit *>(c);
+    cc->c.finalize();
+    const uint64_t need_b = job_device_bytes(cc->c.n, o->precision, o->shots, o->want & TUSQ_WANT_DIST);
+    if (need_b > ctx->c->budget) fail(TUSQ_ENOMEM, "job needs more device memory than the budget");
+    auto *r = new tusq_result;
+    try {
+        double t0 = now_seconds();
+        Tree local;
+        const Tree *t = given ? &given->t : nullptr;
+        double ecm_s = 0.0;
+        if (!given) {
+            local = build_tree(cc->c, *o);
+            t = &local;
+            ecm_s = now_seconds() - t0;
+        } else {
+            need(given->t.n == cc->c.n && given->t.G == cc->c.gates.size(),
+                 "tree was built for another circuit");
+        }
+        t0 = now_seconds();
+        Plan p = build_plan(cc->c, *t, *o, o->precision == TUSQ_C64);
+        const double plan_s = now_seconds() - t0;
+        execute_plan(*ctx->c, *t, p, *o, static_cast<hipStream_t>(stream), r->r);
+        r->r.counters.host_ecm_seconds = ecm_s;
+        r->r.counters.host_plan_seconds = plan_s;
+    } catch (...) {
+        delete r;
+        throw;
+    }
+    *out = r;
+}
+
+int tusq_run(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *o, void *stream,
+             tusq_result **out) {
+    return guarded([&] { run_common(ctx, c, nullptr, o, stream, out); });
+}
+
+int tusq_run_tree(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o,
+                  void *stream, tusq_result **out) {
+    return guarded([&] {
+        need(t != nullptr, "tree is NULL");
+        run_common(ctx, c, t, o, stream, out);
+    });
+}
+
+int tusq_submit(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *o, uint64_t *job_id) {
+    return guarded([&] {
+        need(ctx && c && job_id, "NULL argument");
+        check_opts(o);
+        *job_id = serving_submit(*ctx->c, c->c, *o);
+    });
+}
+
+int tusq_poll(tusq_ctx *ctx, uint64_t job_id, int *state_out) {
+    return guarded([&] {
+        need(ctx && state_out, "NULL argument");
+        *state_out = serving_poll(*ctx->c, job_id);
+    });
+}
+
+int tusq_wait(tusq_ctx *ctx, uint64_t job_id, tusq_result **out) {
+    return guarded([&] {
+        need(ctx && out, "NULL argument");
+        auto *r = new tusq_result;
+        try {
+            serving_wait(*ctx->c, job_id, r->r);
+        } catch (...) {
+            delete r;
+            throw;
+        }
+        *out = r;
+    });
+}
+
+int tusq_cancel(tusq_ctx *ctx, uint64_t job_id) {
+    return guarded([&] {
+        need(ctx != nullptr, "NULL argument");
+        serving_cancel(*ctx->c, job_id);
+    });
+}
+
+int tusq_job_times(tusq_ctx *ctx, uint64_t job_id, double *submitted, double *admitted,
+                   double *finished) {
+    return guarded([&] {
+        need(ctx && submitted && admitted && finished, "NULL argument");
+        serving_times(*ctx->c, job_id, submitted, admitted, finished);
+    });
+}
+
+int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *o,
+                   size_t n_jobs, tusq_result **outs) {
+    return guarded([&] {
+        need(ctx && circs && outs, "NULL argument");
+        check_opts(o);
+        std::vector<const Circuit *> cs(n_jobs);
+        for (size_t i = 0; i < n_jobs; ++i) {
+            need(circs[i] != nullptr, "NULL circuit in batch");
+            auto *cc = const_cast<tusq_circuit *>(circs[i]);
+            cc->c.finalize();
+            cs[i] = &cc->c;
+        }
+        std::vector<Result> rs;
+        run_batch(*ctx->c, cs, *o, rs);
+        size_t made = 0;
+        try {
+            for (; made < n_jobs; ++made) {
+                outs[made] = new tusq_result;
+                outs[made]->r = std::move(rs[made]);
+            }
+        } catch (...) {
+            for (size_t i = 0; i < made; ++i) delete outs[i];
+            throw;
+        }
+    });
+}
+
+int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len) {
+    return guarded([&] {
+        need(r && out, "NULL argument");
+        need(!r->r.dist.empty(), "result holds no distribution");
+        need(len == r->r.dist.size(), "len must be 2^n");
+        std::memcpy(out, r->r.dist.data(), len * 8);
+    });
+}
+
+int tusq_result_samples(const tusq_result *r, uint64_t *out, uint64_t len) {
+    return guarded([&] {
+        need(r && out, "NULL argument");
+        need(len == r->r.samples.size(), "len must equal the number of samples");
+        if (len) std::memcpy(out, r->r.samples.data(), len * 8);
+    });
+}
+
+int tusq_result_num_samples(const tusq_result *r, uint64_t *out) {
+    return guarded([&] {
+        need(r && out, "NULL argument");
+        *out = r->r.samples.size();
+    });
+}
+
+int tusq_result_norms(const tusq_result *r, double *out, uint64_t len) {
+    return guarded([&] {
+        need(r && out, "NULL argument");
+        need(len == r->r.norms.size(), "len must equal the number of leaves run");
+        if (len) std::memcpy(out, r->r.norms.data(), len * 8);
+    });
+}
+
+int tusq_result_counters(const tusq_result *r, tusq_counters *out) {
+    return guarded([&] {
+        need(r && out, "NULL argument");
+        *out = r->r.counters;
+    });
+}
+
+int tusq_result_destroy(tusq_result *r) {
+    delete r;
+    return TUSQ_OK;
+}
+
+}  // extern "C"

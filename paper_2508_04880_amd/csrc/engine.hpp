@@ -1,0 +1,144 @@
+// engine.hpp -- internal data structures of the noisy statevector engine.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "tusq.h"
+
+namespace tusq {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// Status handling: internal code throws Error; the C ABI converts it.
+struct Error {
+    int code;
+    std::string msg;
+};
+[[noreturn]] void fail(int code, const std::string &msg);
+
+// ---------------------------------------------------------------------------
+// Circuit
+struct Gate {
+    uint8_t kind;
+    uint32_t q[2];
+    double p[3];
+    int32_t chan;  // channel index or -1
+};
+
+struct Channel {
+    uint32_t gate;
+    uint8_t m;           // 3 (1-qubit) or 15 (CX)
+    uint64_t thr[15];    // integer cumulative thresholds
+    double prob[15];
+};
+
+struct Circuit {
+    uint32_t n = 0;
+    std::vector<Gate> gates;
+    std::vector<Channel> chans;  // rebuilt in gate order by finalize()
+    bool dirty = true;
+    void finalize();
+};
+
+bool is_cx(uint8_t kind);
+void gate_matrix(const Gate &g, cd m[4]);  // 2x2 of a 1-qubit gate
+
+// ---------------------------------------------------------------------------
+// Error events and the tree of circuits to simulate
+struct Ev {
+    uint32_t slot;   // applied just before gate `slot` (slot == G: after the last gate)
+    uint32_t qubit;
+    uint8_t pauli;   // 1 X, 2 Y, 3 Z
+};
+inline bool ev_less(const Ev &a, const Ev &b) {
+    if (a.slot != b.slot) return a.slot < b.slot;
+    if (a.qubit != b.qubit) return a.qubit < b.qubit;
+    return a.pauli < b.pauli;
+}
+inline bool ev_eq(const Ev &a, const Ev &b) {
+    return a.slot == b.slot && a.qubit == b.qubit && a.pauli == b.pauli;
+}
+
+struct Tree {
+    uint32_t n = 0, G = 0;
+    uint64_t S = 0;
+    std::vector<uint64_t> off;   // leaf l's events: ev[off[l] .. off[l+1])
+    std::vector<Ev> ev;
+    std::vector<uint64_t> count, shots, wnum, wden;
+    tusq_tree_info info{};
+    std::vector<uint32_t> raw_shot, raw_chan;
+    std::vector<uint8_t> raw_out;
+
+    uint64_t leaves() const { return count.size(); }
+    uint64_t nev(uint64_t l) const { return off[l + 1] - off[l]; }
+    const Ev *evs(uint64_t l) const { return ev.data() + off[l]; }
+};
+
+Tree build_tree(const Circuit &c, const tusq_opts &o);
+std::vector<uint8_t> serialize_tree(const Tree &t);
+
+// ---------------------------------------------------------------------------
+// Plan: the depth-first schedule with its fused sweeps.
+//
+// A sweep ("pass") touches every amplitude once: the state is cut into tiles
+// of 2^k amplitudes whose local index bits are the pass's qubits; each tile
+// is staged in LDS, the pass's dense 1- and 2-qubit ops are applied there,
+// and the tile is written back.
+constexpr int KMAX = 16;  // most qubits a tile may span
+
+struct Op {
+    uint8_t a;      // local index of the (first) qubit
+    uint8_t b;      // local index of the second qubit, or 0xFF for a 1-qubit op
+    uint32_t mat;   // offset (complex numbers) into the matrix pool
+};
+
+struct Pass {
+    uint32_t k = 0;
+    uint32_t q[KMAX];
+    uint32_t op_begin = 0, op_end = 0;
+    uint32_t n_gates = 0, n_paulis = 0;  // tokens fused into it
+};
+
+enum StepKind : int64_t { ST_RESET = 0, ST_FWD = 1, ST_INV = 2, ST_LEAF = 3 };
+struct Step {
+    StepKind kind;
+    uint64_t id;  // pass index (FWD/INV) or leaf index (LEAF)
+};
+
+struct FusionParams {
+    uint32_t max_qubits;  // tile qubits
+    uint32_t max_ops;     // dense ops per sweep
+    uint32_t low_qubits;  // lowest qubits every tile contains (coalescing)
+};
+
+struct Plan {
+    uint32_t n = 0;
+    std::vector<Pass> passes;
+    std::vector<Op> ops;
+    std::vector<cd> mats;
+    std::vector<Step> steps;
+    // per leaf in the range: the passes forming its path from the root, used
+    // to recompute a leaf exactly (c64 drift control)
+    std::vector<uint64_t> path_off;
+    std::vector<uint32_t> path;
+    tusq_counters counters{};
+};
+
+FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o);
+Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths);
+
+double now_seconds();
+unsigned host_threads(const tusq_opts &o);
+
+}  // namespace tusq
+
+struct tusq_circuit {
+    tusq::Circuit c;
+};
+struct tusq_tree {
+    tusq::Tree t;
+};

@@ -1,0 +1,64 @@
+// exec.hpp -- device context and plan execution.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace tusq {
+
+void hip_check(hipError_t e, const char *what);
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    void alloc(size_t b);
+    void release();
+};
+
+struct Result {
+    uint32_t n = 0;
+    std::vector<double> dist;
+    std::vector<uint64_t> samples;
+    std::vector<double> norms;
+    tusq_counters counters{};
+};
+
+struct Serving;  // request loop state (serve.cpp)
+
+struct Ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::vector<hipEvent_t> pool;
+    Serving *serving = nullptr;
+
+    Ctx(int dev, uint64_t budget);
+    ~Ctx();
+    hipEvent_t event();
+    void recycle(std::vector<hipEvent_t> &evs);
+};
+
+// Device bytes a job needs (state, recompute buffer, accumulator, sampler
+// scratch, samples, plan) -- used for admission.
+uint64_t job_device_bytes(uint32_t n, uint32_t precision, uint64_t shots, bool want_dist);
+
+void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
+                  Result &res);
+
+}  // namespace tusq
+
+struct tusq_ctx {
+    tusq::Ctx *c;
+};
+struct tusq_result {
+    tusq::Result r;
+};

@@ -1,0 +1,373 @@
+// host_plan.cpp -- the depth-first traversal schedule (TUSQ Sec. III-B) and
+// the fusion of its gate/error tokens into HBM sweeps.
+//
+// A leaf's path from |0...0> is its token list: for slot s = 0..G, the
+// leaf's errors at slot s (qubit order), then gate s.  Consecutive leaves in
+// depth-first order share a prefix; the plan undoes the previous leaf back
+// to the deepest shared node with inverse sweeps and goes down to the next
+// leaf (plain DFTT), or restarts from |0...0> (naive), or takes the cheaper
+// of the two (hybrid).  Every point where some later transition stops its
+// undo is a cut: tokens between cuts form a segment, and a segment is fused
+// into sweeps that are undone as a unit (their inverses, in reverse order).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace tusq {
+
+namespace {
+
+struct Tok {
+    bool is_gate;
+    uint32_t idx;  // gate index, or event index within the leaf
+};
+
+// Token at position p of a leaf, given the leaf's events.  Position p counts
+// gates and events interleaved by slot.
+void leaf_tokens(uint32_t G, const Ev *ev, uint64_t ne, std::vector<Tok> &out) {
+    out.clear();
+    uint64_t e = 0;
+    for (uint32_t s = 0; s <= G; ++s) {
+        while (e < ne && ev[e].slot == s) out.push_back(Tok{false, static_cast<uint32_t>(e++)});
+        if (s < G) out.push_back(Tok{true, s});
+    }
+}
+
+// Shared depth of two leaves: first differing event j, branch slot b (the
+// smaller slot of the two events there); the common prefix is gates [0, b)
+// and events [0, j): b + j tokens.
+uint64_t shared_depth(uint32_t G, const Ev *a, uint64_t na, const Ev *b, uint64_t nb) {
+    uint64_t j = 0;
+    while (j < na && j < nb && ev_eq(a[j], b[j])) ++j;
+    const uint64_t sa = j < na ? a[j].slot : uint64_t(G) + 1;
+    const uint64_t sb = j < nb ? b[j].slot : uint64_t(G) + 1;
+    return std::min<uint64_t>(std::min(sa, sb), G) + j;
+}
+
+using M2 = std::array<cd, 4>;
+using M4 = std::array<cd, 16>;
+
+M4 kron(const M2 &a, const M2 &b) {
+    M4 r;
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k)
+                for (int l = 0; l < 2; ++l) r[(2 * i + k) * 4 + (2 * j + l)] = a[2 * i + j] * b[2 * k + l];
+    return r;
+}
+M4 mul4(const M4 &a, const M4 &b) {
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cd s = 0.0;
+            for (int k = 0; k < 4; ++k) s += a[4 * i + k] * b[4 * k + j];
+            r[4 * i + j] = s;
+        }
+    return r;
+}
+M2 mul2(const M2 &a, const M2 &b) {
+    return M2{a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3], a[2] * b[0] + a[3] * b[2],
+              a[2] * b[1] + a[3] * b[3]};
+}
+const M2 I2m{1.0, 0.0, 0.0, 1.0};
+M4 cx_matrix() {  // basis index 2 * control + target
+    M4 r{};
+    r[0 * 4 + 0] = 1.0;
+    r[1 * 4 + 1] = 1.0;
+    r[2 * 4 + 3] = 1.0;
+    r[3 * 4 + 2] = 1.0;
+    return r;
+}
+M4 swap_halves(const M4 &m) {  // same operator written for the qubit pair in the other order
+    static const int p[4] = {0, 2, 1, 3};
+    M4 r;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) r[4 * p[i] + p[j]] = m[4 * i + j];
+    return r;
+}
+M2 pauli_matrix(uint8_t p) {
+    const cd i(0.0, 1.0);
+    if (p == 1) return M2{0.0, 1.0, 1.0, 0.0};
+    if (p == 2) return M2{0.0, -i, i, 0.0};
+    return M2{1.0, 0.0, 0.0, -1.0};
+}
+
+struct BuildOp {
+    uint32_t qa, qb;  // global qubits; qb = NONE for 1-qubit ops
+    bool live;
+    M2 m2;
+    M4 m4;
+};
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+
+struct Fuser {
+    const Circuit &c;
+    const FusionParams fp;
+    Plan &plan;
+
+    struct Item {
+        uint32_t qa, qb;  // qubits
+        bool two;
+        bool is_gate;
+        M2 m2;            // 1-qubit matrix (gate or Pauli)
+    };
+
+    // Fuse one segment; appends passes to the plan, returns their range.
+    std::pair<uint32_t, uint32_t> fuse(const std::vector<Item> &items) {
+        const uint32_t first = static_cast<uint32_t>(plan.passes.size());
+        const uint32_t n = c.n;
+        std::vector<uint32_t> rest(items.size());
+        for (uint32_t i = 0; i < items.size(); ++i) rest[i] = i;
+        const bool whole = n <= fp.max_qubits;
+        std::vector<int> last(n, -1);
+        std::vector<uint8_t> inq(n, 0), blocked(n, 0);
+        while (!rest.empty()) {
+            std::vector<BuildOp> ops;
+            std::fill(last.begin(), last.end(), -1);
+            std::fill(inq.begin(), inq.end(), 0);
+            std::fill(blocked.begin(), blocked.end(), 0);
+            uint32_t nq = 0;
+            auto addq = [&](uint32_t q) { if (!inq[q]) { inq[q] = 1; ++nq; } };
+            if (whole) {
+                for (uint32_t q = 0; q < n; ++q) addq(q);
+            } else {
+                for (uint32_t q = 0; q < std::min(fp.low_qubits, n); ++q) addq(q);
+            }
+            uint32_t live = 0, gates = 0, paulis = 0;
+            std::vector<uint32_t> keep;
+            bool full = false;
+            for (uint32_t idx : rest) {
+                const Item &it = items[idx];
+                const bool blk = blocked[it.qa] || (it.two && blocked[it.qb]);
+                bool take = false;
+                if (!blk && !full) {
+                    uint32_t need = nq + (inq[it.qa] ? 0 : 1) + (it.two && !inq[it.qb] ? 1 : 0);
+                    if (need <= (whole ? n : fp.max_qubits)) take = true;
+                }
+                if (!take) {
+                    blocked[it.qa] = 1;
+                    if (it.two) blocked[it.qb] = 1;
+                    keep.push_back(idx);
+                    continue;
+                }
+                addq(it.qa);
+                if (it.two) addq(it.qb);
+                if (it.is_gate) ++gates; else ++paulis;
+                if (!it.two) {
+                    const int l = last[it.qa];
+                    if (l >= 0) {
+                        BuildOp &o = ops[l];
+                        if (o.qb == NONE) o.m2 = mul2(it.m2, o.m2);
+                        else if (o.qa == it.qa) o.m4 = mul4(kron(it.m2, I2m), o.m4);
+                        else o.m4 = mul4(kron(I2m, it.m2), o.m4);
+                    } else {
+                        ops.push_back(BuildOp{it.qa, NONE, true, it.m2, {}});
+                        last[it.qa] = static_cast<int>(ops.size()) - 1;
+                        ++live;
+                    }
+                } else {
+                    const int la = last[it.qa], lb = last[it.qb];
+                    const M4 g = cx_matrix();
+                    if (la >= 0 && la == lb) {
+                        BuildOp &o = ops[la];
+                        o.m4 = mul4(o.qa == it.qa ? g : swap_halves(g), o.m4);
+                    } else {
+                        M2 a = I2m, b = I2m;
+                        if (la >= 0 && ops[la].qb == NONE) { a = ops[la].m2; ops[la].live = false; --live; }
+                        if (lb >= 0 && ops[lb].qb == NONE) { b = ops[lb].m2; ops[lb].live = false; --live; }
+                        ops.push_back(BuildOp{it.qa, it.qb, true, {}, mul4(g, kron(a, b))});
+                        last[it.qa] = last[it.qb] = static_cast<int>(ops.size()) - 1;
+                        ++live;
+                    }
+                }
+                if (!whole && live >= fp.max_ops) full = true;
+            }
+            rest.swap(keep);
+            // fill the tile up with the lowest unused qubits: every sweep
+            // then has tiles of the same size and a longer contiguous run
+            for (uint32_t q = 0; q < n && nq < (whole ? n : fp.max_qubits); ++q) addq(q);
+            // local qubit order: ascending global index
+            Pass p;
+            p.k = 0;
+            int loc[64];
+            for (uint32_t q = 0; q < n; ++q)
+                if (inq[q]) { loc[q] = static_cast<int>(p.k); p.q[p.k++] = q; }
+            p.op_begin = static_cast<uint32_t>(plan.ops.size());
+            for (const BuildOp &o : ops) {
+                if (!o.live) continue;
+                Op op;
+                op.a = static_cast<uint8_t>(loc[o.qa]);
+                op.b = o.qb == NONE ? 0xFF : static_cast<uint8_t>(loc[o.qb]);
+                op.mat = static_cast<uint32_t>(plan.mats.size());
+                if (o.qb == NONE) plan.mats.insert(plan.mats.end(), o.m2.begin(), o.m2.end());
+                else plan.mats.insert(plan.mats.end(), o.m4.begin(), o.m4.end());
+                plan.ops.push_back(op);
+            }
+            p.op_end = static_cast<uint32_t>(plan.ops.size());
+            p.n_gates = gates;
+            p.n_paulis = paulis;
+            plan.passes.push_back(p);
+        }
+        return {first, static_cast<uint32_t>(plan.passes.size())};
+    }
+};
+
+}  // namespace
+
+FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o) {
+    FusionParams fp;
+    // tiles of 2^11 complex128 (32 KiB) or 2^12 complex64 (32 KiB) in LDS
+    fp.max_qubits = o.fusion_max_qubits ? o.fusion_max_qubits : (precision == TUSQ_C64 ? 12 : 11);
+    fp.max_ops = o.fusion_max_ops ? o.fusion_max_ops : 12;
+    fp.low_qubits = o.fusion_low_qubits ? o.fusion_low_qubits : 5;
+    if (fp.max_qubits > KMAX) fp.max_qubits = KMAX;
+    if (fp.low_qubits > fp.max_qubits - 2) fp.low_qubits = fp.max_qubits - 2;
+    (void)n;
+    return fp;
+}
+
+Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths) {
+    Plan plan;
+    plan.n = c.n;
+    const uint32_t G = t.G;
+    uint64_t lb = o.leaf_begin, le = o.leaf_end;
+    if (lb == 0 && le == 0) le = t.leaves();
+    if (lb > le || le > t.leaves()) fail(TUSQ_EINVAL, "leaf range out of bounds");
+    const FusionParams fp = fusion_defaults(c.n, o.precision, o);
+    if (fp.max_qubits < 2 || fp.max_ops < 1) fail(TUSQ_EINVAL, "bad fusion parameters");
+
+    // Pass 1: transitions and cut points.
+    struct Comp {
+        uint64_t leaf;
+        bool reset;
+        uint64_t from, len;
+        std::vector<uint64_t> cuts;
+    };
+    std::vector<Comp> comps;
+    struct Range {
+        size_t comp;
+        uint64_t start, end;
+    };
+    std::vector<Range> stack;
+    for (uint64_t l = lb; l < le; ++l) {
+        Comp cp{l, true, 0, G + t.nev(l), {}};
+        if (l > lb && o.traversal != TUSQ_NAIVE) {
+            const uint64_t p = l - 1;
+            const uint64_t d = shared_depth(G, t.evs(p), t.nev(p), t.evs(l), t.nev(l));
+            const uint64_t lp = G + t.nev(p);
+            if (o.traversal == TUSQ_DFTT || (lp - d) + (cp.len - d) < cp.len) {
+                cp.reset = false;
+                cp.from = d;
+            }
+        }
+        if (cp.reset) {
+            stack.clear();
+        } else {
+            while (!stack.empty() && stack.back().start >= cp.from) stack.pop_back();
+            if (!stack.empty() && stack.back().end > cp.from) {
+                comps[stack.back().comp].cuts.push_back(cp.from);
+                stack.back().end = cp.from;
+            }
+        }
+        comps.push_back(cp);
+        stack.push_back(Range{comps.size() - 1, cp.from, cp.len});
+    }
+
+    // Pass 2: segments, fused sweeps and the step list.
+    Fuser fu{c, fp, plan};
+    struct Seg {
+        uint32_t p0, p1;
+        uint64_t start;
+        uint64_t gates, paulis;
+    };
+    std::vector<Seg> applied;
+    std::vector<Tok> toks;
+    std::vector<Fuser::Item> items;
+    auto &ct = plan.counters;
+    if (keep_paths) plan.path_off.push_back(0);
+    for (const Comp &cp : comps) {
+        if (cp.reset) {
+            plan.steps.push_back(Step{ST_RESET, 0});
+            ct.resets++;
+            applied.clear();
+        } else {
+            while (!applied.empty() && applied.back().start >= cp.from) {
+                const Seg &s = applied.back();
+                for (uint32_t p = s.p1; p > s.p0; --p) plan.steps.push_back(Step{ST_INV, p - 1});
+                ct.passes_inv += s.p1 - s.p0;
+                ct.inv_gates += s.gates;
+                ct.inv_paulis += s.paulis;
+                applied.pop_back();
+            }
+        }
+        const Ev *ev = t.evs(cp.leaf);
+        leaf_tokens(G, ev, t.nev(cp.leaf), toks);
+        std::vector<uint64_t> cuts = cp.cuts;
+        std::sort(cuts.begin(), cuts.end());
+        cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+        uint64_t a = cp.from;
+        for (size_t ci = 0; ci <= cuts.size(); ++ci) {
+            const uint64_t b = ci < cuts.size() ? cuts[ci] : cp.len;
+            if (b <= a) continue;
+            items.clear();
+            uint64_t ng = 0, np = 0;
+            for (uint64_t i = a; i < b; ++i) {
+                const Tok &tk = toks[i];
+                Fuser::Item it{};
+                if (tk.is_gate) {
+                    const Gate &g = c.gates[tk.idx];
+                    it.is_gate = true;
+                    it.qa = g.q[0];
+                    if (is_cx(g.kind)) {
+                        it.two = true;
+                        it.qb = g.q[1];
+                    } else {
+                        it.two = false;
+                        it.qb = NONE;
+                        cd m[4];
+                        gate_matrix(g, m);
+                        it.m2 = M2{m[0], m[1], m[2], m[3]};
+                    }
+                    ++ng;
+                } else {
+                    const Ev &e = ev[tk.idx];
+                    it.is_gate = false;
+                    it.two = false;
+                    it.qa = e.qubit;
+                    it.qb = NONE;
+                    it.m2 = pauli_matrix(e.pauli);
+                    ++np;
+                }
+                items.push_back(it);
+            }
+            const auto pr = fu.fuse(items);
+            for (uint32_t p = pr.first; p < pr.second; ++p) plan.steps.push_back(Step{ST_FWD, p});
+            ct.passes_fwd += pr.second - pr.first;
+            ct.fwd_gates += ng;
+            ct.fwd_paulis += np;
+            applied.push_back(Seg{pr.first, pr.second, a, ng, np});
+            a = b;
+        }
+        plan.steps.push_back(Step{ST_LEAF, cp.leaf});
+        ct.leaves++;
+        ct.leaf_sweeps++;
+        ct.draws += t.shots[cp.leaf];
+        if (keep_paths) {
+            for (const Seg &s : applied)
+                for (uint32_t p = s.p0; p < s.p1; ++p) plan.path.push_back(p);
+            plan.path_off.push_back(plan.path.size());
+        }
+    }
+    if (!comps.empty()) {
+        ct.ret_gates = G;
+        ct.ret_paulis = t.nev(comps.back().leaf);
+    }
+    const uint64_t bytes_per_amp = o.precision == TUSQ_C64 ? 8 : 16;
+    ct.sweep_bytes = (ct.passes_fwd + ct.passes_inv) * 2ull * (1ull << c.n) * bytes_per_amp;
+    return plan;
+}
+
+}  // namespace tusq

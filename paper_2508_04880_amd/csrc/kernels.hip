@@ -1,0 +1,365 @@
+// kernels.hip -- gfx950 kernels of the noisy statevector engine.
+//
+//  k_sweep     one fused HBM sweep (TUSQ Eq. (1), many gates per pass): the
+//              state is cut into tiles of 2^k amplitudes whose local index
+//              bits are the sweep's qubits; a workgroup stages one tile in
+//              LDS, applies the sweep's dense 1- and 2-qubit ops (in reverse
+//              order and conjugate-transposed when undoing a sweep, Sec.
+//              III-B), and writes the tile back.  The sweep's qubit set
+//              always holds the lowest qubits, so every wavefront moves
+//              contiguous runs of amplitudes.
+//  k_leaf      acc += w |psi|^2 in FP64 and per-chunk FP64 probability sums
+//              (fixed reduction order: results are bitwise reproducible).
+//  k_scan      inclusive prefix of the chunk sums and the leaf norm (one
+//              workgroup, fixed order).
+//  k_sample    inverse-CDF shot sampling: one wavefront per draw, binary
+//              search over chunk prefixes, then a wave scan inside the chunk.
+//  k_reset, k_to_c64, k_fill   state initialisation and conversion.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+#include "rng.hpp"
+
+namespace tusq {
+
+template <typename V> struct RealOf;
+template <> struct RealOf<double2> { using T = double; };
+template <> struct RealOf<float2> { using T = float; };
+
+template <typename V>
+__device__ __forceinline__ V cfma(V acc, V a, V b) {
+    acc.x += a.x * b.x - a.y * b.y;
+    acc.y += a.x * b.y + a.y * b.x;
+    return acc;
+}
+template <typename V>
+__device__ __forceinline__ V cconj(V a) {
+    a.y = -a.y;
+    return a;
+}
+
+__device__ __forceinline__ uint32_t insert0(uint32_t p, uint32_t bit) {
+    const uint32_t lo = p & ((1u << bit) - 1u);
+    return ((p >> bit) << (bit + 1)) | lo;
+}
+
+// Global offset of local tile index l: bit j of l goes to qubit q[j].  The
+// first `low` qubits are 0 .. low-1, so those bits stay in place.
+__device__ __forceinline__ uint64_t scatter(uint32_t l, const SweepArgs &a) {
+    uint64_t off = l & ((1u << a.low) - 1u);
+    for (uint32_t j = a.low; j < a.k; ++j) off |= static_cast<uint64_t>((l >> j) & 1u) << a.q[j];
+    return off;
+}
+
+template <typename V>
+__global__ void __launch_bounds__(256) k_sweep(V *__restrict__ psi, SweepArgs a,
+                                               const DOp *__restrict__ ops,
+                                               const V *__restrict__ mats) {
+    extern __shared__ unsigned char smem_raw[];
+    V *tile = reinterpret_cast<V *>(smem_raw);
+    const uint32_t T = 1u << a.k;
+    const uint32_t tid = threadIdx.x;
+    // tile base: spread the block index over the qubits outside the tile
+    uint64_t base = blockIdx.x;
+    for (uint32_t j = 0; j < a.k; ++j) {
+        const uint32_t q = a.q[j];
+        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
+    }
+    for (uint32_t l = tid; l < T; l += blockDim.x) tile[l] = psi[base + scatter(l, a)];
+    __syncthreads();
+    for (uint32_t i = 0; i < a.nops; ++i) {
+        const DOp op = ops[a.op_begin + (a.inverse ? a.nops - 1 - i : i)];
+        const uint32_t qa = op.ab & 0xFFu, qb = (op.ab >> 8) & 0xFFu;
+        const V *m = mats + op.mat;
+        if (qb == 0xFFu) {
+            V m00 = m[0], m01 = m[1], m10 = m[2], m11 = m[3];
+            if (a.inverse) {
+                const V t01 = m01;
+                m00 = cconj(m00); m11 = cconj(m11);
+                m01 = cconj(m10); m10 = cconj(t01);
+            }
+            const uint32_t bit = 1u << qa;
+            for (uint32_t p = tid; p < (T >> 1); p += blockDim.x) {
+                const uint32_t i0 = insert0(p, qa), i1 = i0 | bit;
+                const V v0 = tile[i0], v1 = tile[i1];
+                V r0{0, 0}, r1{0, 0};
+                r0 = cfma(cfma(r0, m00, v0), m01, v1);
+                r1 = cfma(cfma(r1, m10, v0), m11, v1);
+                tile[i0] = r0;
+                tile[i1] = r1;
+            }
+        } else {
+            V mm[16];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    mm[4 * r + c] = a.inverse ? cconj(m[4 * c + r]) : m[4 * r + c];
+            const uint32_t lo = qa < qb ? qa : qb, hi = qa < qb ? qb : qa;
+            const uint32_t A = 1u << qa, B = 1u << qb;
+            for (uint32_t p = tid; p < (T >> 2); p += blockDim.x) {
+                const uint32_t i0 = insert0(insert0(p, lo), hi);
+                const uint32_t idx[4] = {i0, i0 | B, i0 | A, i0 | A | B};
+                V v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = tile[idx[r]];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    V acc{0, 0};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc = cfma(acc, mm[4 * r + c], v[c]);
+                    tile[idx[r]] = acc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (uint32_t l = tid; l < T; l += blockDim.x) psi[base + scatter(l, a)] = tile[l];
+}
+
+// ---------------------------------------------------------------------------
+// Leaf accumulation: 256 threads per chunk of C = 2^log_chunk amplitudes.
+// Thread t sums elements t, t + 256, ... in order; the block combines the
+// 256 partial sums by a fixed binary tree.
+template <typename V>
+__global__ void __launch_bounds__(256) k_leaf(const V *__restrict__ psi, uint32_t log_chunk,
+                                              double *__restrict__ acc, double w,
+                                              double *__restrict__ chunk_sum) {
+    __shared__ double red[256];
+    const uint64_t C = 1ull << log_chunk;
+    const uint64_t base = static_cast<uint64_t>(blockIdx.x) * C;
+    double s = 0.0;
+    for (uint64_t i = threadIdx.x; i < C; i += blockDim.x) {
+        const V v = psi[base + i];
+        const double re = static_cast<double>(v.x), im = static_cast<double>(v.y);
+        const double pr = re * re + im * im;
+        s += pr;
+        if (acc) acc[base + i] += w * pr;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = red[0];
+}
+
+// Inclusive prefix over nc chunk sums; thread t owns a contiguous run.
+__global__ void __launch_bounds__(1024) k_scan(const double *__restrict__ chunk_sum, uint64_t nc,
+                                               double *__restrict__ prefix,
+                                               double *__restrict__ norm_out) {
+    __shared__ double part[1024];
+    const uint64_t per = (nc + blockDim.x - 1) / blockDim.x;
+    const uint64_t lo = threadIdx.x * per;
+    const uint64_t hi = lo + per < nc ? lo + per : nc;
+    double s = 0.0;
+    for (uint64_t i = lo; i < hi; ++i) s += chunk_sum[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = 0.0;
+        for (uint32_t t = 0; t < blockDim.x; ++t) {
+            const double v = part[t];
+            part[t] = r;
+            r += v;
+        }
+        *norm_out = r;
+    }
+    __syncthreads();
+    double r = part[threadIdx.x];
+    for (uint64_t i = lo; i < hi; ++i) {
+        r += chunk_sum[i];
+        prefix[i] = r;
+    }
+}
+
+template <typename V>
+__device__ __forceinline__ double prob(const V *psi, uint64_t i) {
+    const V v = psi[i];
+    const double re = static_cast<double>(v.x), im = static_cast<double>(v.y);
+    return re * re + im * im;
+}
+
+// One wavefront per draw.  Draw d of leaf `leaf`: Philox stream 2, counter
+// (d >> 1, leaf, 0), half d & 1; u = (v >> 11) 2^-53; target x = u * norm.
+// Result: the first index whose running probability sum exceeds x.
+template <typename V>
+__global__ void __launch_bounds__(256) k_sample(const V *__restrict__ psi, uint32_t log_chunk,
+                                                const double *__restrict__ prefix, uint64_t nc,
+                                                const double *__restrict__ norm, uint64_t seed,
+                                                uint32_t leaf, uint64_t shots,
+                                                uint64_t *__restrict__ out) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t d = static_cast<uint64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (d >= shots) return;
+    const Pair64 r = philox_pair(seed, static_cast<uint32_t>(d >> 1), leaf, 0, STREAM_SHOTS);
+    const uint64_t v = (d & 1) ? r.hi : r.lo;
+    const double x = static_cast<double>(v >> 11) * 0x1p-53 * (*norm);
+    // first chunk whose inclusive prefix exceeds x
+    uint64_t lo = 0, hi = nc;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (prefix[mid] > x) hi = mid; else lo = mid + 1;
+    }
+    const uint64_t c = lo < nc ? lo : nc - 1;
+    double run = c ? prefix[c - 1] : 0.0;
+    const uint64_t C = 1ull << log_chunk;
+    const uint64_t per = C >= 64 ? C / 64 : 1;
+    const uint64_t b0 = c * C + (C >= 64 ? lane * per : lane);
+    const bool active = C >= 64 || lane < C;
+    double s = 0.0;
+    if (active)
+        for (uint64_t i = 0; i < per; ++i) s += prob(psi, b0 + i);
+    // inclusive wave scan of lane sums, fixed order
+    double incl = s;
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    const double before = run + incl - s;
+    const bool hit = active && (run + incl > x);
+    const unsigned long long mask = __ballot(hit);
+    uint64_t result;
+    if (mask) {
+        const uint32_t first = __ffsll(mask) - 1;
+        uint64_t idx = 0;
+        if (lane == first) {
+            double acc = before;
+            idx = b0 + per - 1;
+            for (uint64_t i = 0; i < per; ++i) {
+                acc += prob(psi, b0 + i);
+                if (acc > x) { idx = b0 + i; break; }
+            }
+        }
+        result = __shfl(idx, first, 64);
+    } else {
+        // rounding left no running sum above x: take the last index of the
+        // chunk with non-zero probability
+        uint64_t last = 0;
+        bool any = false;
+        if (active)
+            for (uint64_t i = 0; i < per; ++i)
+                if (prob(psi, b0 + i) > 0.0) { last = b0 + i; any = true; }
+        const unsigned long long m2 = __ballot(any);
+        const uint32_t src = m2 ? 63 - __clzll(m2) : 0;
+        result = m2 ? __shfl(last, src, 64) : c * C;
+    }
+    if (lane == 0) out[d] = result;
+}
+
+template <typename V>
+__global__ void k_reset(V *psi, uint64_t N) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < N) psi[i] = V{static_cast<typename RealOf<V>::T>(i == 0 ? 1 : 0), 0};
+}
+
+__global__ void k_to_c64(const double2 *src, float2 *dst, uint64_t N) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < N) dst[i] = float2{static_cast<float>(src[i].x), static_cast<float>(src[i].y)};
+}
+
+__global__ void k_fill(double *p, uint64_t n, double v) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side).  Every launcher checks its shapes before launching.
+#define TUSQ_CHECK_LAUNCH()                                  \
+    do {                                                     \
+        hipError_t e_ = hipGetLastError();                   \
+        if (e_ != hipSuccess) return e_;                     \
+    } while (0)
+
+static unsigned grid1(uint64_t n, unsigned b) { return static_cast<unsigned>((n + b - 1) / b); }
+
+template <typename V>
+hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, const V *mats,
+                        hipStream_t s) {
+    if (a.k > n || a.k > 16 || a.k < 1 || n - a.k > 31 || a.low > a.k) return hipErrorInvalidValue;
+    const size_t lds = sizeof(V) << a.k;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const unsigned blocks = 1u << (n - a.k);
+    hipLaunchKernelGGL(k_sweep<V>, dim3(blocks), dim3(256), lds, s, psi, a, ops, mats);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
+hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
+                       double *chunk_sum, double *prefix, double *norm_out, hipStream_t s) {
+    if (log_chunk > n) return hipErrorInvalidValue;
+    const uint64_t nc = 1ull << (n - log_chunk);
+    hipLaunchKernelGGL(k_leaf<V>, dim3(static_cast<unsigned>(nc)), dim3(256), 0, s, psi, log_chunk,
+                       acc, w, chunk_sum);
+    TUSQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, chunk_sum, nc, prefix, norm_out);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
+hipError_t launch_sample(const V *psi, uint32_t n, uint32_t log_chunk, const double *prefix,
+                         const double *norm, uint64_t seed, uint32_t leaf, uint64_t shots,
+                         uint64_t *out, hipStream_t s) {
+    if (!shots) return hipSuccess;
+    const uint64_t nc = 1ull << (n - log_chunk);
+    const uint64_t blocks = (shots + 3) / 4;
+    if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample<V>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, psi,
+                       log_chunk, prefix, nc, norm, seed, leaf, shots, out);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
+hipError_t launch_reset(V *psi, uint32_t n, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    hipLaunchKernelGGL(k_reset<V>, dim3(grid1(N, 256)), dim3(256), 0, s, psi, N);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_to_c64(const double2 *src, float2 *dst, uint32_t n, hipStream_t s) {
+    const uint64_t N = 1ull << n;
+    hipLaunchKernelGGL(k_to_c64, dim3(grid1(N, 256)), dim3(256), 0, s, src, dst, N);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t launch_fill(double *p, uint64_t count, double v, hipStream_t s) {
+    if (!count) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid1(count, 256)), dim3(256), 0, s, p, count, v);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+hipError_t sweep_kernel_setup() {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<double2>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<float2>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template hipError_t launch_sweep<double2>(double2 *, uint32_t, const SweepArgs &, const DOp *,
+                                          const double2 *, hipStream_t);
+template hipError_t launch_sweep<float2>(float2 *, uint32_t, const SweepArgs &, const DOp *,
+                                         const float2 *, hipStream_t);
+template hipError_t launch_leaf<double2>(const double2 *, uint32_t, uint32_t, double *, double,
+                                         double *, double *, double *, hipStream_t);
+template hipError_t launch_leaf<float2>(const float2 *, uint32_t, uint32_t, double *, double,
+                                        double *, double *, double *, hipStream_t);
+template hipError_t launch_sample<double2>(const double2 *, uint32_t, uint32_t, const double *,
+                                           const double *, uint64_t, uint32_t, uint64_t,
+                                           uint64_t *, hipStream_t);
+template hipError_t launch_sample<float2>(const float2 *, uint32_t, uint32_t, const double *,
+                                          const double *, uint64_t, uint32_t, uint64_t,
+                                          uint64_t *, hipStream_t);
+template hipError_t launch_reset<double2>(double2 *, uint32_t, hipStream_t);
+template hipError_t launch_reset<float2>(float2 *, uint32_t, hipStream_t);
+
+}  // namespace tusq

@@ -1,0 +1,44 @@
+// kernels.hpp -- launch interface of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tusq {
+
+// One dense op of a sweep: low byte = local qubit a, next byte = local qubit
+// b (0xFF for a 1-qubit op); mat = offset into the complex matrix pool
+// (2x2 or 4x4, row major, 4x4 basis index 2 * bit(a) + bit(b)).
+struct alignas(8) DOp {
+    uint32_t ab;
+    uint32_t mat;
+};
+
+// Arguments of one sweep launch, passed by value.
+struct SweepArgs {
+    uint32_t k;         // tile qubits
+    uint32_t low;       // q[0 .. low) == 0 .. low-1
+    uint32_t nops;
+    uint32_t op_begin;
+    uint32_t inverse;   // apply the ops' adjoints in reverse order
+    uint8_t q[16];      // tile qubits, ascending
+};
+
+template <typename V>
+hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, const V *mats,
+                        hipStream_t s);
+template <typename V>
+hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
+                       double *chunk_sum, double *prefix, double *norm_out, hipStream_t s);
+template <typename V>
+hipError_t launch_sample(const V *psi, uint32_t n, uint32_t log_chunk, const double *prefix,
+                         const double *norm, uint64_t seed, uint32_t leaf, uint64_t shots,
+                         uint64_t *out, hipStream_t s);
+template <typename V>
+hipError_t launch_reset(V *psi, uint32_t n, hipStream_t s);
+hipError_t launch_to_c64(const double2 *src, float2 *dst, uint32_t n, hipStream_t s);
+hipError_t launch_fill(double *p, uint64_t count, double v, hipStream_t s);
+hipError_t sweep_kernel_setup();
+
+}  // namespace tusq

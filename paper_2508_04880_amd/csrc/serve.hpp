@@ -1,0 +1,20 @@
+// serve.hpp -- asynchronous request loop and batched execution.
+#pragma once
+
+#include <vector>
+
+#include "exec.hpp"
+
+namespace tusq {
+
+uint64_t serving_submit(Ctx &ctx, const Circuit &c, const tusq_opts &o);
+int serving_poll(Ctx &ctx, uint64_t id);
+void serving_wait(Ctx &ctx, uint64_t id, Result &out);
+void serving_cancel(Ctx &ctx, uint64_t id);
+void serving_times(Ctx &ctx, uint64_t id, double *submitted, double *admitted, double *finished);
+void serving_shutdown(Ctx &ctx);
+
+void run_batch(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq_opts &o,
+               std::vector<Result> &out);
+
+}  // namespace tusq

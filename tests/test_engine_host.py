@@ -1,0 +1,219 @@
+"""Host-side parity of the engine (no GPU needed): the C ABI loads and
+exports what include/tusq.h declares; the engine's error characterisation
+(ER sampling, tallying, commutation, pruning, leaf order) reproduces the
+oracle's tree and raw-ER stream bit for bit; its depth-first schedule makes
+the oracle's gate/Pauli application counts; and its fused sweeps, applied
+with NumPy, give the oracle's distribution."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2508_04880_amd as tq
+from workloads import brickwork, ising, random_small_circuit, Circuit, bell_pair
+from workloads.circuits import depol1, depol2
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "tusq.h")) as f:
+        src = f.read()
+    names = set(re.findall(r"\b(tusq_[a-z0-9_]+)\s*\(", src))
+    assert len(names) >= 30
+    lib = ctypes.CDLL(tq.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert tq.lib.tusq_abi_version() == 1
+
+
+def test_product_binding_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_2508_04880_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                with open(os.path.join(dirpath, fn)) as f:
+                    text = f.read()
+                assert "import oracle" not in text and "from oracle" not in text, fn
+                assert "tusq_oracle" not in text and "liboracle" not in text, fn
+
+
+CASES = [
+    ("brick8", lambda: brickwork(8, 20, 1e-3, 1e-2, 1), 10_000),
+    ("brick6_noisy", lambda: brickwork(6, 12, 0.02, 0.05, 3), 5_000),
+    ("ising8", lambda: ising(8, 6, 5e-3, 2e-2), 8_000),
+    ("soup5", lambda: random_small_circuit(5, 60, 4, p1=0.03, p2=0.06), 6_000),
+    ("soup4_axis", lambda: random_small_circuit(
+        4, 80, 9, p1=0.05, p2=0.05, kinds=("RX", "RY", "RZ", "CX", "X", "Y", "Z", "H")), 6_000),
+    ("bell", lambda: bell_pair(0.1, 0.2), 3_000),
+]
+
+
+@pytest.mark.parametrize("name,make,S", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("commute,prune,alpha,beta", [
+    (True, True, (1, 100), 100), (True, False, (1, 100), 100), (False, True, (1, 100), 100),
+    (True, True, (1, 20), 7), (False, False, (1, 100), 100)])
+def test_tree_bit_exact_against_oracle(name, make, S, commute, prune, alpha, beta):
+    c = make()
+    seed = 1234 + S
+    ot = oracle.ecm(c, S, seed, do_commute=commute, prune=prune, alpha=alpha, beta=beta)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=seed, commute=int(commute), prune=int(prune),
+                             alpha=alpha, beta=beta, host_threads=3)
+    et = tq.Tree(ec, o)
+    assert et.serialize() == ot.serialize()
+    for a, b in zip(ot.raw_events(), et.raw_events()):
+        np.testing.assert_array_equal(a, b)
+    info = et.info()
+    for k in ("raw_unique", "canonical_unique", "significant", "insignificant", "s_max"):
+        assert info[k] == ot.stats[k], k
+
+
+def test_tree_independent_of_host_thread_count():
+    c = brickwork(10, 15, 2e-3, 2e-2, 5)
+    outs = []
+    for th in (1, 2, 7):
+        o = tq.tusq_opts_default(shots=20_000, seed=9, host_threads=th)
+        outs.append(tq.Tree(tq.Circuit(c), o).serialize())
+    assert outs[0] == outs[1] == outs[2]
+
+
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+@pytest.mark.parametrize("name,make,S", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_schedule_counts_match_oracle(trav, name, make, S):
+    c = make()
+    ot = oracle.ecm(c, S, 5, prune=False)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=5, prune=0, traversal=trav)
+    et = tq.Tree(ec, o)
+    pc = tq.tusq_plan_counters(ec, et, o)
+    _, _, oc, _ = oracle.run(c, ot, 5, traversal=trav, want_dist=False, want_samples=False)
+    for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
+              "ret_gates", "ret_paulis"):
+        assert pc[k] == oc[k], k
+    # a leaf range starts from the root
+    nl = et.info()["n_leaves"]
+    if nl > 6:
+        o2 = tq.tusq_opts_default(shots=S, seed=5, prune=0, traversal=trav, leaf_begin=2,
+                                  leaf_end=nl - 3)
+        pc2 = tq.tusq_plan_counters(ec, et, o2)
+        _, _, oc2, _ = oracle.run(c, ot, 5, traversal=trav, leaf_begin=2, leaf_end=nl - 3,
+                                  want_dist=False, want_samples=False)
+        for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves"):
+            assert pc2[k] == oc2[k], k
+
+
+# --------------------------------------------------------------------------
+# The fused sweeps, executed with NumPy on the full state
+
+def _apply_local(psi, n, qubits, op, M, inverse):
+    a, b = int(op[0]), int(op[1])
+    st = psi.reshape([2] * n)  # axis n-1-q is qubit q
+    if b == 0xFF:
+        m = M.reshape(2, 2)
+        if inverse:
+            m = m.conj().T
+        ax = n - 1 - int(qubits[a])
+        st = np.moveaxis(np.tensordot(m, st, axes=([1], [ax])), 0, ax)
+    else:
+        m = M.reshape(4, 4)
+        if inverse:
+            m = m.conj().T
+        qa, qb = int(qubits[a]), int(qubits[b])
+        axa, axb = n - 1 - qa, n - 1 - qb
+        m4 = m.reshape(2, 2, 2, 2)  # (ra, rb, ca, cb)
+        st = np.tensordot(m4, st, axes=([2, 3], [axa, axb]))
+        st = np.moveaxis(st, [0, 1], [axa, axb])
+    return st.reshape(-1)
+
+
+def _run_plan_numpy(c, dump, weights, lb):
+    n = c.n
+    psi = np.zeros(1 << n, complex)
+    acc = np.zeros(1 << n)
+    for kind, ident in dump["steps"]:
+        if kind == 0:
+            psi[:] = 0
+            psi[0] = 1
+        elif kind in (1, 2):
+            inv = kind == 2
+            q = dump["qubits"][ident]
+            b0, cnt = dump["op_range"][ident]
+            rng = range(b0, b0 + cnt)
+            for i in (reversed(rng) if inv else rng):
+                op = dump["ops"][i]
+                size = 4 if op[1] == 0xFF else 16
+                M = dump["mats"][op[2]: op[2] + size]
+                psi = _apply_local(psi, n, q, op, M, inv)
+        else:
+            acc += weights[ident] * np.abs(psi) ** 2
+    return acc
+
+
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+@pytest.mark.parametrize("kmax,low,maxops", [(3, 1, 2), (4, 2, 5), (5, 3, 12), (16, 5, 12)])
+def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops):
+    c = brickwork(7, 8, 0.02, 0.05, 11)
+    S = 3000
+    ot = oracle.ecm(c, S, 3, prune=True, alpha=(1, 50), beta=20)
+    dist, _, _, _ = oracle.run(c, ot, 3, traversal=trav, want_samples=False)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=3, alpha=(1, 50), beta=20, traversal=trav,
+                             fusion_max_qubits=kmax, fusion_low_qubits=low,
+                             fusion_max_ops=maxops)
+    et = tq.Tree(ec, o)
+    dump = tq.tusq_plan_dump(ec, et, o)
+    if kmax < c.n:
+        assert all((q[:kmax] != 0xFFFFFFFF).all() for q in dump["qubits"])
+    acc = _run_plan_numpy(c, dump, ot.weights(), 0)
+    np.testing.assert_allclose(acc, dist, atol=1e-12)
+
+
+def test_fused_plan_ising_and_soup():
+    for c in (ising(6, 4, 1e-2, 3e-2), random_small_circuit(6, 70, 2, p1=0.03, p2=0.05)):
+        ot = oracle.ecm(c, 4000, 8, prune=False)
+        dist, _, _, _ = oracle.run(c, ot, 8, want_samples=False)
+        ec = tq.Circuit(c)
+        o = tq.tusq_opts_default(shots=4000, seed=8, prune=0, fusion_max_qubits=4,
+                                 fusion_low_qubits=2, fusion_max_ops=3)
+        et = tq.Tree(ec, o)
+        acc = _run_plan_numpy(c, tq.tusq_plan_dump(ec, et, o), ot.weights(), 0)
+        np.testing.assert_allclose(acc, dist, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Validation at the boundary
+
+def test_invalid_inputs_are_rejected():
+    lib = tq.lib
+    h = ctypes.c_void_p()
+    assert lib.tusq_circuit_create(0, ctypes.byref(h)) == -1
+    assert lib.tusq_circuit_create(3, ctypes.byref(h)) == 0
+    q = (ctypes.c_uint32 * 2)(3, 0)
+    assert lib.tusq_circuit_gate(h, 0, q, None, None) == -1
+    assert b"range" in lib.tusq_last_error()
+    q = (ctypes.c_uint32 * 2)(1, 1)
+    assert lib.tusq_circuit_gate(h, 12, q, None, None) == -1      # CX with equal qubits
+    assert lib.tusq_circuit_gate(h, 99, q, None, None) == -1      # unknown kind
+    q = (ctypes.c_uint32 * 2)(0, 1)
+    gi = ctypes.c_uint32()
+    assert lib.tusq_circuit_gate(h, 12, q, None, ctypes.byref(gi)) == 0
+    p3 = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    assert lib.tusq_circuit_pauli_noise(h, gi, p3, 3) == -1       # CX needs 15
+    bad = (ctypes.c_double * 15)(*([0.1] * 15))
+    assert lib.tusq_circuit_pauli_noise(h, gi, bad, 15) == -1     # sums above 1
+    neg = (ctypes.c_double * 15)(*([-0.01] + [0.0] * 14))
+    assert lib.tusq_circuit_pauli_noise(h, gi, neg, 15) == -1
+    ok = (ctypes.c_double * 15)(*([0.01] * 15))
+    assert lib.tusq_circuit_pauli_noise(h, gi, ok, 15) == 0
+    assert lib.tusq_circuit_pauli_noise(h, gi, ok, 15) == -1      # one channel per gate
+    o = tq.tusq_opts_default(shots=0)
+    t = ctypes.c_void_p()
+    assert lib.tusq_ecm_build(h, ctypes.byref(o), ctypes.byref(t)) == -1
+    assert lib.tusq_circuit_destroy(h) == 0
+    assert lib.tusq_circuit_destroy(None) == 0
+    assert lib.tusq_result_destroy(None) == 0

@@ -1,0 +1,200 @@
+"""GPU parity: the engine's HIP path against the CPU oracle on the same
+seeded inputs, through the C ABI.  Distributions to 1e-10 (complex128),
+samples identical except draws whose oracle margin to a CDF boundary is
+below 1e-11 (a different summation order may move those), counters equal,
+complex64 error stated and bounded."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2508_04880_amd as tq
+from workloads import Circuit, brickwork, ising, random_small_circuit
+from workloads.circuits import depol1
+
+pytestmark = pytest.mark.gpu
+
+TOL_C128 = 1e-10
+# complex64: each sweep rounds every amplitude at ~6e-8 relative; after a
+# few hundred sweeps the probability error stays well below 1e-4
+TOL_C64 = 1e-4
+MARGIN = 1e-11
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tq.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _engine(ctx, c, S, seed, **kw):
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=seed, **kw)
+    t = tq.Tree(ec, o)
+    r = tq.tusq_run_tree(ctx, ec, t, o)
+    return ec, t, o, r
+
+
+def _check_samples(c, ot, seed, samples, lb=0, le=None):
+    le = le or ot.n_leaves
+    off = 0
+    excused = 0
+    for leaf in range(lb, le):
+        k = int(ot.shots[leaf])
+        if not k:
+            continue
+        psi = oracle.trajectory(c, ot.events(leaf))
+        idx, mar = oracle.leaf_margins(c, psi, seed, leaf, k)
+        got = samples[off:off + k]
+        bad = got != idx
+        if bad.any():
+            assert np.all(mar[bad] < MARGIN), (leaf, got[bad][:5], idx[bad][:5], mar[bad][:5])
+            excused += int(bad.sum())
+        off += k
+    assert off == len(samples)
+    return excused
+
+
+@pytest.mark.parametrize("prune", [True, False])
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+def test_config0_brickwork_8q(ctx, prune, trav):
+    _say(f"[gpu] config0 prune={prune} trav={trav}")
+    c = brickwork(8, 20, 1e-3, 1e-2, 1)
+    S, seed = 10_000, 2
+    ot = oracle.ecm(c, S, seed, prune=prune)
+    dist, samples, oc, onorm = oracle.run(c, ot, seed, traversal=trav)
+    ec, t, o, r = _engine(ctx, c, S, seed, prune=int(prune), traversal=trav)
+    assert t.serialize() == ot.serialize()
+    np.testing.assert_allclose(r.distribution(), dist, atol=TOL_C128, rtol=0)
+    ex = _check_samples(c, ot, seed, r.samples())
+    assert ex <= 2
+    ct = r.counters()
+    for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws"):
+        assert ct[k] == oc[k], k
+    np.testing.assert_allclose(r.norms(ot.n_leaves), onorm, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,kmax,low,maxops", [(10, 4, 2, 3), (12, 6, 3, 5), (13, 11, 5, 12),
+                                                (15, 8, 4, 4), (16, 11, 5, 12)])
+def test_tiled_sweeps_random_circuits(ctx, n, kmax, low, maxops):
+    _say(f"[gpu] tiled n={n} kmax={kmax} low={low} maxops={maxops}")
+    c = random_small_circuit(n, 6 * n, n, p1=0.01, p2=0.02)
+    S, seed = 3000, 7
+    ot = oracle.ecm(c, S, seed, alpha=(1, 30), beta=12)
+    dist, samples, _, _ = oracle.run(c, ot, seed)
+    ec, t, o, r = _engine(ctx, c, S, seed, alpha=(1, 30), beta=12, fusion_max_qubits=kmax,
+                          fusion_low_qubits=low, fusion_max_ops=maxops)
+    np.testing.assert_allclose(r.distribution(), dist, atol=TOL_C128, rtol=0)
+    _check_samples(c, ot, seed, r.samples())
+
+
+def test_ising_leaf_range(ctx):
+    _say("[gpu] ising leaf range")
+    c = ising(12, 6, 5e-3, 2e-2)
+    S, seed = 20_000, 4
+    ot = oracle.ecm(c, S, seed)
+    lb, le = 5, min(60, ot.n_leaves)
+    dist, samples, oc, _ = oracle.run(c, ot, seed, leaf_begin=lb, leaf_end=le)
+    ec, t, o, r = _engine(ctx, c, S, seed, leaf_begin=lb, leaf_end=le, fusion_max_qubits=9)
+    np.testing.assert_allclose(r.distribution(), dist, atol=TOL_C128, rtol=0)
+    _check_samples(c, ot, seed, r.samples(), lb, le)
+    assert r.counters()["resets"] == oc["resets"] == 1
+
+
+def test_c64_error_is_stated_and_bounded(ctx):
+    _say("[gpu] c64 error")
+    c = brickwork(14, 20, 1e-3, 1e-2, 3)
+    S, seed = 10_000, 5
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    _, _, _, r64 = _engine(ctx, c, S, seed, precision="c64", want=1, drift_bound=1.0)
+    d64 = r64.distribution()
+    err = np.max(np.abs(d64 - dist))
+    tv = 0.5 * np.abs(d64 - dist).sum()
+    _say(f"[gpu] c64 max-abs {err:.3e} total-variation {tv:.3e}")
+    assert err < TOL_C64
+    # forcing a complex128 recompute at every leaf gives the c128 answer
+    _, _, _, rr = _engine(ctx, c, S, seed, precision="c64", want=1, drift_bound=0.0)
+    ct = rr.counters()
+    assert ct["recomputes"] == ct["leaves"]
+    err2 = np.max(np.abs(rr.distribution() - dist))
+    _say(f"[gpu] c64 with recompute at every leaf: max-abs {err2:.3e}")
+    assert err2 < 1e-6
+
+
+def test_product_state_at_26_qubits(ctx):
+    """Full-size addressing check with an exactly known answer: 1-qubit gates
+    only, so the output is a product of 26 one-qubit distributions."""
+    _say("[gpu] product state n=26")
+    n = 26
+    rng = np.random.default_rng(1)
+    c = Circuit(n)
+    for layer in range(3):
+        for q in range(n):
+            c.add("U3", (q,), rng.random(3) * 6.28)
+    ec, t, o, r = _engine(ctx, c, 1, 1, want=1)
+    dist = r.distribution()
+    per = []
+    for q in range(n):
+        c1 = Circuit(1)
+        for layer in range(3):
+            c1.add("U3", (0,), c.params[layer * n + q])
+        per.append(np.abs(oracle.trajectory(c1)) ** 2)
+    probe = rng.integers(0, 1 << n, 4000)
+    for x in probe:
+        want = 1.0
+        for q in range(n):
+            want *= per[q][(x >> q) & 1]
+        assert abs(dist[x] - want) < 1e-13
+    assert abs(dist.sum() - 1) < 1e-10
+
+
+def test_mirror_circuit_returns_to_zero_at_26_qubits(ctx):
+    """Brickwork followed by its inverse is the identity: the state returns
+    to |0...0> exactly up to rounding, whatever the tiling."""
+    _say("[gpu] mirror n=26")
+    n = 26
+    fwd = brickwork(n, 12, 0.0, 0.0, 9)
+    c = Circuit(n)
+    for k, q, p in zip(fwd.kinds, fwd.qubits, fwd.params):
+        c.add(k, q, p)
+    for k, q, p in reversed(list(zip(fwd.kinds, fwd.qubits, fwd.params))):
+        if k == "U3":
+            th, ph, la = p
+            c.add("U3", q, (-th, -la, -ph))
+        else:
+            c.add(k, q, p)
+    ec, t, o, r = _engine(ctx, c, 1, 1, want=1)
+    d = r.distribution()
+    assert abs(d[0] - 1.0) < 1e-10
+    assert d[1:].max() < 1e-12
+
+
+def test_repeat_run_is_bitwise_identical(ctx):
+    _say("[gpu] determinism")
+    c = brickwork(12, 10, 2e-3, 2e-2, 4)
+    a = _engine(ctx, c, 5000, 3, fusion_max_qubits=8)[3]
+    b = _engine(ctx, c, 5000, 3, fusion_max_qubits=8)[3]
+    assert a.distribution().tobytes() == b.distribution().tobytes()
+    assert a.samples().tobytes() == b.samples().tobytes()
+
+
+def test_injected_failure_and_budget(ctx):
+    _say("[gpu] error paths")
+    c = brickwork(10, 5, 1e-3, 1e-2, 2)
+    with pytest.raises(tq.TusqError) as e:
+        _engine(ctx, c, 2000, 1, debug_fail_at_step=3)
+    assert e.value.code == -4 and "injected" in str(e.value)
+    _engine(ctx, c, 2000, 1)          # context still usable
+    small = tq.Context(0, hbm_budget=1 << 20)
+    with pytest.raises(tq.TusqError) as e2:
+        _engine(small, c, 2000, 1)
+    assert e2.value.code == -2
+    small.close()
