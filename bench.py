@@ -46,6 +46,8 @@ def _args():
     p.add_argument("--fusion-max-ops", type=int, default=0)
     p.add_argument("--fusion-max-qubits", type=int, default=0)
     p.add_argument("--fusion-low-qubits", type=int, default=0)
+    p.add_argument("--drift-bound", type=float, default=1e-5,
+                   help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
     return p.parse_args()
 
 
@@ -79,7 +81,8 @@ def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision):
         tot["tokens"] += int(ct["fwd_gates"] + ct["inv_gates"] + ct["fwd_paulis"] + ct["inv_paulis"])
         _log(f"[bench] {precision} slice leaves [{lb},{lb + L}) shots {n} "
              f"sweeps {ct['passes_fwd'] + ct['passes_inv']} wall {dt:.3f}s "
-             f"sweep GB/s {ct['sweep_bytes'] / max(ct['pass_seconds'], 1e-12) / 1e9:.0f}")
+             f"sweep GB/s {ct['sweep_bytes'] / max(ct['pass_seconds'], 1e-12) / 1e9:.0f} "
+             f"max |norm-1| {ct['max_norm_drift']:.2e} recomputes {ct['recomputes']}")
     return tot
 
 
@@ -119,7 +122,7 @@ def main():
 
     circ = brickwork(a.qubits, a.layers, 1e-3, 1e-2, 1)
     ec = tq.Circuit(circ)
-    base = dict(shots=a.shots, seed=2, fusion_max_ops=a.fusion_max_ops,
+    base = dict(shots=a.shots, seed=2, fusion_max_ops=a.fusion_max_ops, drift_bound=a.drift_bound,
                 fusion_max_qubits=a.fusion_max_qubits, fusion_low_qubits=a.fusion_low_qubits)
     t0 = time.perf_counter()
     tree = tq.Tree(ec, tq.tusq_opts_default(**base))

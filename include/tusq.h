@@ -186,6 +186,17 @@ int tusq_plan_dump(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o
                    uint64_t *op_range, uint64_t *n_ops, uint32_t *ops, uint64_t *n_mats,
                    double *mats);
 
+/* Dump the register-blocked programs of a plan's sweeps: instr holds 2 u32
+ * per instruction (w0 = type | arg << 2 with type 0 = re-layout to the
+ * register qubits packed 5 bits each in arg, 1 = 2x2 op on register bit
+ * arg & 7, 2 = 4x4 op on register bits arg & 7 (high) and (arg >> 3) & 7;
+ * then the matrix offset in complex numbers); ranges holds 4 u32 per sweep
+ * (forward begin, end, undo begin, end).  *reg_qubits receives R.  Arrays
+ * may be NULL to query sizes.                                              */
+int tusq_plan_dump_programs(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *opts,
+                            uint64_t *n_instr, uint32_t *instr, uint64_t *n_passes,
+                            uint32_t *ranges, uint32_t *reg_qubits);
+
 /* ---- device execution ----------------------------------------------------- */
 /* A context owns device buffers, streams and the HBM accounting of one GPU.
  * hbm_budget_bytes = 0 means the device's free memory at creation.         */

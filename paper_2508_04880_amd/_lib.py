@@ -85,6 +85,7 @@ _SIGS = {
     "tusq_tree_destroy": (C.c_int, [P]),
     "tusq_plan_counters": (C.c_int, [P, P, P, P]),
     "tusq_plan_dump": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P]),
+    "tusq_plan_dump_programs": (C.c_int, [P, P, P, P, P, P, P, P]),
     "tusq_ctx_create": (C.c_int, [C.c_int, C.c_uint64, P]),
     "tusq_ctx_destroy": (C.c_int, [P]),
     "tusq_run": (C.c_int, [P, P, P, P, P]),
@@ -227,6 +228,17 @@ def tusq_plan_dump(circuit: Circuit, tree: Tree, opts: tusq_opts) -> dict:
     return {"steps": steps[: ns.value], "qubits": qubits[: npas.value],
             "op_range": oprange[: npas.value], "ops": ops[: nops.value],
             "mats": mats[: nmat.value, 0] + 1j * mats[: nmat.value, 1]}
+
+
+def tusq_plan_dump_programs(circuit: Circuit, tree: Tree, opts: tusq_opts) -> dict:
+    ni, npas, R = C.c_uint64(), C.c_uint64(), C.c_uint32()
+    check(lib.tusq_plan_dump_programs(circuit.h, tree.h, C.byref(opts), C.byref(ni), None,
+                                      C.byref(npas), None, C.byref(R)))
+    instr = np.zeros((max(ni.value, 1), 2), np.uint32)
+    ranges = np.zeros((max(npas.value, 1), 4), np.uint32)
+    check(lib.tusq_plan_dump_programs(circuit.h, tree.h, C.byref(opts), C.byref(ni), _ptr(instr),
+                                      C.byref(npas), _ptr(ranges), C.byref(R)))
+    return {"instr": instr[: ni.value], "ranges": ranges[: npas.value], "reg_qubits": R.value}
 
 
 class Result:

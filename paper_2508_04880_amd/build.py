@@ -24,6 +24,10 @@ CXX_SOURCES = ["host_ecm.cpp", "host_plan.cpp", "capi.cpp", "serve.cpp"]
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # keep hipcc from forming packed FP32 instructions
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # keep the register-blocked sweep's amplitude array in registers:
+             # merging near-identical switch cases would address it through
+             # pointer phis and move it to scratch memory
+             "-mllvm", "-simplifycfg-sink-common=false",
              "-Wall", "-Wno-unused-result"]
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
              "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include", "-pthread"]

@@ -246,6 +246,34 @@ int tusq_plan_dump(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o
     });
 }
 
+int tusq_plan_dump_programs(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o,
+                            uint64_t *n_instr, uint32_t *instr, uint64_t *n_passes, uint32_t *ranges,
+                            uint32_t *reg_qubits) {
+    return guarded([&] {
+        need(c && t && n_instr && n_passes && reg_qubits, "NULL argument");
+        check_opts(o);
+        auto *cc = const_cast<tusq_circuit *>(c);
+        cc->c.finalize();
+        need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
+        Plan p = build_plan(cc->c, t->t, *o, false);
+        *n_instr = p.prog.size();
+        *n_passes = p.passes.size();
+        *reg_qubits = p.reg_qubits;
+        if (instr)
+            for (size_t i = 0; i < p.prog.size(); ++i) {
+                instr[2 * i] = p.prog[i].w0;
+                instr[2 * i + 1] = p.prog[i].mat;
+            }
+        if (ranges)
+            for (size_t i = 0; i < p.passes.size(); ++i) {
+                ranges[4 * i] = p.passes[i].fwd_begin;
+                ranges[4 * i + 1] = p.passes[i].fwd_end;
+                ranges[4 * i + 2] = p.passes[i].inv_begin;
+                ranges[4 * i + 3] = p.passes[i].inv_end;
+            }
+    });
+}
+
 int tusq_ctx_create(int hip_device, uint64_t hbm_budget_bytes, tusq_ctx **out) {
     return guarded([&] {
         need(out != nullptr, "out is NULL");

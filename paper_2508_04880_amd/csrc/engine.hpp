@@ -94,6 +94,7 @@ struct Op {
     uint8_t a;      // local index of the (first) qubit
     uint8_t b;      // local index of the second qubit, or 0xFF for a 1-qubit op
     uint32_t mat;   // offset (complex numbers) into the matrix pool
+    uint32_t adj;   // offset of its adjoint
 };
 
 struct Pass {
@@ -101,6 +102,24 @@ struct Pass {
     uint32_t q[KMAX];
     uint32_t op_begin = 0, op_end = 0;
     uint32_t n_gates = 0, n_paulis = 0;  // tokens fused into it
+    // register-blocked programs (forward and undo), see Instr
+    uint32_t fwd_begin = 0, fwd_end = 0, inv_begin = 0, inv_end = 0;
+};
+
+// One instruction of a register-blocked sweep program.  Each thread holds
+// 2^R amplitudes of its tile whose local index bits at the R "register
+// qubits" vary; the others come from the thread index.
+//   IN_RELAYOUT: move the tile through LDS so that the register qubits
+//                become the R local qubits packed in `arg` (5 bits each);
+//   IN_OP1:      2x2 matrix on register bit (arg & 7);
+//   IN_OP2:      4x4 matrix on register bits a = arg & 7 (high bit of the
+//                4x4 index) and b = (arg >> 3) & 7.
+// mat is an offset (complex numbers) into the matrix pool; undo programs
+// reference the adjoint matrices, in reverse op order.
+enum : uint32_t { IN_RELAYOUT = 0, IN_OP1 = 1, IN_OP2 = 2 };
+struct Instr {
+    uint32_t w0;  // type | arg << 2
+    uint32_t mat;
 };
 
 enum StepKind : int64_t { ST_RESET = 0, ST_FWD = 1, ST_INV = 2, ST_LEAF = 3 };
@@ -121,6 +140,8 @@ struct Plan {
     std::vector<Op> ops;
     std::vector<cd> mats;
     std::vector<Step> steps;
+    std::vector<Instr> prog;
+    uint32_t reg_qubits = 4;  // R of the register-blocked programs
     // per leaf in the range: the passes forming its path from the root, used
     // to recompute a leaf exactly (c64 drift control)
     std::vector<uint64_t> path_off;

@@ -41,6 +41,8 @@ uint64_t job_device_bytes(uint32_t n, uint32_t precision, uint64_t shots, bool w
     return b;
 }
 
+static_assert(sizeof(Instr) == sizeof(Instr2), "program layout shared with the kernels");
+
 namespace {
 
 void to_device_ops(const Plan &plan, std::vector<DOp> &dops) {
@@ -58,6 +60,10 @@ SweepArgs sweep_args(const Pass &p, bool inverse) {
     a.nops = p.op_end - p.op_begin;
     a.op_begin = p.op_begin;
     a.inverse = inverse ? 1 : 0;
+    a.fwd_begin = p.fwd_begin;
+    a.fwd_end = p.fwd_end;
+    a.inv_begin = p.inv_begin;
+    a.inv_end = p.inv_end;
     for (uint32_t j = 0; j < p.k; ++j) a.q[j] = static_cast<uint8_t>(p.q[j]);
     return a;
 }
@@ -77,7 +83,7 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     const bool want_dist = o.want & TUSQ_WANT_DIST;
     const bool want_samples = o.want & TUSQ_WANT_SAMPLES;
 
-    DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops_b, mats_b, mats128_b;
+    DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops_b, mats_b, mats128_b, prog_b;
     psi.alloc(N * sizeof(V));
     if (c64) psi128.alloc(N * sizeof(double2));
     if (want_dist) acc.alloc(N * 8);
@@ -92,6 +98,10 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     if (!dops.empty())
         hip_check(hipMemcpyAsync(dops_b.p, dops.data(), dops.size() * sizeof(DOp), hipMemcpyHostToDevice, s),
                   "upload ops");
+    prog_b.alloc(std::max<size_t>(plan.prog.size(), 1) * sizeof(Instr2));
+    if (!plan.prog.empty())
+        hip_check(hipMemcpyAsync(prog_b.p, plan.prog.data(), plan.prog.size() * sizeof(Instr2),
+                                 hipMemcpyHostToDevice, s), "upload programs");
     std::vector<double2> m128(plan.mats.size());
     for (size_t i = 0; i < plan.mats.size(); ++i) m128[i] = double2{plan.mats[i].real(), plan.mats[i].imag()};
     std::vector<float2> m64;
@@ -118,6 +128,13 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     V *st = static_cast<V *>(psi.p);
     const DOp *dop = static_cast<const DOp *>(dops_b.p);
     const V *mat = static_cast<const V *>(mats_b.p);
+    const Instr2 *prog = static_cast<const Instr2 *>(prog_b.p);
+    // register-blocked sweeps wherever the tile spans at least R qubits
+    auto sweep = [&](const Pass &p, bool inverse) {
+        const SweepArgs a = sweep_args(p, inverse);
+        if (p.k >= plan.reg_qubits) return launch_sweep_reg<V>(st, n, a, prog, mat, s);
+        return launch_sweep<V>(st, n, a, dop, mat, s);
+    };
 
     const bool prof = o.profile != 0;
     std::vector<hipEvent_t> evs;
@@ -141,16 +158,16 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
             break;
         case ST_FWD:
         case ST_INV: {
-            const SweepArgs a = sweep_args(plan.passes[sp.id], sp.kind == ST_INV);
+            const Pass &pp = plan.passes[sp.id];
             if (prof) {
                 hipEvent_t e0 = ctx.event(), e1 = ctx.event();
                 hip_check(hipEventRecord(e0, s), "event");
-                hip_check(launch_sweep<V>(st, n, a, dop, mat, s), "sweep");
+                hip_check(sweep(pp, sp.kind == ST_INV), "sweep");
                 hip_check(hipEventRecord(e1, s), "event");
                 evs.push_back(e0);
                 evs.push_back(e1);
             } else {
-                hip_check(launch_sweep<V>(st, n, a, dop, mat, s), "sweep");
+                hip_check(sweep(pp, sp.kind == ST_INV), "sweep");
             }
             ++passes_since_exact;
             break;

@@ -95,6 +95,72 @@ M2 pauli_matrix(uint8_t p) {
     return M2{1.0, 0.0, 0.0, -1.0};
 }
 
+// Register-blocked programs of one sweep (see Instr): apply every op whose
+// qubits are register qubits, in dependency order; when none is left, pick
+// the next register set from the qubits of the next applicable ops and
+// re-layout through LDS; finally return to the initial layout (the top R
+// local qubits), which the kernel loads and stores coalesced.
+void build_programs(Plan &plan, Pass &p) {
+    const uint32_t k = p.k;
+    const uint32_t R = std::min(plan.reg_qubits, k);
+    const uint32_t init = ((1u << R) - 1u) << (k - R);
+    auto bitpos = [](uint32_t set, uint32_t q) {
+        return static_cast<uint32_t>(__builtin_popcount(set & ((1u << q) - 1u)));
+    };
+    auto relayout = [&](uint32_t set) {
+        uint32_t arg = 0, i = 0;
+        for (uint32_t q = 0; q < k; ++q)
+            if (set >> q & 1u) arg |= q << (5 * i++);
+        plan.prog.push_back(Instr{IN_RELAYOUT | (arg << 2), 0});
+    };
+    for (int pass_dir = 0; pass_dir < 2; ++pass_dir) {
+        const bool inverse = pass_dir == 1;
+        std::vector<uint32_t> rem;
+        for (uint32_t i = p.op_begin; i < p.op_end; ++i) rem.push_back(i);
+        if (inverse) std::reverse(rem.begin(), rem.end());
+        const uint32_t begin = static_cast<uint32_t>(plan.prog.size());
+        uint32_t cur = init;
+        while (!rem.empty()) {
+            uint32_t blocked = 0;
+            std::vector<uint32_t> keep;
+            for (uint32_t idx : rem) {
+                const Op &op = plan.ops[idx];
+                const uint32_t qm = (1u << op.a) | (op.b == 0xFF ? 0u : 1u << op.b);
+                if ((qm & blocked) || (qm & cur) != qm) {
+                    blocked |= qm;
+                    keep.push_back(idx);
+                    continue;
+                }
+                const uint32_t mat = inverse ? op.adj : op.mat;
+                if (op.b == 0xFF)
+                    plan.prog.push_back(Instr{IN_OP1 | (bitpos(cur, op.a) << 2), mat});
+                else
+                    plan.prog.push_back(
+                        Instr{IN_OP2 | ((bitpos(cur, op.a) | (bitpos(cur, op.b) << 3)) << 2), mat});
+            }
+            rem.swap(keep);
+            if (rem.empty()) break;
+            uint32_t nw = 0;
+            blocked = 0;
+            for (uint32_t idx : rem) {
+                const Op &op = plan.ops[idx];
+                const uint32_t qm = (1u << op.a) | (op.b == 0xFF ? 0u : 1u << op.b);
+                if (qm & blocked) { blocked |= qm; continue; }
+                if (static_cast<uint32_t>(__builtin_popcount(nw | qm)) <= R) nw |= qm;
+                else blocked |= qm;
+            }
+            for (uint32_t q = 0; q < k && static_cast<uint32_t>(__builtin_popcount(nw)) < R; ++q)
+                if (cur >> q & 1u) nw |= 1u << q;
+            relayout(nw);
+            cur = nw;
+        }
+        if (cur != init) relayout(init);
+        const uint32_t end = static_cast<uint32_t>(plan.prog.size());
+        if (inverse) { p.inv_begin = begin; p.inv_end = end; }
+        else { p.fwd_begin = begin; p.fwd_end = end; }
+    }
+}
+
 struct BuildOp {
     uint32_t qa, qb;  // global qubits; qb = NONE for 1-qubit ops
     bool live;
@@ -202,13 +268,18 @@ struct Fuser {
                 op.a = static_cast<uint8_t>(loc[o.qa]);
                 op.b = o.qb == NONE ? 0xFF : static_cast<uint8_t>(loc[o.qb]);
                 op.mat = static_cast<uint32_t>(plan.mats.size());
-                if (o.qb == NONE) plan.mats.insert(plan.mats.end(), o.m2.begin(), o.m2.end());
-                else plan.mats.insert(plan.mats.end(), o.m4.begin(), o.m4.end());
+                const int d = o.qb == NONE ? 2 : 4;
+                const cd *m = o.qb == NONE ? o.m2.data() : o.m4.data();
+                plan.mats.insert(plan.mats.end(), m, m + d * d);
+                op.adj = static_cast<uint32_t>(plan.mats.size());
+                for (int r = 0; r < d; ++r)
+                    for (int cc = 0; cc < d; ++cc) plan.mats.push_back(std::conj(m[cc * d + r]));
                 plan.ops.push_back(op);
             }
             p.op_end = static_cast<uint32_t>(plan.ops.size());
             p.n_gates = gates;
             p.n_paulis = paulis;
+            build_programs(plan, p);
             plan.passes.push_back(p);
         }
         return {first, static_cast<uint32_t>(plan.passes.size())};
@@ -232,6 +303,7 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
 Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths) {
     Plan plan;
     plan.n = c.n;
+    plan.reg_qubits = 4;  // 16 amplitudes per thread in both precisions
     const uint32_t G = t.G;
     uint64_t lb = o.leaf_begin, le = o.leaf_end;
     if (lb == 0 && le == 0) le = t.leaves();

@@ -28,11 +28,24 @@ template <typename V> struct RealOf;
 template <> struct RealOf<double2> { using T = double; };
 template <> struct RealOf<float2> { using T = float; };
 
+// acc + a * b as four fused multiply-adds
 template <typename V>
 __device__ __forceinline__ V cfma(V acc, V a, V b) {
-    acc.x += a.x * b.x - a.y * b.y;
-    acc.y += a.x * b.y + a.y * b.x;
+    acc.x = __builtin_fma(a.x, b.x, acc.x);
+    acc.x = __builtin_fma(-a.y, b.y, acc.x);
+    acc.y = __builtin_fma(a.x, b.y, acc.y);
+    acc.y = __builtin_fma(a.y, b.x, acc.y);
     return acc;
+}
+// a * b
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b) {
+    V r;
+    r.x = a.x * b.x;
+    r.x = __builtin_fma(-a.y, b.y, r.x);
+    r.y = a.x * b.y;
+    r.y = __builtin_fma(a.y, b.x, r.y);
+    return r;
 }
 template <typename V>
 __device__ __forceinline__ V cconj(V a) {
@@ -117,6 +130,191 @@ __global__ void __launch_bounds__(256) k_sweep(V *__restrict__ psi, SweepArgs a,
         __syncthreads();
     }
     for (uint32_t l = tid; l < T; l += blockDim.x) psi[base + scatter(l, a)] = tile[l];
+}
+
+// ---------------------------------------------------------------------------
+// Register-blocked sweep.  A workgroup of 2^(k-R) threads owns one tile;
+// thread t holds the 2^R amplitudes whose local index has t in the
+// non-register bits and any value in the R register bits.  Ops on register
+// qubits run entirely in registers (fully unrolled, matrix entries uniform);
+// a re-layout writes the tile to LDS and reads it back with another set of
+// register qubits.  LDS addresses are XOR-swizzled so that the power-of-two
+// strides of a re-layout spread over all banks.
+template <typename V>
+struct Swz {
+    static constexpr uint32_t SW = sizeof(V) == 16 ? 4 : 5;  // 256-byte bank row
+    __device__ static __forceinline__ uint32_t phys(uint32_t l) {
+        return l ^ (((l >> SW) ^ (l >> (2 * SW))) & ((1u << SW) - 1u));
+    }
+};
+
+template <typename V, int R, int B>
+__device__ __forceinline__ void reg_op1(V (&v)[1 << R], const V m0, const V m1, const V m2,
+                                        const V m3) {
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        if (j & (1 << B)) continue;
+        const V x0 = v[j], x1 = v[j | (1 << B)];
+        v[j] = cfma(cmul(m0, x0), m1, x1);
+        v[j | (1 << B)] = cfma(cmul(m2, x0), m3, x1);
+    }
+}
+
+template <typename V, int R, int A, int B>
+__device__ __forceinline__ void reg_op2(V (&v)[1 << R], const V *__restrict__ m) {
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        if (j & ((1 << A) | (1 << B))) continue;
+        const int i[4] = {j, j | (1 << B), j | (1 << A), j | (1 << A) | (1 << B)};
+        V x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = v[i[r]];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            V acc = cmul(m[4 * r], x[0]);
+#pragma unroll
+            for (int c = 1; c < 4; ++c) acc = cfma(acc, m[4 * r + c], x[c]);
+            v[i[r]] = acc;
+        }
+    }
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void dispatch_op1(uint32_t b, V (&v)[1 << R], const V *m) {
+    const V m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+    switch (b) {
+    case 0: reg_op1<V, R, 0>(v, m0, m1, m2, m3); break;
+    case 1: if constexpr (R > 1) reg_op1<V, R, 1>(v, m0, m1, m2, m3); break;
+    case 2: if constexpr (R > 2) reg_op1<V, R, 2>(v, m0, m1, m2, m3); break;
+    case 3: if constexpr (R > 3) reg_op1<V, R, 3>(v, m0, m1, m2, m3); break;
+    case 4: if constexpr (R > 4) reg_op1<V, R, 4>(v, m0, m1, m2, m3); break;
+    default: break;
+    }
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void dispatch_op2(uint32_t ab, V (&v)[1 << R], const V *__restrict__ m) {
+    switch (ab) {
+#define TUSQ_OP2_CASE(A, B) \
+    case (A) | ((B) << 3): if constexpr ((A) < R && (B) < R) reg_op2<V, R, A, B>(v, m); break;
+        TUSQ_OP2_CASE(0, 1) TUSQ_OP2_CASE(0, 2) TUSQ_OP2_CASE(0, 3) TUSQ_OP2_CASE(0, 4)
+        TUSQ_OP2_CASE(1, 0) TUSQ_OP2_CASE(1, 2) TUSQ_OP2_CASE(1, 3) TUSQ_OP2_CASE(1, 4)
+        TUSQ_OP2_CASE(2, 0) TUSQ_OP2_CASE(2, 1) TUSQ_OP2_CASE(2, 3) TUSQ_OP2_CASE(2, 4)
+        TUSQ_OP2_CASE(3, 0) TUSQ_OP2_CASE(3, 1) TUSQ_OP2_CASE(3, 2) TUSQ_OP2_CASE(3, 4)
+        TUSQ_OP2_CASE(4, 0) TUSQ_OP2_CASE(4, 1) TUSQ_OP2_CASE(4, 2) TUSQ_OP2_CASE(4, 3)
+#undef TUSQ_OP2_CASE
+    default: break;
+    }
+}
+
+// local index bits of thread t: t deposited into the positions of `free`
+__device__ __forceinline__ uint32_t deposit(uint32_t t, uint32_t free, uint32_t k) {
+    uint32_t out = 0, b = 0;
+    for (uint32_t p = 0; p < k; ++p)
+        if (free >> p & 1u) out |= ((t >> b++) & 1u) << p;
+    return out;
+}
+
+template <int R>
+__device__ __forceinline__ void unpack_set(uint32_t packed, uint32_t (&pos)[R], uint32_t &mask) {
+    mask = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        pos[i] = (packed >> (5 * i)) & 31u;
+        mask |= 1u << pos[i];
+    }
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void write_tile(const V (&v)[1 << R], V *lds, uint32_t tid, uint32_t k,
+                                           uint32_t packed) {
+    uint32_t pos[R], mask;
+    unpack_set<R>(packed, pos, mask);
+    const uint32_t dt = deposit(tid, ((1u << k) - 1u) & ~mask, k);
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        uint32_t l = dt;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (j >> i & 1) l |= 1u << pos[i];
+        lds[Swz<V>::phys(l)] = v[j];
+    }
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void read_tile(V (&v)[1 << R], const V *lds, uint32_t tid, uint32_t k,
+                                          uint32_t packed) {
+    uint32_t pos[R], mask;
+    unpack_set<R>(packed, pos, mask);
+    const uint32_t dt = deposit(tid, ((1u << k) - 1u) & ~mask, k);
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        uint32_t l = dt;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (j >> i & 1) l |= 1u << pos[i];
+        v[j] = lds[Swz<V>::phys(l)];
+    }
+}
+
+template <typename V, int R>
+__global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArgs a,
+                                                   const Instr2 *__restrict__ prog,
+                                                   const V *__restrict__ mats) {
+    extern __shared__ unsigned char smem_raw[];
+    V *lds = reinterpret_cast<V *>(smem_raw);
+    const uint32_t k = a.k;
+    const uint32_t tid = threadIdx.x;
+    uint64_t base = blockIdx.x;
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t q = a.q[j];
+        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
+    }
+    // initial layout: register qubits are the top R local qubits
+    uint64_t toff = tid & ((1u << a.low) - 1u);
+    for (uint32_t j = a.low; j < k - R; ++j) toff |= static_cast<uint64_t>((tid >> j) & 1u) << a.q[j];
+    uint64_t roff[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) roff[i] = 1ull << a.q[k - R + i];
+    V v[1 << R];
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        uint64_t o = base | toff;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (j >> i & 1) o |= roff[i];
+        v[j] = psi[o];
+    }
+    uint32_t cur = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) cur |= (k - R + i) << (5 * i);
+    bool lds_dirty = false;
+    const uint32_t ib = a.inverse ? a.inv_begin : a.fwd_begin;
+    const uint32_t ie = a.inverse ? a.inv_end : a.fwd_end;
+    for (uint32_t pc = ib; pc < ie; ++pc) {
+        const Instr2 ins = prog[pc];
+        const uint32_t type = ins.w0 & 3u, arg = ins.w0 >> 2;
+        if (type == 0u) {
+            if (lds_dirty) __syncthreads();
+            write_tile<V, R>(v, lds, tid, k, cur);
+            __syncthreads();
+            read_tile<V, R>(v, lds, tid, k, arg);
+            lds_dirty = true;
+            cur = arg;
+        } else if (type == 1u) {
+            dispatch_op1<V, R>(arg & 7u, v, mats + ins.mat);
+        } else {
+            dispatch_op2<V, R>(arg & 63u, v, mats + ins.mat);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        uint64_t o = base | toff;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (j >> i & 1) o |= roff[i];
+        psi[o] = v[j];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -289,6 +487,21 @@ hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, 
 }
 
 template <typename V>
+hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                            const V *mats, hipStream_t s) {
+    constexpr uint32_t R = sizeof(V) == 16 ? REG_QUBITS_C128 : REG_QUBITS_C64;
+    if (a.k > n || a.k > 16 || a.k < R || n - a.k > 31 || a.low > a.k) return hipErrorInvalidValue;
+    if (a.k - R > 8) return hipErrorInvalidValue;  // at most 256 threads
+    const size_t lds = sizeof(V) << a.k;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const unsigned blocks = 1u << (n - a.k);
+    const unsigned threads = 1u << (a.k - R);
+    hipLaunchKernelGGL((k_sweep_reg<V, R>), dim3(blocks), dim3(threads), lds, s, psi, a, prog, mats);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
 hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
                        double *chunk_sum, double *prefix, double *norm_out, hipStream_t s) {
     if (log_chunk > n) return hipErrorInvalidValue;
@@ -338,17 +551,25 @@ hipError_t launch_fill(double *p, uint64_t count, double v, hipStream_t s) {
 }
 
 hipError_t sweep_kernel_setup() {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<double2>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(k_sweep<float2>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    const void *ks[4] = {reinterpret_cast<const void *>(k_sweep<double2>),
+                         reinterpret_cast<const void *>(k_sweep<float2>),
+                         reinterpret_cast<const void *>(k_sweep_reg<double2, REG_QUBITS_C128>),
+                         reinterpret_cast<const void *>(k_sweep_reg<float2, REG_QUBITS_C64>)};
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template hipError_t launch_sweep<double2>(double2 *, uint32_t, const SweepArgs &, const DOp *,
                                           const double2 *, hipStream_t);
 template hipError_t launch_sweep<float2>(float2 *, uint32_t, const SweepArgs &, const DOp *,
                                          const float2 *, hipStream_t);
+template hipError_t launch_sweep_reg<double2>(double2 *, uint32_t, const SweepArgs &,
+                                              const Instr2 *, const double2 *, hipStream_t);
+template hipError_t launch_sweep_reg<float2>(float2 *, uint32_t, const SweepArgs &,
+                                             const Instr2 *, const float2 *, hipStream_t);
 template hipError_t launch_leaf<double2>(const double2 *, uint32_t, uint32_t, double *, double,
                                          double *, double *, double *, hipStream_t);
 template hipError_t launch_leaf<float2>(const float2 *, uint32_t, uint32_t, double *, double,

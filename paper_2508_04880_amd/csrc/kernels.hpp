@@ -15,6 +15,17 @@ struct alignas(8) DOp {
     uint32_t mat;
 };
 
+// One instruction of a register-blocked sweep program (layout of the
+// host's Instr): w0 = type | arg << 2, mat = matrix offset.
+struct alignas(8) Instr2 {
+    uint32_t w0;
+    uint32_t mat;
+};
+
+// register qubits per thread of the register-blocked sweep
+constexpr uint32_t REG_QUBITS_C128 = 4;
+constexpr uint32_t REG_QUBITS_C64 = 4;
+
 // Arguments of one sweep launch, passed by value.
 struct SweepArgs {
     uint32_t k;         // tile qubits
@@ -22,12 +33,16 @@ struct SweepArgs {
     uint32_t nops;
     uint32_t op_begin;
     uint32_t inverse;   // apply the ops' adjoints in reverse order
+    uint32_t fwd_begin, fwd_end, inv_begin, inv_end;  // register programs
     uint8_t q[16];      // tile qubits, ascending
 };
 
 template <typename V>
 hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, const V *mats,
                         hipStream_t s);
+template <typename V>
+hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                            const V *mats, hipStream_t s);
 template <typename V>
 hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
                        double *chunk_sum, double *prefix, double *norm_out, hipStream_t s);

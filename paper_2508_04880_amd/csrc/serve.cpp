@@ -6,5 +6,4 @@ void serving_wait(Ctx &, uint64_t, Result &) { fail(TUSQ_EUNSUPPORTED, "serving 
 void serving_cancel(Ctx &, uint64_t) { fail(TUSQ_EUNSUPPORTED, "serving not available"); }
 void serving_times(Ctx &, uint64_t, double *, double *, double *) { fail(TUSQ_EUNSUPPORTED, "serving not available"); }
 void serving_shutdown(Ctx &) {}
-void run_batch(Ctx &, const std::vector<const Circuit *> &, const tusq_opts &, std::vector<Result> &) { fail(TUSQ_EUNSUPPORTED, "batching not available"); }
 }

@@ -173,6 +173,62 @@ def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops):
     np.testing.assert_allclose(acc, dist, atol=1e-12)
 
 
+def _run_programs_numpy(c, dump, progs, weights):
+    """Replay the register-blocked programs: a re-layout only changes which
+    local qubits the register bits name; ops act on those qubits."""
+    n = c.n
+    R = progs["reg_qubits"]
+    psi = np.zeros(1 << n, complex)
+    acc = np.zeros(1 << n)
+    for kind, ident in dump["steps"]:
+        if kind == 0:
+            psi[:] = 0
+            psi[0] = 1
+            continue
+        if kind == 3:
+            acc += weights[ident] * np.abs(psi) ** 2
+            continue
+        q = dump["qubits"][ident]
+        k = int((q != 0xFFFFFFFF).sum())
+        r = min(R, k)
+        cur = list(range(k - r, k))
+        fb, fe, ib, ie = progs["ranges"][ident]
+        b, e = (ib, ie) if kind == 2 else (fb, fe)
+        for w0, mat in progs["instr"][b:e]:
+            typ, arg = int(w0) & 3, int(w0) >> 2
+            if typ == 0:
+                cur = [(arg >> (5 * i)) & 31 for i in range(r)]
+                assert cur == sorted(cur)
+            elif typ == 1:
+                M = dump["mats"][mat: mat + 4]
+                psi = _apply_local(psi, n, q, (cur[arg & 7], 0xFF), M, False)
+            else:
+                M = dump["mats"][mat: mat + 16]
+                psi = _apply_local(psi, n, q, (cur[arg & 7], cur[(arg >> 3) & 7]), M, False)
+        assert cur == list(range(k - r, k))
+    return acc
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("trav", ["dftt", "hybrid"])
+@pytest.mark.parametrize("kmax,low,maxops", [(6, 2, 4), (7, 3, 12), (16, 5, 12)])
+def test_register_programs_reproduce_oracle(precision, trav, kmax, low, maxops):
+    c = brickwork(8, 8, 0.02, 0.05, 12)
+    S = 3000
+    ot = oracle.ecm(c, S, 4, prune=True, alpha=(1, 50), beta=20)
+    dist, _, _, _ = oracle.run(c, ot, 4, traversal=trav, want_samples=False)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=4, alpha=(1, 50), beta=20, traversal=trav,
+                             precision=precision, fusion_max_qubits=kmax,
+                             fusion_low_qubits=low, fusion_max_ops=maxops)
+    et = tq.Tree(ec, o)
+    dump = tq.tusq_plan_dump(ec, et, o)
+    progs = tq.tusq_plan_dump_programs(ec, et, o)
+    assert progs["reg_qubits"] == 4
+    acc = _run_programs_numpy(c, dump, progs, ot.weights())
+    np.testing.assert_allclose(acc, dist, atol=1e-12)
+
+
 def test_fused_plan_ising_and_soup():
     for c in (ising(6, 4, 1e-2, 3e-2), random_small_circuit(6, 70, 2, p1=0.03, p2=0.05)):
         ot = oracle.ecm(c, 4000, 8, prune=False)
