@@ -30,6 +30,23 @@ void DevBuf::alloc(size_t b) {
     hip_check(hipMalloc(&p, b), "hipMalloc");
     bytes = b;
 }
+void DevBuf::ensure(size_t b) {
+    if (b <= bytes && p) return;
+    alloc(b);
+}
+
+uint64_t Workspace::bytes() const {
+    uint64_t b = 0;
+    for (const DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats,
+                            &mats128, &prog})
+        b += d->bytes;
+    return b;
+}
+void Workspace::release() {
+    for (DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats, &mats128,
+                      &prog})
+        d->release();
+}
 
 uint64_t job_device_bytes(uint32_t n, uint32_t precision, uint64_t shots, bool want_dist) {
     const uint64_t N = 1ull << n;
@@ -70,7 +87,7 @@ SweepArgs sweep_args(const Pass &p, bool inverse) {
 
 template <typename V>
 void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
-               Result &res) {
+               Result &res, Workspace &ws, const std::atomic<bool> *cancel) {
     const uint32_t n = plan.n;
     const uint64_t N = 1ull << n;
     const bool c64 = std::is_same<V, float2>::value;
@@ -83,22 +100,24 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     const bool want_dist = o.want & TUSQ_WANT_DIST;
     const bool want_samples = o.want & TUSQ_WANT_SAMPLES;
 
-    DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops_b, mats_b, mats128_b, prog_b;
-    psi.alloc(N * sizeof(V));
-    if (c64) psi128.alloc(N * sizeof(double2));
-    if (want_dist) acc.alloc(N * 8);
-    csum.alloc(nc * 8);
-    prefix.alloc(nc * 8);
-    norms.alloc(std::max<uint64_t>(le - lb, 1) * 8);
-    if (want_samples && total_shots) samples.alloc(total_shots * 8);
+    DevBuf &psi = ws.psi, &psi128 = ws.psi128, &acc = ws.acc, &csum = ws.csum, &prefix = ws.prefix,
+           &norms = ws.norms, &samples = ws.samples, &dops_b = ws.dops, &mats_b = ws.mats,
+           &mats128_b = ws.mats128, &prog_b = ws.prog;
+    psi.ensure(N * sizeof(V));
+    if (c64) psi128.ensure(N * sizeof(double2));
+    if (want_dist) acc.ensure(N * 8);
+    csum.ensure(nc * 8);
+    prefix.ensure(nc * 8);
+    norms.ensure(std::max<uint64_t>(le - lb, 1) * 8);
+    if (want_samples && total_shots) samples.ensure(total_shots * 8);
 
     std::vector<DOp> dops;
     to_device_ops(plan, dops);
-    dops_b.alloc(std::max<size_t>(dops.size(), 1) * sizeof(DOp));
+    dops_b.ensure(std::max<size_t>(dops.size(), 1) * sizeof(DOp));
     if (!dops.empty())
         hip_check(hipMemcpyAsync(dops_b.p, dops.data(), dops.size() * sizeof(DOp), hipMemcpyHostToDevice, s),
                   "upload ops");
-    prog_b.alloc(std::max<size_t>(plan.prog.size(), 1) * sizeof(Instr2));
+    prog_b.ensure(std::max<size_t>(plan.prog.size(), 1) * sizeof(Instr2));
     if (!plan.prog.empty())
         hip_check(hipMemcpyAsync(prog_b.p, plan.prog.data(), plan.prog.size() * sizeof(Instr2),
                                  hipMemcpyHostToDevice, s), "upload programs");
@@ -109,16 +128,16 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
         m64.resize(plan.mats.size());
         for (size_t i = 0; i < plan.mats.size(); ++i)
             m64[i] = float2{static_cast<float>(plan.mats[i].real()), static_cast<float>(plan.mats[i].imag())};
-        mats_b.alloc(std::max<size_t>(m64.size(), 1) * sizeof(float2));
+        mats_b.ensure(std::max<size_t>(m64.size(), 1) * sizeof(float2));
         if (!m64.empty())
             hip_check(hipMemcpyAsync(mats_b.p, m64.data(), m64.size() * sizeof(float2), hipMemcpyHostToDevice, s),
                       "upload mats");
-        mats128_b.alloc(std::max<size_t>(m128.size(), 1) * sizeof(double2));
+        mats128_b.ensure(std::max<size_t>(m128.size(), 1) * sizeof(double2));
         if (!m128.empty())
             hip_check(hipMemcpyAsync(mats128_b.p, m128.data(), m128.size() * sizeof(double2),
                                      hipMemcpyHostToDevice, s), "upload mats");
     } else {
-        mats_b.alloc(std::max<size_t>(m128.size(), 1) * sizeof(double2));
+        mats_b.ensure(std::max<size_t>(m128.size(), 1) * sizeof(double2));
         if (!m128.empty())
             hip_check(hipMemcpyAsync(mats_b.p, m128.data(), m128.size() * sizeof(double2),
                                      hipMemcpyHostToDevice, s), "upload mats");
@@ -150,6 +169,12 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     for (size_t si = 0; si < plan.steps.size(); ++si) {
         if (o.debug_fail_at_step >= 0 && static_cast<size_t>(o.debug_fail_at_step) == si)
             fail(TUSQ_EDEVICE, "injected failure at schedule step " + std::to_string(si));
+        // chunk boundary: a cancelled job stops here (work already queued on
+        // the stream finishes on its own)
+        if (cancel && (si & 255u) == 0 && cancel->load(std::memory_order_relaxed)) {
+            (void)hipStreamSynchronize(s);
+            fail(TUSQ_ECANCELED, "job cancelled");
+        }
         const Step &sp = plan.steps[si];
         switch (sp.kind) {
         case ST_RESET:
@@ -281,12 +306,14 @@ void Ctx::recycle(std::vector<hipEvent_t> &evs) {
 }
 
 void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
-                  Result &res) {
+                  Result &res, Workspace *ws, const std::atomic<bool> *cancel) {
     hip_check(hipSetDevice(ctx.device), "hipSetDevice");
     if (!s) s = ctx.stream;
     if (plan.n > 34) fail(TUSQ_EUNSUPPORTED, "more than 34 qubits");
-    if (o.precision == TUSQ_C64) run_typed<float2>(ctx, t, plan, o, s, res);
-    else if (o.precision == TUSQ_C128) run_typed<double2>(ctx, t, plan, o, s, res);
+    Workspace local;
+    Workspace &w = ws ? *ws : local;
+    if (o.precision == TUSQ_C64) run_typed<float2>(ctx, t, plan, o, s, res, w, cancel);
+    else if (o.precision == TUSQ_C128) run_typed<double2>(ctx, t, plan, o, s, res, w, cancel);
     else fail(TUSQ_EINVAL, "unknown precision");
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -20,6 +21,15 @@ struct DevBuf {
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf();
     void alloc(size_t b);
+    void ensure(size_t b);  // reallocate only when larger than what is held
+    void release();
+};
+
+// Device buffers of one running job, reusable by the next job on the same
+// execution lane (they only grow).
+struct Workspace {
+    DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops, mats, mats128, prog;
+    uint64_t bytes() const;
     void release();
 };
 
@@ -52,7 +62,7 @@ struct Ctx {
 uint64_t job_device_bytes(uint32_t n, uint32_t precision, uint64_t shots, bool want_dist);
 
 void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
-                  Result &res);
+                  Result &res, Workspace *ws = nullptr, const std::atomic<bool> *cancel = nullptr);
 
 }  // namespace tusq
 

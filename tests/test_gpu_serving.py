@@ -1,0 +1,99 @@
+"""GPU tests of the serving loop: jobs submitted together run concurrently
+on execution lanes; each result equals the same job run alone (bit for
+bit, every job owns its buffers and reductions have a fixed order), small
+jobs match the oracle, admission respects the HBM budget, cancellation
+stops queued work."""
+
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2508_04880_amd as tq
+from workloads import brickwork, ising
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+MIX = [
+    (lambda: brickwork(8, 20, 1e-3, 1e-2, 1), "c128", 10_000),
+    (lambda: ising(12, 6, 5e-4, 5e-3), "c64", 20_000),
+    (lambda: brickwork(18, 12, 1e-3, 1e-2, 3), "c128", 50_000),
+    (lambda: brickwork(14, 15, 1e-3, 1e-2, 4), "c64", 10_000),
+    (lambda: ising(20, 5, 5e-4, 5e-3), "c128", 100_000),
+    (lambda: brickwork(10, 30, 2e-3, 2e-2, 6), "c128", 30_000),
+    (lambda: ising(16, 8, 5e-4, 5e-3), "c64", 10_000),
+    (lambda: brickwork(22, 10, 1e-3, 1e-2, 8), "c128", 20_000),
+]
+
+
+def test_mix_equals_alone_and_oracle():
+    _say("[gpu] serving mix")
+    ctx = tq.Context(0)
+    circs = [f() for f, _, _ in MIX]
+    ecs = [tq.Circuit(c) for c in circs]
+    opts = [tq.tusq_opts_default(shots=S, seed=40 + i, precision=p, drift_bound=1e-4)
+            for i, (_, p, S) in enumerate(MIX)]
+    ids = [tq.tusq_submit(ctx, ec, o) for ec, o in zip(ecs, opts)]
+    res = [tq.tusq_wait(ctx, j, c.n) for j, c in zip(ids, circs)]
+    for j in ids:
+        sub, adm, fin = tq.tusq_job_times(ctx, j)
+        assert sub <= adm <= fin
+        assert tq.tusq_poll(ctx, j) == 2
+    for i, (ec, o, r) in enumerate(zip(ecs, opts, res)):
+        alone = tq.tusq_run(ctx, ec, o)
+        assert r.distribution().tobytes() == alone.distribution().tobytes(), i
+        assert r.samples().tobytes() == alone.samples().tobytes(), i
+    for i in (0, 1, 5):
+        c, o = circs[i], opts[i]
+        ot = oracle.ecm(c, int(o.shots), int(o.seed))
+        dist, _, _, _ = oracle.run(c, ot, int(o.seed), want_samples=False)
+        tol = 1e-10 if o.precision == 0 else 1e-4
+        np.testing.assert_allclose(res[i].distribution(), dist, atol=tol, rtol=0)
+    ctx.close()
+
+
+def test_budget_queues_and_rejects():
+    _say("[gpu] serving budget")
+    big = brickwork(20, 6, 1e-3, 1e-2, 2)
+    # room for about one 20-qubit job at a time (16 MiB state + 8 MiB acc + scratch)
+    ctx = tq.Context(0, hbm_budget=120 << 20)
+    ecs = [tq.Circuit(big) for _ in range(3)]
+    ids = [tq.tusq_submit(ctx, ec, tq.tusq_opts_default(shots=20_000, seed=5 + i))
+           for i, ec in enumerate(ecs)]
+    res = [tq.tusq_wait(ctx, j, 20) for j in ids]
+    times = [tq.tusq_job_times(ctx, j) for j in ids]
+    # admitted one after another: no two run intervals overlap
+    iv = sorted((a, f) for _, a, f in times)
+    for (a0, f0), (a1, f1) in zip(iv, iv[1:]):
+        assert a1 >= f0 - 1e-3
+    for i, r in enumerate(res):
+        alone = tq.tusq_run(ctx, ecs[i], tq.tusq_opts_default(shots=20_000, seed=5 + i))
+        assert r.distribution().tobytes() == alone.distribution().tobytes()
+    huge = tq.Circuit(brickwork(28, 2, 1e-3, 1e-2, 2))
+    with pytest.raises(tq.TusqError) as e:
+        tq.tusq_submit(ctx, huge, tq.tusq_opts_default(shots=100))
+    assert e.value.code == -2
+    ctx.close()
+
+
+def test_cancel_queued_job():
+    _say("[gpu] serving cancel")
+    ctx = tq.Context(0, hbm_budget=120 << 20)
+    job = tq.Circuit(brickwork(20, 10, 1e-3, 1e-2, 7))
+    a = tq.tusq_submit(ctx, job, tq.tusq_opts_default(shots=20_000, seed=1))
+    b = tq.tusq_submit(ctx, job, tq.tusq_opts_default(shots=20_000, seed=2))
+    tq.tusq_cancel(ctx, b)   # queued for host work, planning, or waiting for memory
+    with pytest.raises(tq.TusqError) as e:
+        tq.tusq_wait(ctx, b, 20)
+    assert e.value.code == -6
+    assert tq.tusq_poll(ctx, b) == 4
+    r = tq.tusq_wait(ctx, a, 20)
+    assert abs(r.distribution().sum() - 1.0) < 1e-10
+    ctx.close()
