@@ -46,6 +46,7 @@ def _args():
     p.add_argument("--fusion-max-ops", type=int, default=0)
     p.add_argument("--fusion-max-qubits", type=int, default=0)
     p.add_argument("--fusion-low-qubits", type=int, default=0)
+    p.add_argument("--sweep-kernel", type=int, default=0)
     p.add_argument("--drift-bound", type=float, default=1e-5,
                    help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
     return p.parse_args()
@@ -123,6 +124,7 @@ def main():
     circ = brickwork(a.qubits, a.layers, 1e-3, 1e-2, 1)
     ec = tq.Circuit(circ)
     base = dict(shots=a.shots, seed=2, fusion_max_ops=a.fusion_max_ops, drift_bound=a.drift_bound,
+                sweep_kernel=a.sweep_kernel,
                 fusion_max_qubits=a.fusion_max_qubits, fusion_low_qubits=a.fusion_low_qubits)
     t0 = time.perf_counter()
     tree = tq.Tree(ec, tq.tusq_opts_default(**base))

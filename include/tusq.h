@@ -108,6 +108,9 @@ typedef struct {
     int32_t debug_fail_at_step;/* >= 0: fail with TUSQ_EDEVICE before that
                                   schedule step (tests of error paths)        */
     uint32_t host_threads;     /* host threads for the ECM (0 = all cores)    */
+    uint32_t sweep_kernel;     /* 0 auto, 1 register-blocked, 2 register-
+                                  blocked with the next tile prefetched into
+                                  LDS (persistent grid)                      */
 } tusq_opts;
 
 typedef struct {

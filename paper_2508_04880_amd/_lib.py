@@ -45,7 +45,7 @@ class tusq_opts(C.Structure):
                 ("want", C.c_uint32), ("fusion_max_qubits", C.c_uint32),
                 ("fusion_max_ops", C.c_uint32), ("fusion_low_qubits", C.c_uint32),
                 ("profile", C.c_uint32), ("debug_fail_at_step", C.c_int32),
-                ("host_threads", C.c_uint32)]
+                ("host_threads", C.c_uint32), ("sweep_kernel", C.c_uint32)]
 
 
 class tusq_counters(C.Structure):

@@ -149,9 +149,15 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     const V *mat = static_cast<const V *>(mats_b.p);
     const Instr2 *prog = static_cast<const Instr2 *>(prog_b.p);
     // register-blocked sweeps wherever the tile spans at least R qubits
+    const bool pipelined = o.sweep_kernel == 2;
+    const uint32_t pipe_grid = static_cast<uint32_t>(ctx.cus);  // one 128-KiB workgroup per CU
     auto sweep = [&](const Pass &p, bool inverse) {
         const SweepArgs a = sweep_args(p, inverse);
-        if (p.k >= plan.reg_qubits) return launch_sweep_reg<V>(st, n, a, prog, mat, s);
+        if (p.k >= plan.reg_qubits) {
+            if (pipelined && p.k - plan.reg_qubits >= 6 && (sizeof(V) << p.k) <= 64 * 1024)
+                return launch_sweep_pipe<V>(st, n, a, prog, mat, pipe_grid, s);
+            return launch_sweep_reg<V>(st, n, a, prog, mat, s);
+        }
         return launch_sweep<V>(st, n, a, dop, mat, s);
     };
 
@@ -275,6 +281,7 @@ Ctx::Ctx(int dev, uint64_t budget_) : device(dev) {
     if (dev < 0 || dev >= count) fail(TUSQ_EINVAL, "no such device");
     hip_check(hipSetDevice(dev), "hipSetDevice");
     hip_check(sweep_kernel_setup(), "kernel setup");
+    hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
     size_t fr = 0, tot = 0;
     hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
     budget = budget_ ? budget_ : static_cast<uint64_t>(fr);

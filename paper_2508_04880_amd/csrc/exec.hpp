@@ -45,6 +45,7 @@ struct Serving;  // request loop state (serve.cpp)
 
 struct Ctx {
     int device = 0;
+    int cus = 1;
     uint64_t budget = 0;
     hipStream_t stream = nullptr;
     std::mutex mu;

@@ -58,11 +58,43 @@ __device__ __forceinline__ uint32_t insert0(uint32_t p, uint32_t bit) {
     return ((p >> bit) << (bit + 1)) | lo;
 }
 
+// The sweep's tile qubits, read from the kernel arguments with static
+// indices only (a runtime index would turn every read into a dependent
+// memory round trip).
+struct QMap {
+    uint32_t q[16];
+};
+__device__ __forceinline__ QMap qmap(const SweepArgs &a) {
+    QMap m;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) m.q[j] = a.q[j];
+    return m;
+}
+__device__ __forceinline__ uint32_t qat(const QMap &m, uint32_t idx) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (static_cast<uint32_t>(j) == idx) r = m.q[j];
+    return r;
+}
+// Tile base: spread the tile index over the qubits outside the tile.
+__device__ __forceinline__ uint64_t tile_base(uint64_t t, const QMap &m, uint32_t k) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (static_cast<uint32_t>(j) < k) {
+            const uint32_t q = m.q[j];
+            t = ((t >> q) << (q + 1)) | (t & ((1ull << q) - 1ull));
+        }
+    return t;
+}
 // Global offset of local tile index l: bit j of l goes to qubit q[j].  The
 // first `low` qubits are 0 .. low-1, so those bits stay in place.
-__device__ __forceinline__ uint64_t scatter(uint32_t l, const SweepArgs &a) {
-    uint64_t off = l & ((1u << a.low) - 1u);
-    for (uint32_t j = a.low; j < a.k; ++j) off |= static_cast<uint64_t>((l >> j) & 1u) << a.q[j];
+__device__ __forceinline__ uint64_t scatter(uint32_t l, const QMap &m, uint32_t low, uint32_t k) {
+    uint64_t off = l & ((1u << low) - 1u);
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+        if (static_cast<uint32_t>(j) >= low && static_cast<uint32_t>(j) < k)
+            off |= static_cast<uint64_t>((l >> j) & 1u) << m.q[j];
     return off;
 }
 
@@ -74,13 +106,9 @@ __global__ void __launch_bounds__(256) k_sweep(V *__restrict__ psi, SweepArgs a,
     V *tile = reinterpret_cast<V *>(smem_raw);
     const uint32_t T = 1u << a.k;
     const uint32_t tid = threadIdx.x;
-    // tile base: spread the block index over the qubits outside the tile
-    uint64_t base = blockIdx.x;
-    for (uint32_t j = 0; j < a.k; ++j) {
-        const uint32_t q = a.q[j];
-        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
-    }
-    for (uint32_t l = tid; l < T; l += blockDim.x) tile[l] = psi[base + scatter(l, a)];
+    const QMap qm = qmap(a);
+    const uint64_t base = tile_base(blockIdx.x, qm, a.k);
+    for (uint32_t l = tid; l < T; l += blockDim.x) tile[l] = psi[base + scatter(l, qm, a.low, a.k)];
     __syncthreads();
     for (uint32_t i = 0; i < a.nops; ++i) {
         const DOp op = ops[a.op_begin + (a.inverse ? a.nops - 1 - i : i)];
@@ -129,7 +157,7 @@ __global__ void __launch_bounds__(256) k_sweep(V *__restrict__ psi, SweepArgs a,
         }
         __syncthreads();
     }
-    for (uint32_t l = tid; l < T; l += blockDim.x) psi[base + scatter(l, a)] = tile[l];
+    for (uint32_t l = tid; l < T; l += blockDim.x) psi[base + scatter(l, qm, a.low, a.k)] = tile[l];
 }
 
 // ---------------------------------------------------------------------------
@@ -225,35 +253,79 @@ __device__ __forceinline__ void unpack_set(uint32_t packed, uint32_t (&pos)[R], 
     }
 }
 
+// Workgroup barrier ordering LDS traffic only: s_waitcnt lgkmcnt(0)
+// (vector-memory and export counters left at their maxima), then s_barrier.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_s_barrier();
+}
+
+// Relayout addressing.  The swizzle is linear over GF(2) and the thread and
+// register parts of a local index have disjoint bits, so
+// phys(thread | reg) = phys(thread) ^ phys(reg): one XOR per element with a
+// wave-uniform constant.
 template <typename V, int R>
-__device__ __forceinline__ void write_tile(const V (&v)[1 << R], V *lds, uint32_t tid, uint32_t k,
-                                           uint32_t packed) {
+__device__ __forceinline__ void tile_addr(uint32_t tid, uint32_t k, uint32_t packed, uint32_t &pd,
+                                          uint32_t (&pr)[1 << R]) {
     uint32_t pos[R], mask;
     unpack_set<R>(packed, pos, mask);
-    const uint32_t dt = deposit(tid, ((1u << k) - 1u) & ~mask, k);
+    pd = Swz<V>::phys(deposit(tid, ((1u << k) - 1u) & ~mask, k));
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
-        uint32_t l = dt;
+        uint32_t l = 0;
 #pragma unroll
         for (int i = 0; i < R; ++i)
             if (j >> i & 1) l |= 1u << pos[i];
-        lds[Swz<V>::phys(l)] = v[j];
+        pr[j] = Swz<V>::phys(l);
     }
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void write_tile(const V (&v)[1 << R], V *lds, uint32_t tid, uint32_t k,
+                                           uint32_t packed) {
+    uint32_t pd, pr[1 << R];
+    tile_addr<V, R>(tid, k, packed, pd, pr);
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) lds[pd ^ pr[j]] = v[j];
 }
 
 template <typename V, int R>
 __device__ __forceinline__ void read_tile(V (&v)[1 << R], const V *lds, uint32_t tid, uint32_t k,
                                           uint32_t packed) {
-    uint32_t pos[R], mask;
-    unpack_set<R>(packed, pos, mask);
-    const uint32_t dt = deposit(tid, ((1u << k) - 1u) & ~mask, k);
+    uint32_t pd, pr[1 << R];
+    tile_addr<V, R>(tid, k, packed, pd, pr);
 #pragma unroll
-    for (int j = 0; j < (1 << R); ++j) {
-        uint32_t l = dt;
+    for (int j = 0; j < (1 << R); ++j) v[j] = lds[pd ^ pr[j]];
+}
+
+// Run a sweep program on the registers of one tile (see Instr).  `lds` is
+// the tile-sized re-layout scratch; `dirty` says whether another thread may
+// still be reading it.  The program starts and ends in the initial layout
+// (register qubits = the top R local qubits).
+template <typename V, int R>
+__device__ __forceinline__ void run_program(V (&v)[1 << R], V *lds, uint32_t tid, uint32_t k,
+                                            const Instr2 *__restrict__ prog, uint32_t ib,
+                                            uint32_t ie, const V *__restrict__ mats, bool dirty) {
+    uint32_t cur = 0;
 #pragma unroll
-        for (int i = 0; i < R; ++i)
-            if (j >> i & 1) l |= 1u << pos[i];
-        v[j] = lds[Swz<V>::phys(l)];
+    for (int i = 0; i < R; ++i) cur |= (k - R + i) << (5 * i);
+    for (uint32_t pc = ib; pc < ie; ++pc) {
+        const Instr2 ins = prog[pc];
+        const uint32_t type = ins.w0 & 3u, arg = ins.w0 >> 2;
+        if (type == 0u) {
+            // a re-layout only needs the LDS traffic of the workgroup ordered:
+            // wait for this wave's LDS operations, then meet at the barrier
+            if (dirty) lds_barrier();
+            write_tile<V, R>(v, lds, tid, k, cur);
+            lds_barrier();
+            read_tile<V, R>(v, lds, tid, k, arg);
+            dirty = true;
+            cur = arg;
+        } else if (type == 1u) {
+            dispatch_op1<V, R>(arg & 7u, v, mats + ins.mat);
+        } else {
+            dispatch_op2<V, R>(arg & 63u, v, mats + ins.mat);
+        }
     }
 }
 
@@ -265,17 +337,13 @@ __global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArg
     V *lds = reinterpret_cast<V *>(smem_raw);
     const uint32_t k = a.k;
     const uint32_t tid = threadIdx.x;
-    uint64_t base = blockIdx.x;
-    for (uint32_t j = 0; j < k; ++j) {
-        const uint32_t q = a.q[j];
-        base = ((base >> q) << (q + 1)) | (base & ((1ull << q) - 1ull));
-    }
+    const QMap qm = qmap(a);
+    const uint64_t base = tile_base(blockIdx.x, qm, k);
     // initial layout: register qubits are the top R local qubits
-    uint64_t toff = tid & ((1u << a.low) - 1u);
-    for (uint32_t j = a.low; j < k - R; ++j) toff |= static_cast<uint64_t>((tid >> j) & 1u) << a.q[j];
+    const uint64_t toff = scatter(tid, qm, a.low, k);
     uint64_t roff[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) roff[i] = 1ull << a.q[k - R + i];
+    for (int i = 0; i < R; ++i) roff[i] = 1ull << qat(qm, k - R + i);
     V v[1 << R];
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
@@ -285,28 +353,8 @@ __global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArg
             if (j >> i & 1) o |= roff[i];
         v[j] = psi[o];
     }
-    uint32_t cur = 0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) cur |= (k - R + i) << (5 * i);
-    bool lds_dirty = false;
-    const uint32_t ib = a.inverse ? a.inv_begin : a.fwd_begin;
-    const uint32_t ie = a.inverse ? a.inv_end : a.fwd_end;
-    for (uint32_t pc = ib; pc < ie; ++pc) {
-        const Instr2 ins = prog[pc];
-        const uint32_t type = ins.w0 & 3u, arg = ins.w0 >> 2;
-        if (type == 0u) {
-            if (lds_dirty) __syncthreads();
-            write_tile<V, R>(v, lds, tid, k, cur);
-            __syncthreads();
-            read_tile<V, R>(v, lds, tid, k, arg);
-            lds_dirty = true;
-            cur = arg;
-        } else if (type == 1u) {
-            dispatch_op1<V, R>(arg & 7u, v, mats + ins.mat);
-        } else {
-            dispatch_op2<V, R>(arg & 63u, v, mats + ins.mat);
-        }
-    }
+    run_program<V, R>(v, lds, tid, k, prog, a.inverse ? a.inv_begin : a.fwd_begin,
+                      a.inverse ? a.inv_end : a.fwd_end, mats, false);
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) {
         uint64_t o = base | toff;
@@ -314,6 +362,81 @@ __global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArg
         for (int i = 0; i < R; ++i)
             if (j >> i & 1) o |= roff[i];
         psi[o] = v[j];
+    }
+}
+
+constexpr uint32_t PIPE_TILE_BYTES = 64 * 1024;
+
+// Pipelined register-blocked sweep.  A persistent grid; each workgroup owns
+// two tile buffers in LDS and walks tiles blockIdx.x, +gridDim.x, ...  The
+// next tile streams from HBM straight into the idle buffer
+// (global_load_lds_dwordx4) while the current one is computed in registers,
+// so memory and FP64 work overlap inside one workgroup.
+template <typename V, int R>
+__global__ void __launch_bounds__(256) k_sweep_pipe(V *__restrict__ psi, SweepArgs a,
+                                                    const Instr2 *__restrict__ prog,
+                                                    const V *__restrict__ mats, uint32_t ntiles) {
+    constexpr uint32_t E = 16 / sizeof(V);  // amplitudes per 16-byte lane transfer
+    constexpr uint32_t NJ = (1u << R) / E;  // transfers per thread per tile
+    // two statically placed tile buffers (64 KiB each), so that every LDS
+    // access in an even or odd step names its buffer directly
+    __shared__ V bufA[PIPE_TILE_BYTES / sizeof(V)];
+    __shared__ V bufB[PIPE_TILE_BYTES / sizeof(V)];
+    const uint32_t k = a.k, T = 1u << k, NT = T >> R;
+    const uint32_t tid = threadIdx.x;
+    const QMap qm = qmap(a);
+    auto scat = [&](uint32_t l) { return scatter(l, qm, a.low, k); };
+    auto base_of = [&](uint32_t t) { return tile_base(t, qm, k); };
+    // register layout: thread tid holds local tid + j * NT
+    const uint64_t toff = scat(tid);
+    uint64_t roff[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) roff[i] = 1ull << qat(qm, k - R + i);
+    // transfer layout: lane element m = (jj * NT + tid) * E, natural LDS order
+    const uint64_t moff = scat(tid * E);
+    uint64_t joff[NJ];
+#pragma unroll
+    for (uint32_t jj = 0; jj < NJ; ++jj) joff[jj] = scat(jj * NT * E);
+    auto issue = [&](uint32_t t, V *buf) {
+        const uint64_t base = base_of(t) | moff;
+#pragma unroll
+        for (uint32_t jj = 0; jj < NJ; ++jj) {
+            const V *src = psi + (base | joff[jj]);
+            V *dst = buf + (jj * NT + (tid & ~63u)) * E;
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+        }
+    };
+    const uint32_t ib = a.inverse ? a.inv_begin : a.fwd_begin;
+    const uint32_t ie = a.inverse ? a.inv_end : a.fwd_end;
+    uint32_t t = blockIdx.x;
+    if (t >= ntiles) return;
+    issue(t, bufA);
+    auto step = [&](V *cur, V *nxt) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's transfers (and stores) are done
+        __syncthreads();                // ... and every other wave's
+        V v[1 << R];
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) v[j] = cur[tid + j * NT];
+        const uint32_t tn = t + gridDim.x;
+        if (tn < ntiles) issue(tn, nxt);  // streams in while this tile computes
+        run_program<V, R>(v, cur, tid, k, prog, ib, ie, mats, true);
+        const uint64_t base = base_of(t) | toff;
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) {
+            uint64_t o = base;
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                if (j >> i & 1) o |= roff[i];
+            psi[o] = v[j];
+        }
+        t = tn;
+    };
+    for (;;) {
+        step(bufA, bufB);
+        if (t >= ntiles) break;
+        step(bufB, bufA);
+        if (t >= ntiles) break;
     }
 }
 
@@ -502,6 +625,24 @@ hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2
 }
 
 template <typename V>
+hipError_t launch_sweep_pipe(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                             const V *mats, uint32_t grid, hipStream_t s) {
+    constexpr uint32_t R = sizeof(V) == 16 ? REG_QUBITS_C128 : REG_QUBITS_C64;
+    constexpr uint32_t E = 16 / sizeof(V);
+    if (a.k > n || a.k > 16 || a.k < R || n - a.k > 31 || a.low > a.k) return hipErrorInvalidValue;
+    if (a.k - R > 8 || a.k - R < 6) return hipErrorInvalidValue;  // 64..256 threads, whole waves
+    if (a.low < (E == 2 ? 1u : 0u)) return hipErrorInvalidValue;  // 16-byte transfers stay contiguous
+    if ((sizeof(V) << a.k) > PIPE_TILE_BYTES) return hipErrorInvalidValue;
+    const uint32_t ntiles = 1u << (n - a.k);
+    const unsigned blocks = grid < ntiles ? grid : ntiles;
+    const unsigned threads = 1u << (a.k - R);
+    hipLaunchKernelGGL((k_sweep_pipe<V, R>), dim3(blocks), dim3(threads), 0, s, psi, a, prog, mats,
+                       ntiles);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
 hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
                        double *chunk_sum, double *prefix, double *norm_out, hipStream_t s) {
     if (log_chunk > n) return hipErrorInvalidValue;
@@ -570,6 +711,10 @@ template hipError_t launch_sweep_reg<double2>(double2 *, uint32_t, const SweepAr
                                               const Instr2 *, const double2 *, hipStream_t);
 template hipError_t launch_sweep_reg<float2>(float2 *, uint32_t, const SweepArgs &,
                                              const Instr2 *, const float2 *, hipStream_t);
+template hipError_t launch_sweep_pipe<double2>(double2 *, uint32_t, const SweepArgs &,
+                                               const Instr2 *, const double2 *, uint32_t, hipStream_t);
+template hipError_t launch_sweep_pipe<float2>(float2 *, uint32_t, const SweepArgs &, const Instr2 *,
+                                              const float2 *, uint32_t, hipStream_t);
 template hipError_t launch_leaf<double2>(const double2 *, uint32_t, uint32_t, double *, double,
                                          double *, double *, double *, hipStream_t);
 template hipError_t launch_leaf<float2>(const float2 *, uint32_t, uint32_t, double *, double,

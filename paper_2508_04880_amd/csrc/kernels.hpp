@@ -44,6 +44,9 @@ template <typename V>
 hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
                             const V *mats, hipStream_t s);
 template <typename V>
+hipError_t launch_sweep_pipe(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                             const V *mats, uint32_t grid, hipStream_t s);
+template <typename V>
 hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
                        double *chunk_sum, double *prefix, double *norm_out, hipStream_t s);
 template <typename V>

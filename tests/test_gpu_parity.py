@@ -198,3 +198,21 @@ def test_injected_failure_and_budget(ctx):
         _engine(small, c, 2000, 1)
     assert e2.value.code == -2
     small.close()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("n,kmax,low", [(14, 10, 4), (16, 11, 5), (17, 12, 4)])
+def test_pipelined_sweep_matches_oracle(ctx, precision, n, kmax, low):
+    _say(f"[gpu] pipelined sweep {precision} n={n} k={kmax}")
+    c = brickwork(n, 8, 1e-3, 1e-2, 21 + n)
+    S, seed = 4000, 9
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    kw = dict(fusion_max_qubits=kmax, fusion_low_qubits=low, fusion_max_ops=12,
+              precision=precision, drift_bound=1.0)
+    _, _, _, rp = _engine(ctx, c, S, seed, sweep_kernel=2, **kw)
+    _, _, _, rr = _engine(ctx, c, S, seed, sweep_kernel=1, **kw)
+    tol = TOL_C128 if precision == "c128" else TOL_C64
+    np.testing.assert_allclose(rp.distribution(), dist, atol=tol, rtol=0)
+    # same ops in the same order: both kernels agree bit for bit
+    assert rp.distribution().tobytes() == rr.distribution().tobytes()
