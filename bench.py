@@ -1,27 +1,36 @@
 """Benchmark of the noisy statevector engine on one MI355X.
 
-Workload (default): plain DFTT in complex128 on a 26-qubit random brickwork
-circuit with 100 layers (U3 on every qubit, CX on alternating neighbour
-pairs), depolarising noise p1 = 1e-3 after each U3 and p2 = 1e-2 after each
-CX, 1,000,000 shots, seeds (circuit 1, noise 2).  The host error
-characterisation builds the whole tree (about 1e6 leaves) once, untimed but
-reported; its complete depth-first walk would take days on any device, so a
-step is a depth-first slice of consecutive leaves (the first leaf of a slice
-starts from |0...0>, as a shard of the leaf list would).  value = shots of
-the timed slices per second of wall time (state already resident in HBM).
+Default workload (the headline line): plain DFTT in complex128 on a 26-qubit
+random brickwork circuit with 100 layers (U3 on every qubit, CX on
+alternating neighbour pairs), depolarising noise p1 = 1e-3 after each U3 and
+p2 = 1e-2 after each CX, 1,000,000 shots, seeds (circuit 1, noise 2).  The
+host error characterisation builds the whole tree (about 1e6 leaves) once,
+untimed but reported; its complete depth-first walk would take days on any
+device, so a step is a depth-first slice of consecutive leaves (the first
+leaf of a slice starts from |0...0>, as a shard of the leaf list would).
+value = shots of the timed slices per second of wall time (state resident in
+HBM; the tree and plan live on the host, as in the paper's CPU
+pre-processing).
 
-The JSON line also carries the gate-sweep kernel's roofline (algorithmic
-bytes per sweep over its event-timed duration against the 8 TB/s HBM peak),
-the complex64 rate on the same slices, and the CPU oracle timed on a bounded
-sample of the same work.
+The line carries the gate-sweep kernel's roofline (algorithmic bytes per
+sweep over its event-timed duration against the 8 TB/s HBM peak; measured
+traffic from the committed rocprofv3 counter summary when it was taken on
+the current kernel source), the complex64 rate on the same slices, and the
+CPU oracle timed on a bounded sample of the same work.
+
+Other workloads (--workload): ising30 (30-qubit Trotter Ising, complex64 vs
+complex128), batch (many small jobs in one persistent launch), serve
+(Poisson request stream, p50/p99 latency).  Each prints its own JSON line.
 """
 
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +38,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_04880_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_reg_brickwork26_traffic.txt")
 
 
 def _args():
@@ -36,10 +47,13 @@ def _args():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--leaves-per-step", type=int, default=16)
+    p.add_argument("--workload", default="brick26",
+                   choices=["brick26", "ising30", "batch", "serve"])
+    p.add_argument("--leaves-per-step", type=int, default=8)
     p.add_argument("--shots", type=int, default=1_000_000)
     p.add_argument("--qubits", type=int, default=26)
     p.add_argument("--layers", type=int, default=100)
+    p.add_argument("--traversal", default="dftt", choices=["dftt", "naive", "hybrid"])
     p.add_argument("--no-c64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -49,6 +63,10 @@ def _args():
     p.add_argument("--sweep-kernel", type=int, default=0)
     p.add_argument("--drift-bound", type=float, default=1e-5,
                    help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
+    p.add_argument("--batch-jobs", type=int, default=1024)
+    p.add_argument("--serve-count", type=int, default=60)
+    p.add_argument("--serve-nmax", type=int, default=24)
+    p.add_argument("--serve-load", type=float, default=0.7)
     return p.parse_args()
 
 
@@ -56,15 +74,21 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision):
+def _fusion(a):
+    return dict(fusion_max_ops=a.fusion_max_ops, fusion_max_qubits=a.fusion_max_qubits,
+                fusion_low_qubits=a.fusion_low_qubits, sweep_kernel=a.sweep_kernel,
+                drift_bound=a.drift_bound, traversal=a.traversal)
+
+
+def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision, want=2):
     """Run `steps` consecutive slices of L leaves; returns totals."""
     tot = {"shots": 0, "wall": 0.0, "sweep_bytes": 0, "pass_seconds": 0.0, "pass_events": 0,
-           "passes": 0, "leaves": 0, "device": 0.0, "recomputes": 0, "tokens": 0}
-    shots_per_leaf = None
+           "passes": 0, "leaves": 0, "device": 0.0, "recomputes": 0, "tokens": 0,
+           "drift": 0.0, "results": []}
     for s in range(steps):
         lb = first_leaf + s * L
         o = tq.tusq_opts_default(**base_opts, precision=precision, leaf_begin=lb,
-                                 leaf_end=lb + L, want=2, profile=1)
+                                 leaf_end=lb + L, want=want, profile=1)
         t0 = time.perf_counter()
         r = tq.tusq_run_tree(ctx, ec, tree, o)
         dt = time.perf_counter() - t0
@@ -79,8 +103,11 @@ def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision):
         tot["leaves"] += int(ct["leaves"])
         tot["device"] += float(ct["device_seconds"])
         tot["recomputes"] += int(ct["recomputes"])
-        tot["tokens"] += int(ct["fwd_gates"] + ct["inv_gates"] + ct["fwd_paulis"] + ct["inv_paulis"])
-        _log(f"[bench] {precision} slice leaves [{lb},{lb + L}) shots {n} "
+        tot["tokens"] += int(ct["fwd_gates"] + ct["inv_gates"] + ct["fwd_paulis"]
+                             + ct["inv_paulis"])
+        tot["drift"] = max(tot["drift"], float(ct["max_norm_drift"]))
+        tot["results"].append(r)
+        _log(f"[bench] {precision} leaves [{lb},{lb + L}) shots {n} "
              f"sweeps {ct['passes_fwd'] + ct['passes_inv']} wall {dt:.3f}s "
              f"sweep GB/s {ct['sweep_bytes'] / max(ct['pass_seconds'], 1e-12) / 1e9:.0f} "
              f"max |norm-1| {ct['max_norm_drift']:.2e} recomputes {ct['recomputes']}")
@@ -112,20 +139,33 @@ def cpu_baseline(circ, tokens_applied, shots, budget_s):
                       f"timed slices"}
 
 
-def main():
-    a = _args()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this engine runs on one GPU; multi-GPU sharding is a "
-                          "design note only", "n_gpus": a.gpus}))
-        sys.exit(2)
-    import paper_2508_04880_amd as tq
-    from workloads import brickwork
+def measured_traffic(bytes_per_launch):
+    """HBM bytes per sweep from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        kv = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.strip().split("=", 1)
+                    kv[k.strip()] = v.strip()
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+        if kv.get("kernels_hip_sha256_16") != sha:
+            return None
+        fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
+        write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
+        return {"bytes_per_launch": round(fetch + write),
+                "vs_algorithmic": round((fetch + write) / bytes_per_launch, 4)}
+    except (OSError, KeyError, ValueError):
+        return None
 
+
+def bench_brick26(a, tq):
+    from workloads import brickwork
     circ = brickwork(a.qubits, a.layers, 1e-3, 1e-2, 1)
     ec = tq.Circuit(circ)
-    base = dict(shots=a.shots, seed=2, fusion_max_ops=a.fusion_max_ops, drift_bound=a.drift_bound,
-                sweep_kernel=a.sweep_kernel,
-                fusion_max_qubits=a.fusion_max_qubits, fusion_low_qubits=a.fusion_low_qubits)
+    base = dict(shots=a.shots, seed=2, **_fusion(a))
     t0 = time.perf_counter()
     tree = tq.Tree(ec, tq.tusq_opts_default(**base))
     ecm_s = time.perf_counter() - t0
@@ -136,13 +176,12 @@ def main():
     run_slices(tq, ctx, ec, tree, base, 0, a.warmup, L, "c128")
     first = a.warmup * L
     r128 = run_slices(tq, ctx, ec, tree, base, first, a.steps, L, "c128")
-    r64 = None
-    if not a.no_c64:
-        r64 = run_slices(tq, ctx, ec, tree, base, first, a.steps, L, "c64")
+    r64 = None if a.no_c64 else run_slices(tq, ctx, ec, tree, base, first, a.steps, L, "c64")
     value = r128["shots"] / r128["wall"]
     gbs = r128["sweep_bytes"] / r128["pass_seconds"] / 1e9
-    per_launch_bytes = 2 * (1 << a.qubits) * 16
-    avg_launch_us = r128["pass_seconds"] / max(r128["pass_events"], 1) * 1e6
+    per_launch = 2 * (1 << a.qubits) * 16
+    avg_us = r128["pass_seconds"] / max(r128["pass_events"], 1) * 1e6
+    traffic = measured_traffic(per_launch)
     out = {
         "metric": "noisy shots/sec (plain DFTT, complex128) + gate-sweep HBM GB/s",
         "value": round(value, 4),
@@ -156,28 +195,162 @@ def main():
         "vs_baseline": None,
         "dtype": "c128",
         "data": "synthetic",
-        "config": {"workload": f"brickwork n={a.qubits} L={a.layers} p1=1e-3 p2=1e-2 "
-                               f"S={a.shots} DFS slices of {L} leaves, plain DFTT",
+        "config": {"workload": f"random brickwork n={a.qubits} L={a.layers} p1=1e-3 "
+                               f"p2=1e-2 S={a.shots}, depth-first slices of {L} leaves, "
+                               f"{a.traversal}",
                    "qubits": a.qubits, "layers": a.layers, "shots": a.shots,
                    "leaves_per_step": L, "tree_leaves": info["n_leaves"],
                    "host_ecm_seconds": round(ecm_s, 3)},
         "gate_sweep_GBps": round(gbs, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_sweep<double2>",
-                     "bytes_per_launch": per_launch_bytes,
-                     "avg_launch_us": round(avg_launch_us, 2),
-                     "launches": r128["pass_events"]},
+                     "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_sweep_reg<double2,4>",
+                     "algorithmic_bytes_per_launch": per_launch,
+                     "avg_launch_us": round(avg_us, 2), "launches": r128["pass_events"]},
         "sweeps_per_leaf": round(r128["passes"] / max(r128["leaves"], 1), 2),
+        "gate_applications_per_leaf": round(r128["tokens"] / max(r128["leaves"], 1), 1),
     }
     if r64:
         out["c64"] = {"shots_per_s": round(r64["shots"] / r64["wall"], 4),
                       "gate_sweep_GBps": round(r64["sweep_bytes"] / r64["pass_seconds"] / 1e9, 1),
-                      "recomputes": r64["recomputes"],
+                      "recomputes": r64["recomputes"], "max_norm_drift": r64["drift"],
+                      "drift_bound": a.drift_bound,
                       "speedup_vs_c128": round(r128["wall"] / r64["wall"], 3)}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, r128["tokens"], r128["shots"], a.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_ising30(a, tq):
+    import numpy as np
+    from workloads import ising
+    circ = ising(30, 20, 5e-4, 5e-3)
+    ec = tq.Circuit(circ)
+    base = dict(shots=a.shots, seed=2, **_fusion(a))
+    t0 = time.perf_counter()
+    tree = tq.Tree(ec, tq.tusq_opts_default(**base))
+    ecm_s = time.perf_counter() - t0
+    info = tree.info()
+    _log(f"[bench] host ECM {ecm_s:.2f}s: {info}")
+    ctx = tq.Context(0)
+    L = max(1, min(a.leaves_per_step, 4))
+    r64 = run_slices(tq, ctx, ec, tree, base, 0, 1, L, "c64", want=3)
+    r128 = run_slices(tq, ctx, ec, tree, base, 0, 1, L, "c128", want=3)
+    d64 = r64["results"][0].distribution()
+    d128 = r128["results"][0].distribution()
+    err = float(np.max(np.abs(d64 - d128)))
+    tv = float(0.5 * np.abs(d64 - d128).sum())
+    s64, s128 = r64["results"][0].samples(), r128["results"][0].samples()
+    same = float((s64 == s128).mean()) if len(s64) else 1.0
+    return {"metric": "noisy shots/sec, 30-qubit Trotter Ising, complex64 vs complex128",
+            "value": round(r64["shots"] / r64["wall"], 4), "unit": "shots/s", "n_gpus": 1,
+            "dtype": "c64", "data": "synthetic",
+            "config": {"workload": f"Ising n=30 steps=20 p1=5e-4 p2=5e-3 S={a.shots}, "
+                                   f"first {L} of {info['n_leaves']} leaves"},
+            "c128_shots_per_s": round(r128["shots"] / r128["wall"], 4),
+            "c64_GBps": round(r64["sweep_bytes"] / r64["pass_seconds"] / 1e9, 1),
+            "c128_GBps": round(r128["sweep_bytes"] / r128["pass_seconds"] / 1e9, 1),
+            "c64_error_vs_c128": {"max_abs": err, "total_variation": tv,
+                                  "identical_samples": same,
+                                  "recomputes": r64["recomputes"],
+                                  "max_norm_drift": r64["drift"],
+                                  "drift_bound": a.drift_bound},
+            "host_ecm_seconds": round(ecm_s, 3)}
+
+
+def bench_batch(a, tq):
+    from workloads import batch_job_params, batch_jobs
+    params = batch_job_params(a.batch_jobs)
+    circs = batch_jobs(params)
+    ecs = [tq.Circuit(c) for c in circs]
+    ctx = tq.Context(0)
+    out = {"metric": "batched noisy jobs: shots/sec in one persistent launch",
+           "unit": "shots/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"{a.batch_jobs} random-brickwork jobs, n~U{{10..16}}, "
+                                  f"L~U{{10..60}}, p2~U[1e-3,2e-2], p1=p2/10, S=1e4, "
+                                  f"{a.traversal}"}}
+    for prec in ("c128", "c64"):
+        o = tq.tusq_opts_default(shots=10_000, seed=100_000, precision=prec,
+                                 traversal=a.traversal, want=2)
+        t0 = time.perf_counter()
+        res = tq.tusq_run_batch(ctx, ecs, o)
+        wall = time.perf_counter() - t0
+        ct = res[0].counters()
+        shots = sum(len(r.samples()) for r in res)
+        out[prec] = {"wall_s": round(wall, 3), "device_s": round(ct["device_seconds"], 3),
+                     "host_ecm_s": round(ct["host_ecm_seconds"], 3),
+                     "host_plan_s": round(ct["host_plan_seconds"], 3),
+                     "shots_per_s_device": round(shots / ct["device_seconds"], 1),
+                     "shots_per_s_wall": round(shots / wall, 1)}
+        _log(f"[bench] batch {prec}: {out[prec]}")
+    out["value"] = out["c128"]["shots_per_s_device"]
+    out["dtype"] = "c128"
+    return out
+
+
+def bench_serve(a, tq):
+    import numpy as np
+    from workloads import serving_requests
+    ctx = tq.Context(0)
+    # capacity from a few requests served one at a time
+    warm = serving_requests(6, 1.0, seed=41, n_max=a.serve_nmax, shots_exp=(4.0, 5.0))
+    t0 = time.perf_counter()
+    for rq in warm:
+        o = tq.tusq_opts_default(shots=rq.shots, seed=rq.seed, precision=rq.precision, want=2)
+        tq.tusq_run(ctx, tq.Circuit(rq.circuit()), o)
+    per = (time.perf_counter() - t0) / len(warm)
+    rate = a.serve_load / per
+    reqs = serving_requests(a.serve_count, rate, seed=4, n_max=a.serve_nmax,
+                            shots_exp=(4.0, 5.0))
+    _log(f"[bench] serving: capacity {1 / per:.2f} req/s, offered {rate:.2f} req/s")
+    prepared = [(rq, tq.Circuit(rq.circuit())) for rq in reqs]
+    ids = [None] * len(reqs)
+    start = time.perf_counter()
+
+    def producer():
+        for i, (rq, ec) in enumerate(prepared):
+            delay = start + rq.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            o = tq.tusq_opts_default(shots=rq.shots, seed=rq.seed, precision=rq.precision,
+                                     want=2)
+            ids[i] = tq.tusq_submit(ctx, ec, o)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    lat, shots = [], 0
+    first_sub, last_fin = None, None
+    for (rq, ec), j in zip(prepared, ids):
+        r = tq.tusq_wait(ctx, j, rq.n)
+        shots += len(r.samples())
+        sub, adm, fin = tq.tusq_job_times(ctx, j)
+        lat.append(fin - sub)
+        first_sub = sub if first_sub is None else min(first_sub, sub)
+        last_fin = fin if last_fin is None else max(last_fin, fin)
+    lat = np.array(lat)
+    return {"metric": "served noisy jobs: p50/p99 latency and aggregate shots/sec",
+            "value": round(float(np.percentile(lat, 50)), 4), "unit": "s (p50 latency)",
+            "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+            "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4),
+            "aggregate_shots_per_s": round(shots / (last_fin - first_sub), 1),
+            "offered_req_per_s": round(rate, 3), "capacity_req_per_s": round(1 / per, 3),
+            "config": {"workload": f"{a.serve_count} Poisson requests, n log-uniform "
+                                   f"12..{a.serve_nmax}, brickwork/Ising 50/50, S=10^U[4,5], "
+                                   f"c64/c128 50/50, load {a.serve_load}"}}
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this engine runs on one GPU; sharding across GPUs is a "
+                          "design note only", "n_gpus": a.gpus}))
+        sys.exit(2)
+    import paper_2508_04880_amd as tq
+    fn = {"brick26": bench_brick26, "ising30": bench_ising30, "batch": bench_batch,
+          "serve": bench_serve}[a.workload]
+    print(json.dumps(fn(a, tq)), flush=True)
 
 
 if __name__ == "__main__":

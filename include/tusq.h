@@ -108,9 +108,10 @@ typedef struct {
     int32_t debug_fail_at_step;/* >= 0: fail with TUSQ_EDEVICE before that
                                   schedule step (tests of error paths)        */
     uint32_t host_threads;     /* host threads for the ECM (0 = all cores)    */
-    uint32_t sweep_kernel;     /* 0 auto, 1 register-blocked, 2 register-
-                                  blocked with the next tile prefetched into
-                                  LDS (persistent grid)                      */
+    uint32_t sweep_kernel;     /* 0 auto, 1 register-blocked (16 amplitudes
+                                  per thread), 2 the same with the next tile
+                                  prefetched into LDS (persistent grid),
+                                  3 register-blocked with 8 per thread       */
 } tusq_opts;
 
 typedef struct {

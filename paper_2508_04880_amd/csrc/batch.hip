@@ -27,6 +27,12 @@
 
 namespace tusq {
 
+// fused multiply-add in the precision of the operands (the double builtin
+// would promote complex64 arithmetic to FP64)
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+
 struct BUnit {
     uint32_t job, n, resident, k;
     uint32_t step_begin, step_end;
@@ -54,10 +60,10 @@ struct BLeaf {
 // acc + a * b as four fused multiply-adds
 template <typename V>
 __device__ __forceinline__ V bfma(V acc, V a, V b) {
-    acc.x = __builtin_fma(a.x, b.x, acc.x);
-    acc.x = __builtin_fma(-a.y, b.y, acc.x);
-    acc.y = __builtin_fma(a.x, b.y, acc.y);
-    acc.y = __builtin_fma(a.y, b.x, acc.y);
+    acc.x = fma_t(a.x, b.x, acc.x);
+    acc.x = fma_t(-a.y, b.y, acc.x);
+    acc.y = fma_t(a.x, b.y, acc.y);
+    acc.y = fma_t(a.y, b.x, acc.y);
     return acc;
 }
 

@@ -154,9 +154,10 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     auto sweep = [&](const Pass &p, bool inverse) {
         const SweepArgs a = sweep_args(p, inverse);
         if (p.k >= plan.reg_qubits) {
-            if (pipelined && p.k - plan.reg_qubits >= 6 && (sizeof(V) << p.k) <= 64 * 1024)
+            if (pipelined && plan.reg_qubits == 4 && p.k - plan.reg_qubits >= 6 &&
+                (sizeof(V) << p.k) <= 64 * 1024)
                 return launch_sweep_pipe<V>(st, n, a, prog, mat, pipe_grid, s);
-            return launch_sweep_reg<V>(st, n, a, prog, mat, s);
+            return launch_sweep_reg<V>(st, n, a, prog, mat, plan.reg_qubits, s);
         }
         return launch_sweep<V>(st, n, a, dop, mat, s);
     };

@@ -303,7 +303,9 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
 Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths) {
     Plan plan;
     plan.n = c.n;
-    plan.reg_qubits = 4;  // 16 amplitudes per thread in both precisions
+    // register qubits per thread: 4 (16 amplitudes) unless the 8-amplitude
+    // variant is asked for
+    plan.reg_qubits = o.sweep_kernel == 3 ? 3 : 4;
     const uint32_t G = t.G;
     uint64_t lb = o.leaf_begin, le = o.leaf_end;
     if (lb == 0 && le == 0) le = t.leaves();

@@ -24,6 +24,12 @@
 
 namespace tusq {
 
+// fused multiply-add in the precision of the operands (the double builtin
+// would promote complex64 arithmetic to FP64)
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+
 template <typename V> struct RealOf;
 template <> struct RealOf<double2> { using T = double; };
 template <> struct RealOf<float2> { using T = float; };
@@ -31,10 +37,10 @@ template <> struct RealOf<float2> { using T = float; };
 // acc + a * b as four fused multiply-adds
 template <typename V>
 __device__ __forceinline__ V cfma(V acc, V a, V b) {
-    acc.x = __builtin_fma(a.x, b.x, acc.x);
-    acc.x = __builtin_fma(-a.y, b.y, acc.x);
-    acc.y = __builtin_fma(a.x, b.y, acc.y);
-    acc.y = __builtin_fma(a.y, b.x, acc.y);
+    acc.x = fma_t(a.x, b.x, acc.x);
+    acc.x = fma_t(-a.y, b.y, acc.x);
+    acc.y = fma_t(a.x, b.y, acc.y);
+    acc.y = fma_t(a.y, b.x, acc.y);
     return acc;
 }
 // a * b
@@ -42,9 +48,9 @@ template <typename V>
 __device__ __forceinline__ V cmul(V a, V b) {
     V r;
     r.x = a.x * b.x;
-    r.x = __builtin_fma(-a.y, b.y, r.x);
+    r.x = fma_t(-a.y, b.y, r.x);
     r.y = a.x * b.y;
-    r.y = __builtin_fma(a.y, b.x, r.y);
+    r.y = fma_t(a.y, b.x, r.y);
     return r;
 }
 template <typename V>
@@ -609,10 +615,9 @@ hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, 
     return hipSuccess;
 }
 
-template <typename V>
-hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
-                            const V *mats, hipStream_t s) {
-    constexpr uint32_t R = sizeof(V) == 16 ? REG_QUBITS_C128 : REG_QUBITS_C64;
+template <typename V, uint32_t R>
+static hipError_t launch_reg_r(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                               const V *mats, hipStream_t s) {
     if (a.k > n || a.k > 16 || a.k < R || n - a.k > 31 || a.low > a.k) return hipErrorInvalidValue;
     if (a.k - R > 8) return hipErrorInvalidValue;  // at most 256 threads
     const size_t lds = sizeof(V) << a.k;
@@ -622,6 +627,14 @@ hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2
     hipLaunchKernelGGL((k_sweep_reg<V, R>), dim3(blocks), dim3(threads), lds, s, psi, a, prog, mats);
     TUSQ_CHECK_LAUNCH();
     return hipSuccess;
+}
+
+template <typename V>
+hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                            const V *mats, uint32_t reg_qubits, hipStream_t s) {
+    if (reg_qubits == 3) return launch_reg_r<V, 3>(psi, n, a, prog, mats, s);
+    if (reg_qubits == 4) return launch_reg_r<V, 4>(psi, n, a, prog, mats, s);
+    return hipErrorInvalidValue;
 }
 
 template <typename V>
@@ -692,10 +705,12 @@ hipError_t launch_fill(double *p, uint64_t count, double v, hipStream_t s) {
 }
 
 hipError_t sweep_kernel_setup() {
-    const void *ks[4] = {reinterpret_cast<const void *>(k_sweep<double2>),
+    const void *ks[6] = {reinterpret_cast<const void *>(k_sweep<double2>),
                          reinterpret_cast<const void *>(k_sweep<float2>),
-                         reinterpret_cast<const void *>(k_sweep_reg<double2, REG_QUBITS_C128>),
-                         reinterpret_cast<const void *>(k_sweep_reg<float2, REG_QUBITS_C64>)};
+                         reinterpret_cast<const void *>(k_sweep_reg<double2, 4>),
+                         reinterpret_cast<const void *>(k_sweep_reg<float2, 4>),
+                         reinterpret_cast<const void *>(k_sweep_reg<double2, 3>),
+                         reinterpret_cast<const void *>(k_sweep_reg<float2, 3>)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -708,9 +723,9 @@ template hipError_t launch_sweep<double2>(double2 *, uint32_t, const SweepArgs &
 template hipError_t launch_sweep<float2>(float2 *, uint32_t, const SweepArgs &, const DOp *,
                                          const float2 *, hipStream_t);
 template hipError_t launch_sweep_reg<double2>(double2 *, uint32_t, const SweepArgs &,
-                                              const Instr2 *, const double2 *, hipStream_t);
+                                              const Instr2 *, const double2 *, uint32_t, hipStream_t);
 template hipError_t launch_sweep_reg<float2>(float2 *, uint32_t, const SweepArgs &,
-                                             const Instr2 *, const float2 *, hipStream_t);
+                                             const Instr2 *, const float2 *, uint32_t, hipStream_t);
 template hipError_t launch_sweep_pipe<double2>(double2 *, uint32_t, const SweepArgs &,
                                                const Instr2 *, const double2 *, uint32_t, hipStream_t);
 template hipError_t launch_sweep_pipe<float2>(float2 *, uint32_t, const SweepArgs &, const Instr2 *,

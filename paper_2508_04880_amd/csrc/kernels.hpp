@@ -42,7 +42,7 @@ hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, 
                         hipStream_t s);
 template <typename V>
 hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
-                            const V *mats, hipStream_t s);
+                            const V *mats, uint32_t reg_qubits, hipStream_t s);
 template <typename V>
 hipError_t launch_sweep_pipe(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
                              const V *mats, uint32_t grid, hipStream_t s);
