@@ -61,6 +61,7 @@ def _args():
     p.add_argument("--fusion-max-qubits", type=int, default=0)
     p.add_argument("--fusion-low-qubits", type=int, default=0)
     p.add_argument("--sweep-kernel", type=int, default=0)
+    p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--drift-bound", type=float, default=1e-5,
                    help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
     p.add_argument("--batch-jobs", type=int, default=1024)
@@ -161,6 +162,25 @@ def measured_traffic(bytes_per_launch):
         return None
 
 
+TUNED = ("fusion_max_qubits", "fusion_low_qubits", "fusion_max_ops", "sweep_kernel")
+
+
+def tuned_opts(a, tq, ctx, ec, tree, base, precision):
+    """Sweep shapes from the library's autotuner (probed on leaf 0, which the
+    timed slices never include), unless given on the command line."""
+    if a.no_autotune or a.fusion_max_ops or a.fusion_max_qubits or a.sweep_kernel:
+        return dict(base)
+    t0 = time.perf_counter()
+    t = tq.tusq_autotune(ctx, ec, tree, tq.tusq_opts_default(**base, precision=precision,
+                                                             leaf_begin=0), 1)
+    out = dict(base)
+    for k in TUNED:
+        out[k] = getattr(t, k)
+    _log(f"[bench] autotuned {precision} in {time.perf_counter() - t0:.1f}s: "
+         f"{ {k: out[k] for k in TUNED} }")
+    return out
+
+
 def bench_brick26(a, tq):
     from workloads import brickwork
     circ = brickwork(a.qubits, a.layers, 1e-3, 1e-2, 1)
@@ -173,10 +193,15 @@ def bench_brick26(a, tq):
     _log(f"[bench] host ECM {ecm_s:.2f}s: {info}")
     ctx = tq.Context(0)
     L = a.leaves_per_step
-    run_slices(tq, ctx, ec, tree, base, 0, a.warmup, L, "c128")
-    first = a.warmup * L
-    r128 = run_slices(tq, ctx, ec, tree, base, first, a.steps, L, "c128")
-    r64 = None if a.no_c64 else run_slices(tq, ctx, ec, tree, base, first, a.steps, L, "c64")
+    b128 = tuned_opts(a, tq, ctx, ec, tree, base, "c128")
+    run_slices(tq, ctx, ec, tree, b128, 1, a.warmup, L, "c128")
+    first = 1 + a.warmup * L
+    r128 = run_slices(tq, ctx, ec, tree, b128, first, a.steps, L, "c128")
+    r64 = None
+    if not a.no_c64:
+        b64 = tuned_opts(a, tq, ctx, ec, tree, base, "c64")
+        run_slices(tq, ctx, ec, tree, b64, 1, 1, L, "c64")
+        r64 = run_slices(tq, ctx, ec, tree, b64, first, a.steps, L, "c64")
     value = r128["shots"] / r128["wall"]
     gbs = r128["sweep_bytes"] / r128["pass_seconds"] / 1e9
     per_launch = 2 * (1 << a.qubits) * 16
@@ -199,8 +224,9 @@ def bench_brick26(a, tq):
                                f"p2=1e-2 S={a.shots}, depth-first slices of {L} leaves, "
                                f"{a.traversal}",
                    "qubits": a.qubits, "layers": a.layers, "shots": a.shots,
-                   "leaves_per_step": L, "tree_leaves": info["n_leaves"],
-                   "host_ecm_seconds": round(ecm_s, 3)},
+                   "leaves_per_step": L, "first_timed_leaf": first,
+                   "tree_leaves": info["n_leaves"], "host_ecm_seconds": round(ecm_s, 3),
+                   "sweep_shape_c128": {k: b128[k] for k in TUNED}},
         "gate_sweep_GBps": round(gbs, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -212,6 +238,7 @@ def bench_brick26(a, tq):
     }
     if r64:
         out["c64"] = {"shots_per_s": round(r64["shots"] / r64["wall"], 4),
+                      "sweep_shape": {k: b64[k] for k in TUNED},
                       "gate_sweep_GBps": round(r64["sweep_bytes"] / r64["pass_seconds"] / 1e9, 1),
                       "recomputes": r64["recomputes"], "max_norm_drift": r64["drift"],
                       "drift_bound": a.drift_bound,
@@ -234,8 +261,10 @@ def bench_ising30(a, tq):
     _log(f"[bench] host ECM {ecm_s:.2f}s: {info}")
     ctx = tq.Context(0)
     L = max(1, min(a.leaves_per_step, 4))
-    r64 = run_slices(tq, ctx, ec, tree, base, 0, 1, L, "c64", want=3)
-    r128 = run_slices(tq, ctx, ec, tree, base, 0, 1, L, "c128", want=3)
+    b64 = tuned_opts(a, tq, ctx, ec, tree, base, "c64")
+    b128 = tuned_opts(a, tq, ctx, ec, tree, base, "c128")
+    r64 = run_slices(tq, ctx, ec, tree, b64, 1, 1, L, "c64", want=3)
+    r128 = run_slices(tq, ctx, ec, tree, b128, 1, 1, L, "c128", want=3)
     d64 = r64["results"][0].distribution()
     d128 = r128["results"][0].distribution()
     err = float(np.max(np.abs(d64 - d128)))
@@ -246,7 +275,9 @@ def bench_ising30(a, tq):
             "value": round(r64["shots"] / r64["wall"], 4), "unit": "shots/s", "n_gpus": 1,
             "dtype": "c64", "data": "synthetic",
             "config": {"workload": f"Ising n=30 steps=20 p1=5e-4 p2=5e-3 S={a.shots}, "
-                                   f"first {L} of {info['n_leaves']} leaves"},
+                                   f"leaves 1..{L} of {info['n_leaves']}"},
+            "sweep_shapes": {"c64": {k: b64[k] for k in TUNED},
+                             "c128": {k: b128[k] for k in TUNED}},
             "c128_shots_per_s": round(r128["shots"] / r128["wall"], 4),
             "c64_GBps": round(r64["sweep_bytes"] / r64["pass_seconds"] / 1e9, 1),
             "c128_GBps": round(r128["sweep_bytes"] / r128["pass_seconds"] / 1e9, 1),

@@ -216,6 +216,16 @@ int tusq_run(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *opts, void *
 int tusq_run_tree(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t,
                   const tusq_opts *opts, void *hip_stream, tusq_result **out);
 
+/* Autotuner: time a few candidate sweep shapes (tile qubits, low qubits,
+ * dense ops per sweep, amplitudes per thread) on the depth-first slice
+ * [opts->leaf_begin, opts->leaf_begin + probe_leaves) of tree t and write
+ * the fastest into *tuned (a copy of *opts with fusion_max_qubits,
+ * fusion_low_qubits, fusion_max_ops and sweep_kernel set).  The choice is
+ * cached in the context per (qubits, precision, gate count).  States that
+ * fit one tile need no tuning and are returned unchanged.                */
+int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, const tusq_opts *opts,
+                  uint32_t probe_leaves, tusq_opts *tuned);
+
 /* Serving: asynchronous jobs admitted by HBM need (state + recompute buffer
  * + FP64 accumulator + sampler scratch) against the context budget.  Jobs
  * that arrive while others run are admitted as memory and execution lanes

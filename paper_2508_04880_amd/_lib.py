@@ -90,6 +90,7 @@ _SIGS = {
     "tusq_ctx_destroy": (C.c_int, [P]),
     "tusq_run": (C.c_int, [P, P, P, P, P]),
     "tusq_run_tree": (C.c_int, [P, P, P, P, P, P]),
+    "tusq_autotune": (C.c_int, [P, P, P, P, C.c_uint32, P]),
     "tusq_submit": (C.c_int, [P, P, P, P]),
     "tusq_poll": (C.c_int, [P, C.c_uint64, P]),
     "tusq_wait": (C.c_int, [P, C.c_uint64, P]),
@@ -308,6 +309,14 @@ def tusq_run_tree(ctx: Context, circuit: Circuit, tree: Tree, opts: tusq_opts,
     check(lib.tusq_run_tree(ctx.h, circuit.h, tree.h, C.byref(opts), C.c_void_p(stream or 0),
                             C.byref(h)))
     return Result(h, circuit.n)
+
+
+def tusq_autotune(ctx: Context, circuit: Circuit, tree: Tree, opts: tusq_opts,
+                  probe_leaves: int = 1) -> tusq_opts:
+    out = tusq_opts()
+    check(lib.tusq_autotune(ctx.h, circuit.h, tree.h, C.byref(opts), C.c_uint32(probe_leaves),
+                            C.byref(out)))
+    return out
 
 
 def tusq_submit(ctx: Context, circuit: Circuit, opts: tusq_opts) -> int:

@@ -2,6 +2,7 @@
 // status codes; no exception crosses it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -342,6 +343,68 @@ int tusq_run_tree(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, cons
     return guarded([&] {
         need(t != nullptr, "tree is NULL");
         run_common(ctx, c, t, o, stream, out);
+    });
+}
+
+int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o,
+                  uint32_t probe_leaves, tusq_opts *tuned) {
+    return guarded([&] {
+        need(ctx && c && t && o && tuned, "NULL argument");
+        check_opts(o);
+        auto *cc = const_cast<tusq_circuit *>(c);
+        cc->c.finalize();
+        need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
+        *tuned = *o;
+        const uint32_t n = cc->c.n;
+        if (n <= 12) return;  // one tile holds the state
+        const uint64_t key = (static_cast<uint64_t>(n) << 48) | (static_cast<uint64_t>(o->precision) << 40) |
+                             cc->c.gates.size();
+        {
+            std::lock_guard<std::mutex> g(ctx->c->mu);
+            auto it = ctx->c->tuned.find(key);
+            if (it != ctx->c->tuned.end()) {
+                tuned->fusion_max_qubits = it->second[0];
+                tuned->fusion_low_qubits = it->second[1];
+                tuned->fusion_max_ops = it->second[2];
+                tuned->sweep_kernel = it->second[3];
+                return;
+            }
+        }
+        // (tile qubits, low qubits, ops per sweep, kernel): 1 = 16 amplitudes
+        // per thread, 3 = 8 (at most 11 tile qubits)
+        static const uint32_t cand[][4] = {{12, 4, 16, 1}, {12, 4, 24, 1}, {11, 5, 12, 1},
+                                           {11, 4, 16, 3}, {11, 5, 12, 3}, {11, 4, 24, 3}};
+        const uint64_t L = t->t.leaves();
+        const uint64_t lb = std::min<uint64_t>(o->leaf_begin, L ? L - 1 : 0);
+        const uint64_t le = std::min<uint64_t>(L, lb + std::max<uint32_t>(1, probe_leaves));
+        double best = 1e300;
+        uint32_t pick[4] = {0, 0, 0, 0};
+        for (const auto &cd : cand) {
+            if (cd[0] > n) continue;
+            tusq_opts tr = *o;
+            tr.fusion_max_qubits = cd[0];
+            tr.fusion_low_qubits = cd[1];
+            tr.fusion_max_ops = cd[2];
+            tr.sweep_kernel = cd[3];
+            tr.leaf_begin = lb;
+            tr.leaf_end = le;
+            tr.want = 0;
+            tr.profile = 0;
+            tr.drift_bound = 1e300;
+            Plan p = build_plan(cc->c, t->t, tr, false);
+            Result r;
+            execute_plan(*ctx->c, t->t, p, tr, nullptr, r);
+            if (r.counters.device_seconds < best) {
+                best = r.counters.device_seconds;
+                std::copy(cd, cd + 4, pick);
+            }
+        }
+        tuned->fusion_max_qubits = pick[0];
+        tuned->fusion_low_qubits = pick[1];
+        tuned->fusion_max_ops = pick[2];
+        tuned->sweep_kernel = pick[3];
+        std::lock_guard<std::mutex> g(ctx->c->mu);
+        ctx->c->tuned[key] = {pick[0], pick[1], pick[2], pick[3]};
     });
 }
 

@@ -222,8 +222,13 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
                     hip_check(launch_reset<double2>(s128, n, s), "reset128");
                     const double2 *mat128 = static_cast<const double2 *>(mats128_b.p);
                     for (uint64_t k = plan.path_off[li]; k < plan.path_off[li + 1]; ++k) {
-                        const SweepArgs a = sweep_args(plan.passes[plan.path[k]], false);
-                        hip_check(launch_sweep<double2>(s128, n, a, dop, mat128, s), "recompute sweep");
+                        const Pass &pp = plan.passes[plan.path[k]];
+                        const SweepArgs a = sweep_args(pp, false);
+                        // the sweep programs are precision independent
+                        hip_check(pp.k >= plan.reg_qubits
+                                      ? launch_sweep_reg<double2>(s128, n, a, prog, mat128, plan.reg_qubits, s)
+                                      : launch_sweep<double2>(s128, n, a, dop, mat128, s),
+                                  "recompute sweep");
                     }
                     hip_check(launch_to_c64(s128, reinterpret_cast<float2 *>(st), n, s), "convert");
                     ct.recomputes++;

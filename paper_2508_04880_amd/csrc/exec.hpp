@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -51,6 +53,7 @@ struct Ctx {
     std::mutex mu;
     std::vector<hipEvent_t> pool;
     Serving *serving = nullptr;
+    std::map<uint64_t, std::array<uint32_t, 4>> tuned;  // autotuner choices
 
     Ctx(int dev, uint64_t budget);
     ~Ctx();

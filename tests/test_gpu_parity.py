@@ -216,3 +216,37 @@ def test_pipelined_sweep_matches_oracle(ctx, precision, n, kmax, low):
     np.testing.assert_allclose(rp.distribution(), dist, atol=tol, rtol=0)
     # same ops in the same order: both kernels agree bit for bit
     assert rp.distribution().tobytes() == rr.distribution().tobytes()
+
+
+def test_autotuned_shape_is_valid_and_correct(ctx):
+    _say("[gpu] autotune")
+    c = brickwork(16, 10, 1e-3, 1e-2, 31)
+    S, seed = 3000, 12
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=seed)
+    t = tq.Tree(ec, o)
+    tuned = tq.tusq_autotune(ctx, ec, t, o, 2)
+    shape = (tuned.fusion_max_qubits, tuned.fusion_low_qubits, tuned.fusion_max_ops,
+             tuned.sweep_kernel)
+    assert shape in {(12, 4, 16, 1), (12, 4, 24, 1), (11, 5, 12, 1), (11, 4, 16, 3),
+                     (11, 5, 12, 3), (11, 4, 24, 3)}
+    again = tq.tusq_autotune(ctx, ec, t, o, 2)   # cached
+    assert again.fusion_max_ops == tuned.fusion_max_ops
+    r = tq.tusq_run_tree(ctx, ec, t, tuned)
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    np.testing.assert_allclose(r.distribution(), dist, atol=TOL_C128, rtol=0)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_eight_amplitude_sweep_matches_oracle(ctx, precision):
+    _say(f"[gpu] 8-amplitude sweep {precision}")
+    c = brickwork(15, 10, 1e-3, 1e-2, 33)
+    S, seed = 3000, 14
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    _, _, _, r = _engine(ctx, c, S, seed, precision=precision, sweep_kernel=3,
+                         fusion_max_qubits=11, fusion_low_qubits=4, fusion_max_ops=16,
+                         drift_bound=1.0)
+    tol = TOL_C128 if precision == "c128" else TOL_C64
+    np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
