@@ -38,8 +38,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
 KERNEL_SRC = os.path.join(ROOT, "paper_2508_04880_amd", "csrc", "kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_reg_brickwork26_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_pp_brickwork26_traffic.txt")
 
 
 def _args():
@@ -81,9 +82,17 @@ def _fusion(a):
                 drift_bound=a.drift_bound, traversal=a.traversal)
 
 
+def kernel_name(sweep_kernel, v):
+    """The sweep kernel a sweep_kernel option selects (0 = automatic)."""
+    return {0: f"k_sweep_pp<{v},4>", 1: f"k_sweep_reg<{v},4>", 2: f"k_sweep_pipe<{v},4>",
+            3: f"k_sweep_reg<{v},3>", 4: f"k_sweep_pp<{v},4>",
+            5: f"k_sweep_pp<{v},3>"}.get(int(sweep_kernel), "?")
+
+
 def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision, want=2):
     """Run `steps` consecutive slices of L leaves; returns totals."""
-    tot = {"shots": 0, "wall": 0.0, "sweep_bytes": 0, "pass_seconds": 0.0, "pass_events": 0,
+    tot = {"shots": 0, "wall": 0.0, "sweep_bytes": 0, "sweep_flops": 0, "pass_seconds": 0.0,
+           "pass_events": 0,
            "passes": 0, "leaves": 0, "device": 0.0, "recomputes": 0, "tokens": 0,
            "drift": 0.0, "results": []}
     for s in range(steps):
@@ -98,6 +107,7 @@ def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision, wa
         tot["shots"] += n
         tot["wall"] += dt
         tot["sweep_bytes"] += int(ct["sweep_bytes"])
+        tot["sweep_flops"] += int(ct["sweep_flops"])
         tot["pass_seconds"] += float(ct["pass_seconds"])
         tot["pass_events"] += int(ct["pass_events"])
         tot["passes"] += int(ct["passes_fwd"] + ct["passes_inv"])
@@ -140,9 +150,9 @@ def cpu_baseline(circ, tokens_applied, shots, budget_s):
                       f"timed slices"}
 
 
-def measured_traffic(bytes_per_launch):
+def measured_traffic(kernel):
     """HBM bytes per sweep from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+    was taken on this kernel and the current kernel source; else None."""
     try:
         kv = {}
         with open(TRAFFIC_FILE) as f:
@@ -152,12 +162,11 @@ def measured_traffic(bytes_per_launch):
                     kv[k.strip()] = v.strip()
         with open(KERNEL_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
-        if kv.get("kernels_hip_sha256_16") != sha:
+        if kv.get("kernels_hip_sha256_16") != sha or kv.get("kernel") != kernel:
             return None
         fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
         write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
-        return {"bytes_per_launch": round(fetch + write),
-                "vs_algorithmic": round((fetch + write) / bytes_per_launch, 4)}
+        return round(fetch + write)
     except (OSError, KeyError, ValueError):
         return None
 
@@ -206,7 +215,8 @@ def bench_brick26(a, tq):
     gbs = r128["sweep_bytes"] / r128["pass_seconds"] / 1e9
     per_launch = 2 * (1 << a.qubits) * 16
     avg_us = r128["pass_seconds"] / max(r128["pass_events"], 1) * 1e6
-    traffic = measured_traffic(per_launch)
+    traffic = measured_traffic(kernel_name(b128["sweep_kernel"], "double2"))
+    tflops = r128["sweep_flops"] / r128["pass_seconds"] / 1e12
     out = {
         "metric": "noisy shots/sec (plain DFTT, complex128) + gate-sweep HBM GB/s",
         "value": round(value, 4),
@@ -230,9 +240,16 @@ def bench_brick26(a, tq):
         "gate_sweep_GBps": round(gbs, 1),
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_sweep_reg<double2,4>",
+                     "traffic": traffic,
+                     "traffic_vs_algorithmic": (round(traffic / per_launch, 4)
+                                                if traffic else None),
+                     "kernel": kernel_name(b128["sweep_kernel"], "double2"),
                      "algorithmic_bytes_per_launch": per_launch,
-                     "avg_launch_us": round(avg_us, 2), "launches": r128["pass_events"]},
+                     "avg_launch_us": round(avg_us, 2), "launches": r128["pass_events"],
+                     # the same sweeps against the FP64 vector peak: the dense
+                     # ops' real operations per second
+                     "fp64_tflops": round(tflops, 2), "fp64_peak_tflops": FP64_PEAK_TFLOPS,
+                     "fp64_frac": round(tflops / FP64_PEAK_TFLOPS, 4)},
         "sweeps_per_leaf": round(r128["passes"] / max(r128["leaves"], 1), 2),
         "gate_applications_per_leaf": round(r128["tokens"] / max(r128["leaves"], 1), 1),
     }

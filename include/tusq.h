@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 1u
+#define TUSQ_ABI_VERSION 2u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -108,10 +108,14 @@ typedef struct {
     int32_t debug_fail_at_step;/* >= 0: fail with TUSQ_EDEVICE before that
                                   schedule step (tests of error paths)        */
     uint32_t host_threads;     /* host threads for the ECM (0 = all cores)    */
-    uint32_t sweep_kernel;     /* 0 auto, 1 register-blocked (16 amplitudes
-                                  per thread), 2 the same with the next tile
-                                  prefetched into LDS (persistent grid),
-                                  3 register-blocked with 8 per thread       */
+    uint32_t sweep_kernel;     /* 0 auto (= 4), 1 register-blocked, one tile
+                                  per workgroup (16 amplitudes per thread),
+                                  2 the same with the next tile prefetched
+                                  into LDS (persistent grid), 3 as 1 with 8
+                                  amplitudes per thread, 4 persistent
+                                  register-blocked with the next tile
+                                  prefetched into registers (16 per thread),
+                                  5 as 4 with 8 per thread                   */
 } tusq_opts;
 
 typedef struct {
@@ -124,6 +128,10 @@ typedef struct {
     uint64_t leaf_sweeps;               /* leaf accumulation sweeps               */
     uint64_t recomputes, recompute_passes;
     uint64_t sweep_bytes;               /* algorithmic bytes of all sweeps        */
+    uint64_t sweep_flops;               /* real floating-point operations of the
+                                           sweeps' dense ops: 16 per amplitude for
+                                           a 2x2, 32 for a 4x4 (one complex
+                                           multiply-add = 8)                     */
     uint64_t pass_events;               /* sweeps timed with events (profile)    */
     double pass_seconds;                /* their summed device time               */
     double host_ecm_seconds, host_plan_seconds, device_seconds;

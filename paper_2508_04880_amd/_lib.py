@@ -52,7 +52,7 @@ class tusq_counters(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in (
         "fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws",
         "ret_gates", "ret_paulis", "passes_fwd", "passes_inv", "leaf_sweeps", "recomputes",
-        "recompute_passes", "sweep_bytes", "pass_events")] + \
+        "recompute_passes", "sweep_bytes", "sweep_flops", "pass_events")] + \
         [(k, C.c_double) for k in ("pass_seconds", "host_ecm_seconds", "host_plan_seconds",
                                    "device_seconds", "max_norm_drift")]
 
@@ -108,6 +108,12 @@ for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
     _f.restype = _res
     _f.argtypes = _args
+
+# struct layouts below follow this version of include/tusq.h
+ABI_VERSION = 2
+if lib.tusq_abi_version() != ABI_VERSION:
+    raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
+                      f"expects {ABI_VERSION}: rebuild the library")
 
 
 class TusqError(RuntimeError):

@@ -440,6 +440,7 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         ct.resets += pc.resets; ct.leaves += pc.leaves; ct.draws += pc.draws;
         ct.passes_fwd += pc.passes_fwd; ct.passes_inv += pc.passes_inv;
         ct.leaf_sweeps += pc.leaf_sweeps; ct.sweep_bytes += pc.sweep_bytes;
+        ct.sweep_flops += pc.sweep_flops;
     }
     const double t_plan = now_seconds() - t1;
     // largest units first

@@ -113,7 +113,8 @@ struct Pass {
 //                become the R local qubits packed in `arg` (5 bits each);
 //   IN_OP1:      2x2 matrix on register bit (arg & 7);
 //   IN_OP2:      4x4 matrix on register bits a = arg & 7 (high bit of the
-//                4x4 index) and b = (arg >> 3) & 7.
+//                4x4 index) and b = (arg >> 3) & 7, with a > b.
+// Every program has even length (padded with a 2x2 identity).
 // mat is an offset (complex numbers) into the matrix pool; undo programs
 // reference the adjoint matrices, in reverse op order.
 enum : uint32_t { IN_RELAYOUT = 0, IN_OP1 = 1, IN_OP2 = 2 };
@@ -142,6 +143,7 @@ struct Plan {
     std::vector<Step> steps;
     std::vector<Instr> prog;
     uint32_t reg_qubits = 4;  // R of the register-blocked programs
+    uint32_t identity2 = UINT32_MAX;  // pool offset of the 2x2 identity (program padding)
     // per leaf in the range: the passes forming its path from the root, used
     // to recompute a leaf exactly (c64 drift control)
     std::vector<uint64_t> path_off;

@@ -150,6 +150,7 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     const Instr2 *prog = static_cast<const Instr2 *>(prog_b.p);
     // register-blocked sweeps wherever the tile spans at least R qubits
     const bool pipelined = o.sweep_kernel == 2;
+    const bool one_tile_per_wg = o.sweep_kernel == 1 || o.sweep_kernel == 3;
     const uint32_t pipe_grid = static_cast<uint32_t>(ctx.cus);  // one 128-KiB workgroup per CU
     auto sweep = [&](const Pass &p, bool inverse) {
         const SweepArgs a = sweep_args(p, inverse);
@@ -157,7 +158,9 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
             if (pipelined && plan.reg_qubits == 4 && p.k - plan.reg_qubits >= 6 &&
                 (sizeof(V) << p.k) <= 64 * 1024)
                 return launch_sweep_pipe<V>(st, n, a, prog, mat, pipe_grid, s);
-            return launch_sweep_reg<V>(st, n, a, prog, mat, plan.reg_qubits, s);
+            if (one_tile_per_wg) return launch_sweep_reg<V>(st, n, a, prog, mat, plan.reg_qubits, s);
+            return launch_sweep_pp<V>(st, n, a, prog, mat, plan.reg_qubits,
+                                      static_cast<uint32_t>(ctx.cus), s);
         }
         return launch_sweep<V>(st, n, a, dop, mat, s);
     };
@@ -226,7 +229,9 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
                         const SweepArgs a = sweep_args(pp, false);
                         // the sweep programs are precision independent
                         hip_check(pp.k >= plan.reg_qubits
-                                      ? launch_sweep_reg<double2>(s128, n, a, prog, mat128, plan.reg_qubits, s)
+                                      ? launch_sweep_pp<double2>(s128, n, a, prog, mat128,
+                                                                 plan.reg_qubits,
+                                                                 static_cast<uint32_t>(ctx.cus), s)
                                       : launch_sweep<double2>(s128, n, a, dop, mat128, s),
                                   "recompute sweep");
                     }

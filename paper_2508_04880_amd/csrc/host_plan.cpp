@@ -155,6 +155,15 @@ void build_programs(Plan &plan, Pass &p) {
             cur = nw;
         }
         if (cur != init) relayout(init);
+        // even length (the ping-pong kernel runs instructions in pairs):
+        // pad with the identity on register bit 0
+        if ((plan.prog.size() - begin) & 1u) {
+            if (plan.identity2 == UINT32_MAX) {
+                plan.identity2 = static_cast<uint32_t>(plan.mats.size());
+                plan.mats.insert(plan.mats.end(), {cd(1.0), cd(0.0), cd(0.0), cd(1.0)});
+            }
+            plan.prog.push_back(Instr{IN_OP1, plan.identity2});
+        }
         const uint32_t end = static_cast<uint32_t>(plan.prog.size());
         if (inverse) { p.inv_begin = begin; p.inv_end = end; }
         else { p.fwd_begin = begin; p.fwd_end = end; }
@@ -267,9 +276,16 @@ struct Fuser {
                 Op op;
                 op.a = static_cast<uint8_t>(loc[o.qa]);
                 op.b = o.qb == NONE ? 0xFF : static_cast<uint8_t>(loc[o.qb]);
+                // 2-qubit ops keep the higher local qubit as the high bit of
+                // the 4x4 index (the kernels' canonical order)
+                M4 m4 = o.m4;
+                if (o.qb != NONE && op.a < op.b) {
+                    std::swap(op.a, op.b);
+                    m4 = swap_halves(m4);
+                }
                 op.mat = static_cast<uint32_t>(plan.mats.size());
                 const int d = o.qb == NONE ? 2 : 4;
-                const cd *m = o.qb == NONE ? o.m2.data() : o.m4.data();
+                const cd *m = o.qb == NONE ? o.m2.data() : m4.data();
                 plan.mats.insert(plan.mats.end(), m, m + d * d);
                 op.adj = static_cast<uint32_t>(plan.mats.size());
                 for (int r = 0; r < d; ++r)
@@ -306,9 +322,9 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
 Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths) {
     Plan plan;
     plan.n = c.n;
-    // register qubits per thread: 4 (16 amplitudes) unless the 8-amplitude
+    // register qubits per thread: 4 (16 amplitudes) unless an 8-amplitude
     // variant is asked for
-    plan.reg_qubits = o.sweep_kernel == 3 ? 3 : 4;
+    plan.reg_qubits = (o.sweep_kernel == 3 || o.sweep_kernel == 5) ? 3 : 4;
     const uint32_t G = t.G;
     uint64_t lb = o.leaf_begin, le = o.leaf_end;
     if (lb == 0 && le == 0) le = t.leaves();
@@ -444,6 +460,15 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     }
     const uint64_t bytes_per_amp = o.precision == TUSQ_C64 ? 8 : 16;
     ct.sweep_bytes = (ct.passes_fwd + ct.passes_inv) * 2ull * (1ull << c.n) * bytes_per_amp;
+    // dense-op work: per amplitude, a 2x2 is 2 complex multiply-adds and a
+    // 4x4 is 4 (8 real operations each)
+    uint64_t per_amp = 0;
+    for (const Step &sp : plan.steps) {
+        if (sp.kind != ST_FWD && sp.kind != ST_INV) continue;
+        const Pass &p = plan.passes[sp.id];
+        for (uint32_t i = p.op_begin; i < p.op_end; ++i) per_amp += plan.ops[i].b == 0xFF ? 16 : 32;
+    }
+    ct.sweep_flops = per_amp << c.n;
     return plan;
 }
 

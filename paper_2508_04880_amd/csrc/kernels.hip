@@ -17,6 +17,7 @@
 //  k_reset, k_to_c64, k_fill   state initialisation and conversion.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -371,6 +372,233 @@ __global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArg
     }
 }
 
+// ---------------------------------------------------------------------------
+// Persistent ping-pong sweep.  Same programs and tile layout as k_sweep_reg,
+// with three changes that take per-instruction overhead off the vector ALU
+// and overlap HBM traffic with FP64 work:
+//  * two register arrays alternate as source and destination: every
+//    instruction writes its results straight into the other array, so the
+//    interpreter loop carries no register copies (programs have even length,
+//    padded with a copy instruction);
+//  * relayout addresses are one XOR per element: the swizzle is linear, so the
+//    thread part of an LDS address is the XOR of one wave-uniform column per
+//    set thread-index bit, and the register parts are wave-uniform;
+//  * each workgroup walks tiles blockIdx.x, +gridDim.x, ... and loads the
+//    next tile into a third register array while the current one computes.
+
+// workgroups of up to 2^PP_TBITS threads
+constexpr int PP_TBITS = 9;
+
+// LDS byte offset of this thread's part of a layout (register set `packed`):
+// thread-index bit b sits at the b-th local position outside the set.  The
+// positions are walked in a static loop with a wave-uniform bit counter, so
+// each free position costs one bit-field extract and one AND-XOR.
+template <typename V, int R>
+__device__ __forceinline__ uint32_t lds_thread_part(uint32_t tid, uint32_t k, uint32_t packed) {
+    uint32_t set = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) set |= 1u << ((packed >> (5 * i)) & 31u);
+    uint32_t pd = 0, b = 0;
+#pragma unroll
+    for (uint32_t p = 0; p < 16; ++p) {
+        if (p < k && !((set >> p) & 1u)) {
+            const uint32_t sel = 0u - ((tid >> b) & 1u);
+            pd ^= sel & (Swz<V>::phys(1u << p) * static_cast<uint32_t>(sizeof(V)));
+            ++b;
+        }
+    }
+    return pd;
+}
+
+// LDS byte offsets of the register parts of a layout (wave-uniform).
+template <typename V, int R>
+__device__ __forceinline__ void lds_reg_part(uint32_t packed, uint32_t (&pr)[1 << R]) {
+    uint32_t bit[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) bit[i] = 1u << ((packed >> (5 * i)) & 31u);
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        uint32_t l = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (j >> i & 1) l |= bit[i];
+        pr[j] = Swz<V>::phys(l) * static_cast<uint32_t>(sizeof(V));
+    }
+}
+
+template <typename V, int R, int B>
+__device__ __forceinline__ void pp_op1(const V (&x)[1 << R], V (&y)[1 << R],
+                                       const V *__restrict__ m) {
+    const V m0 = m[0], m1 = m[1], m2 = m[2], m3 = m[3];
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        if (j & (1 << B)) continue;
+        y[j] = cfma(cmul(m0, x[j]), m1, x[j | (1 << B)]);
+        y[j | (1 << B)] = cfma(cmul(m2, x[j]), m3, x[j | (1 << B)]);
+    }
+}
+
+// 4x4 matrix with row/column index 2 * bit(A) + bit(B); programs give A > B
+template <typename V, int R, int A, int B>
+__device__ __forceinline__ void pp_op2(const V (&x)[1 << R], V (&y)[1 << R],
+                                       const V *__restrict__ m) {
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        if (j & ((1 << A) | (1 << B))) continue;
+        const int i[4] = {j, j | (1 << B), j | (1 << A), j | (1 << A) | (1 << B)};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            V acc = cmul(m[4 * r], x[i[0]]);
+#pragma unroll
+            for (int c = 1; c < 4; ++c) acc = cfma(acc, m[4 * r + c], x[i[c]]);
+            y[i[r]] = acc;
+        }
+    }
+}
+
+template <typename V, int R>
+__device__ __forceinline__ void pp_copy(const V (&x)[1 << R], V (&y)[1 << R]) {
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) y[j] = x[j];
+}
+
+// One program instruction from x into y.  `cur` is the current layout,
+// `dirty` whether another wave may still read the LDS scratch.  Programs
+// hold valid instructions only (relayout, 1-qubit op on a register bit,
+// 2-qubit op on register bits a > b); there is no copy case, whose moves the
+// compiler would hoist in front of the dispatch.
+template <typename V, int R>
+__device__ __forceinline__ void pp_step(const V (&x)[1 << R], V (&y)[1 << R], Instr2 ins,
+                                        const V *__restrict__ mats, unsigned char *lds,
+                                        uint32_t tid, uint32_t k, uint32_t &cur,
+                                        bool &dirty) {
+    const uint32_t type = ins.w0 & 3u, arg = ins.w0 >> 2;
+    if (type == 0u) {  // relayout
+        uint32_t pr[1 << R];
+        if (dirty) lds_barrier();
+        uint32_t pd = lds_thread_part<V, R>(tid, k, cur);
+        lds_reg_part<V, R>(cur, pr);
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) *reinterpret_cast<V *>(lds + (pd ^ pr[j])) = x[j];
+        lds_barrier();
+        pd = lds_thread_part<V, R>(tid, k, arg);
+        lds_reg_part<V, R>(arg, pr);
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) y[j] = *reinterpret_cast<const V *>(lds + (pd ^ pr[j]));
+        dirty = true;
+        cur = arg;
+    } else if (type == 1u) {
+        const V *m = mats + ins.mat;
+        switch (arg & 7u) {
+        case 0: pp_op1<V, R, 0>(x, y, m); break;
+        case 1: pp_op1<V, R, 1>(x, y, m); break;
+        case 2: pp_op1<V, R, 2>(x, y, m); break;
+        case 3: if constexpr (R > 3) { pp_op1<V, R, 3>(x, y, m); break; } [[fallthrough]];
+        default: __builtin_unreachable();
+        }
+    } else {
+        const V *m = mats + ins.mat;
+        switch (arg & 63u) {
+        case 1 | (0 << 3): pp_op2<V, R, 1, 0>(x, y, m); break;
+        case 2 | (0 << 3): pp_op2<V, R, 2, 0>(x, y, m); break;
+        case 2 | (1 << 3): pp_op2<V, R, 2, 1>(x, y, m); break;
+        case 3 | (0 << 3): if constexpr (R > 3) { pp_op2<V, R, 3, 0>(x, y, m); break; } [[fallthrough]];
+        case 3 | (1 << 3): if constexpr (R > 3) { pp_op2<V, R, 3, 1>(x, y, m); break; } [[fallthrough]];
+        case 3 | (2 << 3): if constexpr (R > 3) { pp_op2<V, R, 3, 2>(x, y, m); break; } [[fallthrough]];
+        default: __builtin_unreachable();
+        }
+    }
+}
+
+template <typename V, int R>
+__global__ void __launch_bounds__(1 << PP_TBITS) k_sweep_pp(V *__restrict__ psi, SweepArgs a,
+                                                            const Instr2 *__restrict__ prog,
+                                                            const V *__restrict__ mats,
+                                                            uint32_t ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    const uint32_t k = a.k;
+    const uint32_t tid = threadIdx.x;
+    uint32_t init = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) init |= (k - R + i) << (5 * i);
+    const uint32_t ib = a.inverse ? a.inv_begin : a.fwd_begin;
+    const uint32_t ie = a.inverse ? a.inv_end : a.fwd_end;
+    uint32_t t = blockIdx.x;
+    if (t >= ntiles) return;
+
+    // Addresses.  The thread's amplitudes sit at pt[base | roff_j]: pt folds
+    // in the thread-index bits, roff_j the register bits (register qubit i
+    // is global qubit byte i of rq) and base the tile index spread over the
+    // qubits outside the tile (mask `out`).  Walking tiles t, t + G, ...
+    // advances base by a masked add: with the gaps filled with ones, carries
+    // skip the tile qubits.
+    uint64_t base, dG, out;
+    uint32_t rq = 0;
+    V *pt;
+    {
+        const QMap qm = qmap(a);
+        pt = psi + scatter(tid, qm, a.low, k);
+#pragma unroll
+        for (int i = 0; i < R; ++i) rq |= qat(qm, k - R + i) << (8 * i);
+        uint64_t in = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if (static_cast<uint32_t>(j) < k) in |= 1ull << qm.q[j];
+        out = ~in;
+        base = tile_base(t, qm, k);
+        dG = tile_base(gridDim.x, qm, k);
+    }
+    // register offsets are rebuilt from rq where used (the empty asm keeps
+    // the compiler from hoisting all 2^R of them into scalar registers that
+    // would stay live across the program loop)
+    auto off = [&](uint32_t q, int j) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i)
+            if (j >> i & 1) o |= 1ull << ((q >> (8 * i)) & 63u);
+        return o;
+    };
+    V x[1 << R], y[1 << R], nx[1 << R];
+    {
+        uint32_t q = rq;
+        asm volatile("" : "+s"(q));
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) x[j] = pt[base | off(q, j)];
+    }
+    bool dirty = false;
+    for (;;) {
+        // this tile's amplitudes have landed before the next tile's loads are
+        // issued: the program loop then waits on no vector-memory counter
+        // (a wait there would also wait for the prefetch)
+#pragma unroll
+        for (int j = 0; j < (1 << R); ++j) asm volatile("" : "+v"(x[j].x), "+v"(x[j].y));
+        const uint32_t tn = t + gridDim.x;
+        if (tn < ntiles) {  // in flight while this tile computes
+            const uint64_t nbase = ((base | ~out) + dG) & out;
+            uint32_t q = rq;
+            asm volatile("" : "+s"(q));
+#pragma unroll
+            for (int j = 0; j < (1 << R); ++j) nx[j] = pt[nbase | off(q, j)];
+        }
+        uint32_t cur = init;
+        for (uint32_t pc = ib; pc < ie; pc += 2) {
+            const Instr2 i0 = prog[pc], i1 = prog[pc + 1];
+            pp_step<V, R>(x, y, i0, mats, smem_raw, tid, k, cur, dirty);
+            pp_step<V, R>(y, x, i1, mats, smem_raw, tid, k, cur, dirty);
+        }
+        {
+            uint32_t q = rq;
+            asm volatile("" : "+s"(q));
+#pragma unroll
+            for (int j = 0; j < (1 << R); ++j) pt[base | off(q, j)] = x[j];
+        }
+        if (tn >= ntiles) break;
+        pp_copy<V, R>(nx, x);
+        t = tn;
+        base = ((base | ~out) + dG) & out;
+    }
+}
+
 constexpr uint32_t PIPE_TILE_BYTES = 64 * 1024;
 
 // Pipelined register-blocked sweep.  A persistent grid; each workgroup owns
@@ -637,6 +865,43 @@ hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2
     return hipErrorInvalidValue;
 }
 
+template <typename V, uint32_t R>
+static hipError_t launch_pp_r(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                              const V *mats, uint32_t cus, hipStream_t s) {
+    if (a.k > n || a.k > 16 || a.k < R || n - a.k > 31 || a.low > a.k) return hipErrorInvalidValue;
+    if (a.k - R > static_cast<uint32_t>(PP_TBITS)) return hipErrorInvalidValue;  // at most 512 threads
+    if (a.inverse ? (a.inv_end - a.inv_begin) & 1u : (a.fwd_end - a.fwd_begin) & 1u)
+        return hipErrorInvalidValue;  // programs come in pairs of instructions
+    const size_t lds = sizeof(V) << a.k;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    const unsigned threads = 1u << (a.k - R);
+    const uint32_t ntiles = 1u << (n - a.k);
+    // resident workgroups per CU for this tile size (cached per kernel and k)
+    static std::atomic<int> occ_cache[17];
+    int occ = occ_cache[a.k].load(std::memory_order_relaxed);
+    if (occ == 0) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, reinterpret_cast<const void *>(k_sweep_pp<V, R>), static_cast<int>(threads), lds);
+        if (e != hipSuccess) return e;
+        if (occ < 1) occ = 1;
+        occ_cache[a.k].store(occ, std::memory_order_relaxed);
+    }
+    const uint64_t want = static_cast<uint64_t>(occ) * (cus ? cus : 1u);
+    const unsigned blocks = static_cast<unsigned>(want < ntiles ? want : ntiles);
+    hipLaunchKernelGGL((k_sweep_pp<V, R>), dim3(blocks), dim3(threads), lds, s, psi, a, prog, mats,
+                       ntiles);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
+hipError_t launch_sweep_pp(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                           const V *mats, uint32_t reg_qubits, uint32_t cus, hipStream_t s) {
+    if (reg_qubits == 3) return launch_pp_r<V, 3>(psi, n, a, prog, mats, cus, s);
+    if (reg_qubits == 4) return launch_pp_r<V, 4>(psi, n, a, prog, mats, cus, s);
+    return hipErrorInvalidValue;
+}
+
 template <typename V>
 hipError_t launch_sweep_pipe(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
                              const V *mats, uint32_t grid, hipStream_t s) {
@@ -705,12 +970,16 @@ hipError_t launch_fill(double *p, uint64_t count, double v, hipStream_t s) {
 }
 
 hipError_t sweep_kernel_setup() {
-    const void *ks[6] = {reinterpret_cast<const void *>(k_sweep<double2>),
+    const void *ks[10] = {reinterpret_cast<const void *>(k_sweep<double2>),
                          reinterpret_cast<const void *>(k_sweep<float2>),
                          reinterpret_cast<const void *>(k_sweep_reg<double2, 4>),
                          reinterpret_cast<const void *>(k_sweep_reg<float2, 4>),
                          reinterpret_cast<const void *>(k_sweep_reg<double2, 3>),
-                         reinterpret_cast<const void *>(k_sweep_reg<float2, 3>)};
+                         reinterpret_cast<const void *>(k_sweep_reg<float2, 3>),
+                         reinterpret_cast<const void *>(k_sweep_pp<double2, 4>),
+                         reinterpret_cast<const void *>(k_sweep_pp<float2, 4>),
+                         reinterpret_cast<const void *>(k_sweep_pp<double2, 3>),
+                         reinterpret_cast<const void *>(k_sweep_pp<float2, 3>)};
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -726,6 +995,11 @@ template hipError_t launch_sweep_reg<double2>(double2 *, uint32_t, const SweepAr
                                               const Instr2 *, const double2 *, uint32_t, hipStream_t);
 template hipError_t launch_sweep_reg<float2>(float2 *, uint32_t, const SweepArgs &,
                                              const Instr2 *, const float2 *, uint32_t, hipStream_t);
+template hipError_t launch_sweep_pp<double2>(double2 *, uint32_t, const SweepArgs &,
+                                              const Instr2 *, const double2 *, uint32_t, uint32_t,
+                                              hipStream_t);
+template hipError_t launch_sweep_pp<float2>(float2 *, uint32_t, const SweepArgs &, const Instr2 *,
+                                             const float2 *, uint32_t, uint32_t, hipStream_t);
 template hipError_t launch_sweep_pipe<double2>(double2 *, uint32_t, const SweepArgs &,
                                                const Instr2 *, const double2 *, uint32_t, hipStream_t);
 template hipError_t launch_sweep_pipe<float2>(float2 *, uint32_t, const SweepArgs &, const Instr2 *,

@@ -43,6 +43,11 @@ hipError_t launch_sweep(V *psi, uint32_t n, const SweepArgs &a, const DOp *ops, 
 template <typename V>
 hipError_t launch_sweep_reg(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
                             const V *mats, uint32_t reg_qubits, hipStream_t s);
+// persistent ping-pong variant of launch_sweep_reg: min(tiles, resident
+// workgroups per CU x cus) workgroups; programs must have even length
+template <typename V>
+hipError_t launch_sweep_pp(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
+                           const V *mats, uint32_t reg_qubits, uint32_t cus, hipStream_t s);
 template <typename V>
 hipError_t launch_sweep_pipe(V *psi, uint32_t n, const SweepArgs &a, const Instr2 *prog,
                              const V *mats, uint32_t grid, hipStream_t s);

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == 1
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 2
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -194,15 +194,21 @@ def _run_programs_numpy(c, dump, progs, weights):
         cur = list(range(k - r, k))
         fb, fe, ib, ie = progs["ranges"][ident]
         b, e = (ib, ie) if kind == 2 else (fb, fe)
+        # program form the kernels rely on: even length (instructions run in
+        # pairs), register bits in range, 2-qubit ops with a > b
+        assert (e - b) % 2 == 0
         for w0, mat in progs["instr"][b:e]:
             typ, arg = int(w0) & 3, int(w0) >> 2
+            assert typ in (0, 1, 2)
             if typ == 0:
                 cur = [(arg >> (5 * i)) & 31 for i in range(r)]
-                assert cur == sorted(cur)
+                assert cur == sorted(cur) and cur[-1] < k
             elif typ == 1:
+                assert (arg & 7) < r
                 M = dump["mats"][mat: mat + 4]
                 psi = _apply_local(psi, n, q, (cur[arg & 7], 0xFF), M, False)
             else:
+                assert r > (arg & 7) > ((arg >> 3) & 7)
                 M = dump["mats"][mat: mat + 16]
                 psi = _apply_local(psi, n, q, (cur[arg & 7], cur[(arg >> 3) & 7]), M, False)
         assert cur == list(range(k - r, k))

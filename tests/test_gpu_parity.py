@@ -228,8 +228,8 @@ def test_autotuned_shape_is_valid_and_correct(ctx):
     tuned = tq.tusq_autotune(ctx, ec, t, o, 2)
     shape = (tuned.fusion_max_qubits, tuned.fusion_low_qubits, tuned.fusion_max_ops,
              tuned.sweep_kernel)
-    assert shape in {(12, 4, 16, 1), (12, 4, 24, 1), (11, 5, 12, 1), (11, 4, 16, 3),
-                     (11, 5, 12, 3), (11, 4, 24, 3)}
+    assert shape in {(12, 4, 16, 1), (12, 4, 24, 1), (12, 4, 16, 4), (12, 4, 24, 4),
+                     (13, 4, 24, 4), (11, 4, 16, 5)}
     again = tq.tusq_autotune(ctx, ec, t, o, 2)   # cached
     assert again.fusion_max_ops == tuned.fusion_max_ops
     r = tq.tusq_run_tree(ctx, ec, t, tuned)
@@ -250,3 +250,42 @@ def test_eight_amplitude_sweep_matches_oracle(ctx, precision):
                          drift_bound=1.0)
     tol = TOL_C128 if precision == "c128" else TOL_C64
     np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("n,kmax,low,pair", [(14, 10, 4, (4, 1)), (17, 12, 4, (4, 1)),
+                                              (15, 11, 4, (5, 3)), (17, 13, 4, (4, None))])
+def test_persistent_sweep_matches_oracle(ctx, precision, n, kmax, low, pair):
+    """Persistent register-prefetching sweep (16 or 8 amplitudes per thread)
+    against the oracle, and bit for bit against the one-tile-per-workgroup
+    kernel running the same programs."""
+    _say(f"[gpu] persistent sweep {precision} n={n} k={kmax} kernels={pair}")
+    c = brickwork(n, 8, 1e-3, 1e-2, 41 + n)
+    S, seed = 4000, 19
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    kw = dict(fusion_max_qubits=kmax, fusion_low_qubits=low, fusion_max_ops=16,
+              precision=precision, drift_bound=1.0)
+    _, _, _, rp = _engine(ctx, c, S, seed, sweep_kernel=pair[0], **kw)
+    tol = TOL_C128 if precision == "c128" else TOL_C64
+    np.testing.assert_allclose(rp.distribution(), dist, atol=tol, rtol=0)
+    if pair[1] is not None:   # (512-thread tiles exist in the persistent kernel only)
+        _, _, _, rr = _engine(ctx, c, S, seed, sweep_kernel=pair[1], **kw)
+        assert rp.distribution().tobytes() == rr.distribution().tobytes()
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_persistent_sweep_several_tiles_per_workgroup(ctx, precision):
+    """2^22 amplitudes in 2^12-amplitude tiles: more tiles than resident
+    workgroups, so every workgroup walks several tiles and prefetches."""
+    _say(f"[gpu] persistent sweep n=22 {precision}")
+    c = brickwork(22, 4, 1e-3, 1e-2, 77)
+    S, seed = 300, 23
+    kw = dict(fusion_max_qubits=12, fusion_low_qubits=4, fusion_max_ops=16,
+              precision=precision, drift_bound=1.0, want=3)
+    _, _, _, rp = _engine(ctx, c, S, seed, sweep_kernel=4, **kw)
+    _, _, _, rr = _engine(ctx, c, S, seed, sweep_kernel=1, **kw)
+    assert rp.distribution().tobytes() == rr.distribution().tobytes()
+    assert rp.samples().tobytes() == rr.samples().tobytes()
+    tol = 1e-12 if precision == "c128" else 1e-5
+    assert abs(rp.distribution().sum() - 1.0) < tol
