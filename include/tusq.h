@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 2u
+#define TUSQ_ABI_VERSION 3u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -198,13 +198,20 @@ int tusq_plan_dump(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o
                    uint64_t *op_range, uint64_t *n_ops, uint32_t *ops, uint64_t *n_mats,
                    double *mats);
 
-/* Dump the register-blocked programs of a plan's sweeps: instr holds 2 u32
- * per instruction (w0 = type | arg << 2 with type 0 = re-layout to the
- * register qubits packed 5 bits each in arg, 1 = 2x2 op on register bit
- * arg & 7, 2 = 4x4 op on register bits arg & 7 (high) and (arg >> 3) & 7;
- * then the matrix offset in complex numbers); ranges holds 4 u32 per sweep
- * (forward begin, end, undo begin, end).  *reg_qubits receives R.  Arrays
- * may be NULL to query sizes.                                              */
+/* Dump the register-blocked programs of a plan's sweeps.  A layout of a
+ * tile is a register word (bits 5i.. = local position of register bit i)
+ * and a thread word (bits 4b.. = local position of thread-index bit b, or
+ * 0xFFFFFFFF: the positions outside the register set, ascending).  instr
+ * holds 2 u32 per instruction, (w0 = type | arg << 2, m):
+ *   type 0  re-layout into (register word arg, thread word m);
+ *   type 1  2x2 op on register bit arg & 7, matrix offset m (complex);
+ *   type 2  4x4 op on register bits arg & 7 (high bit of the 4x4 index)
+ *           and (arg >> 3) & 7, matrix offset m;
+ *   type 3  swap register bit arg & 7 with thread bit 4 + ((arg >> 3) & 1).
+ * ranges holds 12 u32 per sweep: forward begin, end, undo begin, end, then
+ * the forward program's start layout (2 words) and end layout (2 words),
+ * then the same for the undo program.  *reg_qubits receives R.  Arrays may
+ * be NULL to query sizes.                                                  */
 int tusq_plan_dump_programs(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *opts,
                             uint64_t *n_instr, uint32_t *instr, uint64_t *n_passes,
                             uint32_t *ranges, uint32_t *reg_qubits);

@@ -110,7 +110,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 2
+ABI_VERSION = 3
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")
@@ -242,7 +242,7 @@ def tusq_plan_dump_programs(circuit: Circuit, tree: Tree, opts: tusq_opts) -> di
     check(lib.tusq_plan_dump_programs(circuit.h, tree.h, C.byref(opts), C.byref(ni), None,
                                       C.byref(npas), None, C.byref(R)))
     instr = np.zeros((max(ni.value, 1), 2), np.uint32)
-    ranges = np.zeros((max(npas.value, 1), 4), np.uint32)
+    ranges = np.zeros((max(npas.value, 1), 12), np.uint32)
     check(lib.tusq_plan_dump_programs(circuit.h, tree.h, C.byref(opts), C.byref(ni), _ptr(instr),
                                       C.byref(npas), _ptr(ranges), C.byref(R)))
     return {"instr": instr[: ni.value], "ranges": ranges[: npas.value], "reg_qubits": R.value}

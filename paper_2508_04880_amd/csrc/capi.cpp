@@ -267,10 +267,13 @@ int tusq_plan_dump_programs(const tusq_circuit *c, const tusq_tree *t, const tus
             }
         if (ranges)
             for (size_t i = 0; i < p.passes.size(); ++i) {
-                ranges[4 * i] = p.passes[i].fwd_begin;
-                ranges[4 * i + 1] = p.passes[i].fwd_end;
-                ranges[4 * i + 2] = p.passes[i].inv_begin;
-                ranges[4 * i + 3] = p.passes[i].inv_end;
+                uint32_t *r = ranges + 12 * i;
+                r[0] = p.passes[i].fwd_begin;
+                r[1] = p.passes[i].fwd_end;
+                r[2] = p.passes[i].inv_begin;
+                r[3] = p.passes[i].inv_end;
+                for (int d = 0; d < 2; ++d)
+                    for (int w = 0; w < 4; ++w) r[4 + 4 * d + w] = p.passes[i].lay[d][w];
             }
     });
 }

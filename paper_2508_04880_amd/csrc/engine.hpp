@@ -4,6 +4,7 @@
 #include <complex>
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "tusq.h"
@@ -104,20 +105,28 @@ struct Pass {
     uint32_t n_gates = 0, n_paulis = 0;  // tokens fused into it
     // register-blocked programs (forward and undo), see Instr
     uint32_t fwd_begin = 0, fwd_end = 0, inv_begin = 0, inv_end = 0;
+    // per direction: layouts the program starts (load) and ends (store) in,
+    // as (register word, thread word) pairs, see Instr
+    uint32_t lay[2][4] = {};
 };
 
 // One instruction of a register-blocked sweep program.  Each thread holds
 // 2^R amplitudes of its tile whose local index bits at the R "register
-// qubits" vary; the others come from the thread index.
-//   IN_RELAYOUT: move the tile through LDS so that the register qubits
-//                become the R local qubits packed in `arg` (5 bits each);
+// qubits" vary; the others come from the thread index.  A layout is a
+// register word (bits 5i.. of register bit i's local position) and a thread
+// word (bits 4b.. of thread-index bit b's local position, or THR_ASC: the
+// positions outside the register set in ascending order).
+//   IN_RELAYOUT: move the tile through LDS into the layout (arg, mat);
 //   IN_OP1:      2x2 matrix on register bit (arg & 7);
 //   IN_OP2:      4x4 matrix on register bits a = arg & 7 (high bit of the
-//                4x4 index) and b = (arg >> 3) & 7, with a > b.
-// Every program has even length (padded with a 2x2 identity).
-// mat is an offset (complex numbers) into the matrix pool; undo programs
-// reference the adjoint matrices, in reverse op order.
-enum : uint32_t { IN_RELAYOUT = 0, IN_OP1 = 1, IN_OP2 = 2 };
+//                4x4 index) and b = (arg >> 3) & 7, with a > b;
+//   IN_EXCH:     swap register bit r = arg & 7 with thread-index bit
+//                4 + ((arg >> 3) & 1) (a lane exchange inside the wavefront).
+// mat is an offset (complex numbers) into the matrix pool for ops; undo
+// programs reference the adjoint matrices, in reverse op order.  Every
+// program has even length (padded with a 2x2 identity).
+enum : uint32_t { IN_RELAYOUT = 0, IN_OP1 = 1, IN_OP2 = 2, IN_EXCH = 3 };
+constexpr uint32_t THR_ASC = 0xFFFFFFFFu;
 struct Instr {
     uint32_t w0;  // type | arg << 2
     uint32_t mat;
@@ -143,6 +152,8 @@ struct Plan {
     std::vector<Step> steps;
     std::vector<Instr> prog;
     uint32_t reg_qubits = 4;  // R of the register-blocked programs
+    bool general_layouts = false;  // programs for the persistent kernel (see build_programs)
+    std::unordered_map<uint32_t, uint32_t> swapped;  // 4x4 offset -> same op, qubits swapped
     uint32_t identity2 = UINT32_MAX;  // pool offset of the 2x2 identity (program padding)
     // per leaf in the range: the passes forming its path from the root, used
     // to recompute a leaf exactly (c64 drift control)

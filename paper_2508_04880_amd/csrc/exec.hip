@@ -81,6 +81,11 @@ SweepArgs sweep_args(const Pass &p, bool inverse) {
     a.fwd_end = p.fwd_end;
     a.inv_begin = p.inv_begin;
     a.inv_end = p.inv_end;
+    const uint32_t *lay = p.lay[inverse ? 1 : 0];
+    a.lay_in_reg = lay[0];
+    a.lay_in_thr = lay[1];
+    a.lay_out_reg = lay[2];
+    a.lay_out_thr = lay[3];
     for (uint32_t j = 0; j < p.k; ++j) a.q[j] = static_cast<uint8_t>(p.q[j]);
     return a;
 }

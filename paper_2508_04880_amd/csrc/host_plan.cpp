@@ -95,76 +95,261 @@ M2 pauli_matrix(uint8_t p) {
     return M2{1.0, 0.0, 0.0, -1.0};
 }
 
+// Register layout of a tile: register bit i holds local position reg[i],
+// thread-index bit b holds thr[b] (asc: the positions outside the register
+// set, ascending).
+struct Layout {
+    uint32_t R = 0, T = 0;
+    uint32_t reg[4] = {0, 0, 0, 0};
+    uint32_t thr[16] = {};
+    bool asc = true;
+    uint32_t set() const {
+        uint32_t m = 0;
+        for (uint32_t i = 0; i < R; ++i) m |= 1u << reg[i];
+        return m;
+    }
+    int reg_index(uint32_t pos) const {
+        for (uint32_t i = 0; i < R; ++i)
+            if (reg[i] == pos) return static_cast<int>(i);
+        return -1;
+    }
+    uint32_t reg_word() const {
+        uint32_t w = 0;
+        for (uint32_t i = 0; i < R; ++i) w |= reg[i] << (5 * i);
+        return w;
+    }
+    uint32_t thr_word() const {
+        if (asc) return THR_ASC;
+        uint32_t w = 0;
+        for (uint32_t b = 0; b < T; ++b) w |= thr[b] << (4 * b);
+        return w;
+    }
+};
+
+uint32_t op_mask(const Op &op) { return (1u << op.a) | (op.b == 0xFF ? 0u : 1u << op.b); }
+
+// Ops of `rem` (in order) that a register set covers, respecting the order
+// of ops on shared qubits; returns the rest.
+std::vector<uint32_t> uncovered(const Plan &plan, const std::vector<uint32_t> &rem, uint32_t set) {
+    std::vector<uint32_t> keep;
+    uint32_t blocked = 0;
+    for (uint32_t idx : rem) {
+        const uint32_t qm = op_mask(plan.ops[idx]);
+        if ((qm & blocked) || (qm & set) != qm) {
+            blocked |= qm;
+            keep.push_back(idx);
+        }
+    }
+    return keep;
+}
+
+// Next register set: the qubits of the next applicable ops (in order, while
+// R qubits suffice), topped up with `fill` positions (lowest first) and then
+// any others outside `avoid`.
+uint32_t greedy_set(const Plan &plan, const std::vector<uint32_t> &rem, uint32_t R, uint32_t k,
+                    uint32_t fill, uint32_t avoid) {
+    uint32_t nw = 0, blocked = 0;
+    for (uint32_t idx : rem) {
+        const uint32_t qm = op_mask(plan.ops[idx]);
+        if ((qm & blocked) || (qm & avoid)) { blocked |= qm; continue; }
+        if (static_cast<uint32_t>(__builtin_popcount(nw | qm)) <= R) nw |= qm;
+        else blocked |= qm;
+    }
+    for (uint32_t q = 0; q < k && static_cast<uint32_t>(__builtin_popcount(nw)) < R; ++q)
+        if ((fill >> q & 1u) && !(avoid >> q & 1u)) nw |= 1u << q;
+    for (uint32_t q = k; q-- > 0 && static_cast<uint32_t>(__builtin_popcount(nw)) < R;)
+        if (!(avoid >> q & 1u)) nw |= 1u << q;
+    return nw;
+}
+
 // Register-blocked programs of one sweep (see Instr): apply every op whose
 // qubits are register qubits, in dependency order; when none is left, pick
-// the next register set from the qubits of the next applicable ops and
-// re-layout through LDS; finally return to the initial layout (the top R
-// local qubits), which the kernel loads and stores coalesced.
+// the next register set from the qubits of the next applicable ops and move
+// there.
+//
+// For the persistent kernel (general layouts) a program starts and ends in
+// layouts of its own choosing whose thread bits 0 .. lowc-1 hold the local
+// positions 0 .. lowc-1 (the lowest global qubits, so loads and stores move
+// contiguous runs); a move whose new register qubits sit at thread bits 4
+// and 5 is a lane exchange inside the wavefront (no LDS), and every LDS
+// re-layout places the qubits the following move will need at those two
+// thread bits.  Otherwise (other kernels) programs start and end in the
+// initial layout (the top R local qubits) and every move is an LDS
+// re-layout to an ascending register set.
 void build_programs(Plan &plan, Pass &p) {
     const uint32_t k = p.k;
     const uint32_t R = std::min(plan.reg_qubits, k);
-    const uint32_t init = ((1u << R) - 1u) << (k - R);
-    auto bitpos = [](uint32_t set, uint32_t q) {
-        return static_cast<uint32_t>(__builtin_popcount(set & ((1u << q) - 1u)));
+    const uint32_t T = k - R;
+    uint32_t low = 0;
+    while (low < k && p.q[low] == low) ++low;
+    // positions kept at the lowest thread bits in load and store layouts
+    // (at most 4, and leaving R positions for the registers)
+    const uint32_t lowc = std::min<uint32_t>(std::min<uint32_t>(low, 4), T);
+    const uint32_t lowmask = (1u << lowc) - 1u;
+    const bool general = plan.general_layouts && T <= 8;
+    const bool exch_ok = general && T >= 6;
+
+    auto identity2 = [&]() {
+        if (plan.identity2 == UINT32_MAX) {
+            plan.identity2 = static_cast<uint32_t>(plan.mats.size());
+            plan.mats.insert(plan.mats.end(), {cd(1.0), cd(0.0), cd(0.0), cd(1.0)});
+        }
+        return plan.identity2;
     };
-    auto relayout = [&](uint32_t set) {
-        uint32_t arg = 0, i = 0;
+    // the op's matrix written for its two qubits in the other order
+    auto swapped = [&](uint32_t mat) {
+        auto it = plan.swapped.find(mat);
+        if (it != plan.swapped.end()) return it->second;
+        M4 m;
+        for (int i = 0; i < 16; ++i) m[i] = plan.mats[mat + i];
+        const M4 w = swap_halves(m);
+        const uint32_t off = static_cast<uint32_t>(plan.mats.size());
+        plan.mats.insert(plan.mats.end(), w.begin(), w.end());
+        plan.swapped.emplace(mat, off);
+        return off;
+    };
+    auto sorted_layout = [&](uint32_t set) {
+        Layout L;
+        L.R = R;
+        L.T = T;
+        uint32_t i = 0, b = 0;
+        for (uint32_t q = 0; q < k; ++q) {
+            if (set >> q & 1u) L.reg[i++] = q;
+            else L.thr[b++] = q;
+        }
+        L.asc = true;
+        return L;
+    };
+    // explicit layout with register set `set`: positions 0 .. lowc-1 stay at
+    // their thread bits, `hot` (up to two positions) go to thread bits 4 and
+    // 5, the rest fill the other thread bits in ascending order
+    auto make_layout = [&](uint32_t set, const std::vector<uint32_t> &hot) {
+        Layout L = sorted_layout(set);
+        L.asc = false;
+        bool used[16] = {};
+        bool placed[16] = {};
+        for (uint32_t q = 0; q < lowc; ++q)
+            if (!(set >> q & 1u)) { L.thr[q] = q; used[q] = placed[q] = true; }
+        uint32_t slot = 4;
+        for (uint32_t q : hot)
+            if (slot < 6 && slot < T && !(set >> q & 1u) && !placed[q]) {
+                L.thr[slot] = q;
+                used[slot] = placed[q] = true;
+                ++slot;
+            }
+        uint32_t b = 0;
+        for (uint32_t q = 0; q < k; ++q) {
+            if ((set >> q & 1u) || placed[q]) continue;
+            while (used[b]) ++b;
+            L.thr[b] = q;
+            used[b] = placed[q] = true;
+        }
+        return L;
+    };
+    // positions the move after reaching `set` will bring into registers
+    auto lookahead = [&](const std::vector<uint32_t> &rem, uint32_t set) {
+        std::vector<uint32_t> hot;
+        const std::vector<uint32_t> rest = uncovered(plan, rem, set);
+        if (rest.empty()) return hot;
+        const uint32_t nx = greedy_set(plan, rest, R, k, set, 0);
         for (uint32_t q = 0; q < k; ++q)
-            if (set >> q & 1u) arg |= q << (5 * i++);
-        plan.prog.push_back(Instr{IN_RELAYOUT | (arg << 2), 0});
+            if ((nx >> q & 1u) && !(set >> q & 1u)) hot.push_back(q);
+        return hot;
     };
+    auto emit_relayout = [&](const Layout &L) {
+        plan.prog.push_back(Instr{IN_RELAYOUT | (L.reg_word() << 2), L.thr_word()});
+    };
+
     for (int pass_dir = 0; pass_dir < 2; ++pass_dir) {
         const bool inverse = pass_dir == 1;
         std::vector<uint32_t> rem;
         for (uint32_t i = p.op_begin; i < p.op_end; ++i) rem.push_back(i);
         if (inverse) std::reverse(rem.begin(), rem.end());
         const uint32_t begin = static_cast<uint32_t>(plan.prog.size());
-        uint32_t cur = init;
+        const uint32_t init_set = ((1u << R) - 1u) << (k - R);
+        Layout cur;
+        if (general) {
+            // start: registers from the first ops that avoid the coalesced positions
+            const uint32_t s0 = greedy_set(plan, rem, R, k, init_set, lowmask);
+            cur = make_layout(s0, exch_ok ? lookahead(rem, s0) : std::vector<uint32_t>{});
+        } else {
+            cur = sorted_layout(init_set);
+        }
+        const Layout start = cur;
         while (!rem.empty()) {
+            // apply what the registers cover
+            const uint32_t set = cur.set();
             uint32_t blocked = 0;
             std::vector<uint32_t> keep;
             for (uint32_t idx : rem) {
                 const Op &op = plan.ops[idx];
-                const uint32_t qm = (1u << op.a) | (op.b == 0xFF ? 0u : 1u << op.b);
-                if ((qm & blocked) || (qm & cur) != qm) {
+                const uint32_t qm = op_mask(op);
+                if ((qm & blocked) || (qm & set) != qm) {
                     blocked |= qm;
                     keep.push_back(idx);
                     continue;
                 }
-                const uint32_t mat = inverse ? op.adj : op.mat;
-                if (op.b == 0xFF)
-                    plan.prog.push_back(Instr{IN_OP1 | (bitpos(cur, op.a) << 2), mat});
-                else
-                    plan.prog.push_back(
-                        Instr{IN_OP2 | ((bitpos(cur, op.a) | (bitpos(cur, op.b) << 3)) << 2), mat});
+                uint32_t mat = inverse ? op.adj : op.mat;
+                const uint32_t A = static_cast<uint32_t>(cur.reg_index(op.a));
+                if (op.b == 0xFF) {
+                    plan.prog.push_back(Instr{IN_OP1 | (A << 2), mat});
+                } else {
+                    uint32_t B = static_cast<uint32_t>(cur.reg_index(op.b));
+                    uint32_t hi = A, lo = B;
+                    if (A < B) { hi = B; lo = A; mat = swapped(mat); }
+                    plan.prog.push_back(Instr{IN_OP2 | ((hi | (lo << 3)) << 2), mat});
+                }
             }
             rem.swap(keep);
             if (rem.empty()) break;
-            uint32_t nw = 0;
-            blocked = 0;
-            for (uint32_t idx : rem) {
-                const Op &op = plan.ops[idx];
-                const uint32_t qm = (1u << op.a) | (op.b == 0xFF ? 0u : 1u << op.b);
-                if (qm & blocked) { blocked |= qm; continue; }
-                if (static_cast<uint32_t>(__builtin_popcount(nw | qm)) <= R) nw |= qm;
-                else blocked |= qm;
+            // move to the next register set
+            const uint32_t nw = greedy_set(plan, rem, R, k, set, 0);
+            uint32_t missing = nw & ~set;
+            bool by_exchange = exch_ok;
+            for (uint32_t q = 0; q < k && by_exchange; ++q)
+                if ((missing >> q & 1u) && cur.thr[4] != q && cur.thr[5] != q) by_exchange = false;
+            if (by_exchange) {
+                for (uint32_t q = 0; q < k; ++q) {
+                    if (!(missing >> q & 1u)) continue;
+                    const uint32_t h = cur.thr[4] == q ? 0u : 1u;
+                    uint32_t r = 0;
+                    while (nw >> cur.reg[r] & 1u) ++r;  // a register qubit the new set drops
+                    plan.prog.push_back(Instr{IN_EXCH | ((r | (h << 3)) << 2), 0});
+                    std::swap(cur.reg[r], cur.thr[4 + h]);
+                }
+            } else {
+                cur = general ? make_layout(nw, exch_ok ? lookahead(rem, nw) : std::vector<uint32_t>{})
+                              : sorted_layout(nw);
+                emit_relayout(cur);
             }
-            for (uint32_t q = 0; q < k && static_cast<uint32_t>(__builtin_popcount(nw)) < R; ++q)
-                if (cur >> q & 1u) nw |= 1u << q;
-            relayout(nw);
-            cur = nw;
         }
-        if (cur != init) relayout(init);
+        // end: a layout the store moves coalesced
+        bool ok_end = true;
+        if (general) {
+            for (uint32_t b = 0; b < lowc; ++b) ok_end = ok_end && cur.thr[b] == b;
+        } else {
+            ok_end = cur.set() == init_set;
+        }
+        if (!ok_end) {
+            if (general) {
+                uint32_t keepset = cur.set() & ~lowmask;
+                for (uint32_t q = k; q-- > lowc && static_cast<uint32_t>(__builtin_popcount(keepset)) < R;)
+                    keepset |= 1u << q;
+                cur = make_layout(keepset, {});
+            } else {
+                cur = sorted_layout(init_set);
+            }
+            emit_relayout(cur);
+        }
         // even length (the ping-pong kernel runs instructions in pairs):
         // pad with the identity on register bit 0
-        if ((plan.prog.size() - begin) & 1u) {
-            if (plan.identity2 == UINT32_MAX) {
-                plan.identity2 = static_cast<uint32_t>(plan.mats.size());
-                plan.mats.insert(plan.mats.end(), {cd(1.0), cd(0.0), cd(0.0), cd(1.0)});
-            }
-            plan.prog.push_back(Instr{IN_OP1, plan.identity2});
-        }
+        if ((plan.prog.size() - begin) & 1u) plan.prog.push_back(Instr{IN_OP1, identity2()});
         const uint32_t end = static_cast<uint32_t>(plan.prog.size());
+        uint32_t *lay = p.lay[pass_dir];
+        lay[0] = start.reg_word();
+        lay[1] = start.thr_word();
+        lay[2] = cur.reg_word();
+        lay[3] = cur.thr_word();
         if (inverse) { p.inv_begin = begin; p.inv_end = end; }
         else { p.fwd_begin = begin; p.fwd_end = end; }
     }
@@ -325,6 +510,7 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     // register qubits per thread: 4 (16 amplitudes) unless an 8-amplitude
     // variant is asked for
     plan.reg_qubits = (o.sweep_kernel == 3 || o.sweep_kernel == 5) ? 3 : 4;
+    plan.general_layouts = o.sweep_kernel == 0 || o.sweep_kernel == 4 || o.sweep_kernel == 5;
     const uint32_t G = t.G;
     uint64_t lb = o.leaf_begin, le = o.leaf_end;
     if (lb == 0 && le == 0) le = t.leaves();

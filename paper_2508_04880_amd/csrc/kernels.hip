@@ -389,25 +389,78 @@ __global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArg
 // workgroups of up to 2^PP_TBITS threads
 constexpr int PP_TBITS = 9;
 
-// LDS byte offset of this thread's part of a layout (register set `packed`):
-// thread-index bit b sits at the b-th local position outside the set.  The
-// positions are walked in a static loop with a wave-uniform bit counter, so
-// each free position costs one bit-field extract and one AND-XOR.
+// thread word of a layout whose thread-index bits take the positions outside
+// the register set in ascending order
+constexpr uint32_t PP_THR_ASC = 0xFFFFFFFFu;
+
+// LDS byte offset of this thread's part of a layout: the XOR over set
+// thread-index bits b of the swizzled column of the local position that bit
+// b holds (explicit thread word: 4 bits per thread bit; ascending: the
+// positions outside the register set, walked with a wave-uniform counter).
 template <typename V, int R>
-__device__ __forceinline__ uint32_t lds_thread_part(uint32_t tid, uint32_t k, uint32_t packed) {
-    uint32_t set = 0;
+__device__ __forceinline__ uint32_t lds_thread_part(uint32_t tid, uint32_t k, uint32_t reg,
+                                                    uint32_t thr) {
+    uint32_t pd = 0;
+    if (thr != PP_THR_ASC) {
 #pragma unroll
-    for (int i = 0; i < R; ++i) set |= 1u << ((packed >> (5 * i)) & 31u);
-    uint32_t pd = 0, b = 0;
+        for (uint32_t b = 0; b < 8; ++b) {
+            if (b + R < k) {
+                const uint32_t p = (thr >> (4 * b)) & 15u;
+                pd ^= (0u - ((tid >> b) & 1u)) &
+                      (Swz<V>::phys(1u << p) * static_cast<uint32_t>(sizeof(V)));
+            }
+        }
+    } else {
+        uint32_t set = 0;
 #pragma unroll
-    for (uint32_t p = 0; p < 16; ++p) {
-        if (p < k && !((set >> p) & 1u)) {
-            const uint32_t sel = 0u - ((tid >> b) & 1u);
-            pd ^= sel & (Swz<V>::phys(1u << p) * static_cast<uint32_t>(sizeof(V)));
-            ++b;
+        for (int i = 0; i < R; ++i) set |= 1u << ((reg >> (5 * i)) & 31u);
+        uint32_t b = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < 16; ++p) {
+            if (p < k && !((set >> p) & 1u)) {
+                pd ^= (0u - ((tid >> b) & 1u)) &
+                      (Swz<V>::phys(1u << p) * static_cast<uint32_t>(sizeof(V)));
+                ++b;
+            }
         }
     }
     return pd;
+}
+
+// Global element offset of this thread's part of a layout (the thread-index
+// bits placed at the tile qubits their local positions name).
+template <int R>
+__device__ __forceinline__ uint64_t layout_thread_offset(uint32_t tid, const QMap &qm, uint32_t k,
+                                                         uint32_t reg, uint32_t thr) {
+    uint64_t off = 0;
+    if (thr != PP_THR_ASC) {
+#pragma unroll
+        for (uint32_t b = 0; b < 8; ++b)
+            if (b + R < k)
+                off |= static_cast<uint64_t>((tid >> b) & 1u) << qat(qm, (thr >> (4 * b)) & 15u);
+    } else {
+        uint32_t set = 0;
+#pragma unroll
+        for (int i = 0; i < R; ++i) set |= 1u << ((reg >> (5 * i)) & 31u);
+        uint32_t b = 0;
+#pragma unroll
+        for (uint32_t p = 0; p < 16; ++p) {
+            if (p < k && !((set >> p) & 1u)) {
+                off |= static_cast<uint64_t>((tid >> b) & 1u) << qm.q[p];
+                ++b;
+            }
+        }
+    }
+    return off;
+}
+
+// the register qubits of a layout as global qubit indices, one byte each
+template <int R>
+__device__ __forceinline__ uint32_t layout_reg_qubits(const QMap &qm, uint32_t reg) {
+    uint32_t rq = 0;
+#pragma unroll
+    for (int i = 0; i < R; ++i) rq |= qat(qm, (reg >> (5 * i)) & 31u) << (8 * i);
+    return rq;
 }
 
 // LDS byte offsets of the register parts of a layout (wave-uniform).
@@ -456,37 +509,71 @@ __device__ __forceinline__ void pp_op2(const V (&x)[1 << R], V (&y)[1 << R],
     }
 }
 
+// Swap register bit B with lane bit 4 (HI = false: 16-lane rows) or 5
+// (HI = true: 32-lane halves): for each pair (x[j], x[j | 1 << B]) the odd
+// rows / upper half of the first trade places with the even rows / lower
+// half of the second.
+template <typename V, int R, int B, bool HI>
+__device__ __forceinline__ void pp_exch(const V (&x)[1 << R], V (&y)[1 << R]) {
+    constexpr int W = sizeof(V) / 4;
+    struct Words {
+        uint32_t w[W];
+    };
+#pragma unroll
+    for (int j = 0; j < (1 << R); ++j) {
+        if (j & (1 << B)) continue;
+        const Words a = __builtin_bit_cast(Words, x[j]);
+        const Words b = __builtin_bit_cast(Words, x[j | (1 << B)]);
+        Words na, nb;
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            if constexpr (HI) {
+                const auto r = __builtin_amdgcn_permlane32_swap(a.w[i], b.w[i], false, false);
+                na.w[i] = r[0];
+                nb.w[i] = r[1];
+            } else {
+                const auto r = __builtin_amdgcn_permlane16_swap(a.w[i], b.w[i], false, false);
+                na.w[i] = r[0];
+                nb.w[i] = r[1];
+            }
+        }
+        y[j] = __builtin_bit_cast(V, na);
+        y[j | (1 << B)] = __builtin_bit_cast(V, nb);
+    }
+}
+
 template <typename V, int R>
 __device__ __forceinline__ void pp_copy(const V (&x)[1 << R], V (&y)[1 << R]) {
 #pragma unroll
     for (int j = 0; j < (1 << R); ++j) y[j] = x[j];
 }
 
-// One program instruction from x into y.  `cur` is the current layout,
+// One program instruction from x into y.  (reg, thr) is the current layout,
 // `dirty` whether another wave may still read the LDS scratch.  Programs
 // hold valid instructions only (relayout, 1-qubit op on a register bit,
-// 2-qubit op on register bits a > b); there is no copy case, whose moves the
-// compiler would hoist in front of the dispatch.
+// 2-qubit op on register bits a > b, lane exchange); there is no copy case,
+// whose moves the compiler would hoist in front of the dispatch.
 template <typename V, int R>
 __device__ __forceinline__ void pp_step(const V (&x)[1 << R], V (&y)[1 << R], Instr2 ins,
                                         const V *__restrict__ mats, unsigned char *lds,
-                                        uint32_t tid, uint32_t k, uint32_t &cur,
+                                        uint32_t tid, uint32_t k, uint32_t &reg, uint32_t &thr,
                                         bool &dirty) {
     const uint32_t type = ins.w0 & 3u, arg = ins.w0 >> 2;
-    if (type == 0u) {  // relayout
+    if (type == 0u) {  // relayout into (arg, ins.mat)
         uint32_t pr[1 << R];
         if (dirty) lds_barrier();
-        uint32_t pd = lds_thread_part<V, R>(tid, k, cur);
-        lds_reg_part<V, R>(cur, pr);
+        uint32_t pd = lds_thread_part<V, R>(tid, k, reg, thr);
+        lds_reg_part<V, R>(reg, pr);
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) *reinterpret_cast<V *>(lds + (pd ^ pr[j])) = x[j];
         lds_barrier();
-        pd = lds_thread_part<V, R>(tid, k, arg);
+        pd = lds_thread_part<V, R>(tid, k, arg, ins.mat);
         lds_reg_part<V, R>(arg, pr);
 #pragma unroll
         for (int j = 0; j < (1 << R); ++j) y[j] = *reinterpret_cast<const V *>(lds + (pd ^ pr[j]));
         dirty = true;
-        cur = arg;
+        reg = arg;
+        thr = ins.mat;
     } else if (type == 1u) {
         const V *m = mats + ins.mat;
         switch (arg & 7u) {
@@ -496,7 +583,7 @@ __device__ __forceinline__ void pp_step(const V (&x)[1 << R], V (&y)[1 << R], In
         case 3: if constexpr (R > 3) { pp_op1<V, R, 3>(x, y, m); break; } [[fallthrough]];
         default: __builtin_unreachable();
         }
-    } else {
+    } else if (type == 2u) {
         const V *m = mats + ins.mat;
         switch (arg & 63u) {
         case 1 | (0 << 3): pp_op2<V, R, 1, 0>(x, y, m); break;
@@ -507,6 +594,23 @@ __device__ __forceinline__ void pp_step(const V (&x)[1 << R], V (&y)[1 << R], In
         case 3 | (2 << 3): if constexpr (R > 3) { pp_op2<V, R, 3, 2>(x, y, m); break; } [[fallthrough]];
         default: __builtin_unreachable();
         }
+    } else {  // lane exchange of register bit r with thread bit 4 + h
+        const uint32_t r = arg & 7u, h = (arg >> 3) & 1u;
+        switch (r | (h << 3)) {
+        case 0: pp_exch<V, R, 0, false>(x, y); break;
+        case 1: pp_exch<V, R, 1, false>(x, y); break;
+        case 2: pp_exch<V, R, 2, false>(x, y); break;
+        case 8: pp_exch<V, R, 0, true>(x, y); break;
+        case 9: pp_exch<V, R, 1, true>(x, y); break;
+        case 10: pp_exch<V, R, 2, true>(x, y); break;
+        case 3: if constexpr (R > 3) { pp_exch<V, R, 3, false>(x, y); break; } [[fallthrough]];
+        case 11: if constexpr (R > 3) { pp_exch<V, R, 3, true>(x, y); break; } [[fallthrough]];
+        default: __builtin_unreachable();
+        }
+        const uint32_t ts = 4u * (4u + h), rs = 5u * r;
+        const uint32_t rp = (reg >> rs) & 31u, tp = (thr >> ts) & 15u;
+        reg = (reg & ~(31u << rs)) | (tp << rs);
+        thr = (thr & ~(15u << ts)) | (rp << ts);
     }
 }
 
@@ -518,28 +622,27 @@ __global__ void __launch_bounds__(1 << PP_TBITS) k_sweep_pp(V *__restrict__ psi,
     extern __shared__ unsigned char smem_raw[];
     const uint32_t k = a.k;
     const uint32_t tid = threadIdx.x;
-    uint32_t init = 0;
-#pragma unroll
-    for (int i = 0; i < R; ++i) init |= (k - R + i) << (5 * i);
     const uint32_t ib = a.inverse ? a.inv_begin : a.fwd_begin;
     const uint32_t ie = a.inverse ? a.inv_end : a.fwd_end;
     uint32_t t = blockIdx.x;
     if (t >= ntiles) return;
 
-    // Addresses.  The thread's amplitudes sit at pt[base | roff_j]: pt folds
-    // in the thread-index bits, roff_j the register bits (register qubit i
-    // is global qubit byte i of rq) and base the tile index spread over the
-    // qubits outside the tile (mask `out`).  Walking tiles t, t + G, ...
-    // advances base by a masked add: with the gaps filled with ones, carries
+    // Addresses.  In the program's start layout the thread's amplitudes sit
+    // at pin[base | roff_j] (pin folds in the thread-index bits, roff_j the
+    // register bits: register bit i is global qubit byte i of rin), in its end
+    // layout at pout[base | roff'_j] (rout).  base spreads the tile index over
+    // the qubits outside the tile (mask `out`); walking tiles t, t + G, ...
+    // advances it by a masked add: with the gaps filled with ones, carries
     // skip the tile qubits.
     uint64_t base, dG, out;
-    uint32_t rq = 0;
-    V *pt;
+    uint32_t rin, rout;
+    V *pin, *pout;
     {
         const QMap qm = qmap(a);
-        pt = psi + scatter(tid, qm, a.low, k);
-#pragma unroll
-        for (int i = 0; i < R; ++i) rq |= qat(qm, k - R + i) << (8 * i);
+        pin = psi + layout_thread_offset<R>(tid, qm, k, a.lay_in_reg, a.lay_in_thr);
+        pout = psi + layout_thread_offset<R>(tid, qm, k, a.lay_out_reg, a.lay_out_thr);
+        rin = layout_reg_qubits<R>(qm, a.lay_in_reg);
+        rout = layout_reg_qubits<R>(qm, a.lay_out_reg);
         uint64_t in = 0;
 #pragma unroll
         for (int j = 0; j < 16; ++j)
@@ -548,9 +651,9 @@ __global__ void __launch_bounds__(1 << PP_TBITS) k_sweep_pp(V *__restrict__ psi,
         base = tile_base(t, qm, k);
         dG = tile_base(gridDim.x, qm, k);
     }
-    // register offsets are rebuilt from rq where used (the empty asm keeps
-    // the compiler from hoisting all 2^R of them into scalar registers that
-    // would stay live across the program loop)
+    // register offsets are rebuilt from rin / rout where used (the empty asm
+    // keeps the compiler from hoisting all 2^R of them into scalar registers
+    // that would stay live across the program loop)
     auto off = [&](uint32_t q, int j) {
         uint64_t o = 0;
 #pragma unroll
@@ -560,10 +663,10 @@ __global__ void __launch_bounds__(1 << PP_TBITS) k_sweep_pp(V *__restrict__ psi,
     };
     V x[1 << R], y[1 << R], nx[1 << R];
     {
-        uint32_t q = rq;
+        uint32_t q = rin;
         asm volatile("" : "+s"(q));
 #pragma unroll
-        for (int j = 0; j < (1 << R); ++j) x[j] = pt[base | off(q, j)];
+        for (int j = 0; j < (1 << R); ++j) x[j] = pin[base | off(q, j)];
     }
     bool dirty = false;
     for (;;) {
@@ -575,22 +678,22 @@ __global__ void __launch_bounds__(1 << PP_TBITS) k_sweep_pp(V *__restrict__ psi,
         const uint32_t tn = t + gridDim.x;
         if (tn < ntiles) {  // in flight while this tile computes
             const uint64_t nbase = ((base | ~out) + dG) & out;
-            uint32_t q = rq;
+            uint32_t q = rin;
             asm volatile("" : "+s"(q));
 #pragma unroll
-            for (int j = 0; j < (1 << R); ++j) nx[j] = pt[nbase | off(q, j)];
+            for (int j = 0; j < (1 << R); ++j) nx[j] = pin[nbase | off(q, j)];
         }
-        uint32_t cur = init;
+        uint32_t reg = a.lay_in_reg, thr = a.lay_in_thr;
         for (uint32_t pc = ib; pc < ie; pc += 2) {
             const Instr2 i0 = prog[pc], i1 = prog[pc + 1];
-            pp_step<V, R>(x, y, i0, mats, smem_raw, tid, k, cur, dirty);
-            pp_step<V, R>(y, x, i1, mats, smem_raw, tid, k, cur, dirty);
+            pp_step<V, R>(x, y, i0, mats, smem_raw, tid, k, reg, thr, dirty);
+            pp_step<V, R>(y, x, i1, mats, smem_raw, tid, k, reg, thr, dirty);
         }
         {
-            uint32_t q = rq;
+            uint32_t q = rout;
             asm volatile("" : "+s"(q));
 #pragma unroll
-            for (int j = 0; j < (1 << R); ++j) pt[base | off(q, j)] = x[j];
+            for (int j = 0; j < (1 << R); ++j) pout[base | off(q, j)] = x[j];
         }
         if (tn >= ntiles) break;
         pp_copy<V, R>(nx, x);

@@ -34,6 +34,10 @@ struct SweepArgs {
     uint32_t op_begin;
     uint32_t inverse;   // apply the ops' adjoints in reverse order
     uint32_t fwd_begin, fwd_end, inv_begin, inv_end;  // register programs
+    // layouts (register word, thread word) the program of this direction
+    // starts in (load) and ends in (store); thread word ~0u = positions
+    // outside the register set in ascending order
+    uint32_t lay_in_reg, lay_in_thr, lay_out_reg, lay_out_thr;
     uint8_t q[16];      // tile qubits, ascending
 };
 

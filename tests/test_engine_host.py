@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 2
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 3
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -173,9 +173,24 @@ def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops):
     np.testing.assert_allclose(acc, dist, atol=1e-12)
 
 
+THR_ASC = 0xFFFFFFFF
+
+
+def _layout(k, r, reg_word, thr_word):
+    """(register positions, thread positions) of a layout's two words."""
+    reg = [(reg_word >> (5 * i)) & 31 for i in range(r)]
+    if thr_word == THR_ASC:
+        thr = [p for p in range(k) if p not in reg]
+    else:
+        thr = [(thr_word >> (4 * b)) & 15 for b in range(k - r)]
+    assert sorted(reg + thr) == list(range(k)), (reg, thr)
+    return reg, thr
+
+
 def _run_programs_numpy(c, dump, progs, weights):
-    """Replay the register-blocked programs: a re-layout only changes which
-    local qubits the register bits name; ops act on those qubits."""
+    """Replay the register-blocked programs: a re-layout or lane exchange
+    only changes which local qubits the register bits name; ops act on
+    those qubits.  Also checks the program form the kernels rely on."""
     n = c.n
     R = progs["reg_qubits"]
     psi = np.zeros(1 << n, complex)
@@ -191,48 +206,67 @@ def _run_programs_numpy(c, dump, progs, weights):
         q = dump["qubits"][ident]
         k = int((q != 0xFFFFFFFF).sum())
         r = min(R, k)
-        cur = list(range(k - r, k))
-        fb, fe, ib, ie = progs["ranges"][ident]
-        b, e = (ib, ie) if kind == 2 else (fb, fe)
-        # program form the kernels rely on: even length (instructions run in
-        # pairs), register bits in range, 2-qubit ops with a > b
-        assert (e - b) % 2 == 0
+        low = 0
+        while low < k and q[low] == low:
+            low += 1
+        rg = progs["ranges"][ident]
+        inv = kind == 2
+        b, e = (rg[2], rg[3]) if inv else (rg[0], rg[1])
+        lay = rg[8:12] if inv else rg[4:8]
+        reg, thr = _layout(k, r, int(lay[0]), int(lay[1]))
+        end_reg, end_thr = _layout(k, r, int(lay[2]), int(lay[3]))
+        # loads and stores move contiguous runs: the lowest local positions
+        # sit at the lowest thread bits
+        lowc = min(low, 4, k - r)
+        for lay_thr in (thr, end_thr):
+            assert lay_thr[:lowc] == list(range(lowc))
+        assert (e - b) % 2 == 0      # instructions run in pairs
         for w0, mat in progs["instr"][b:e]:
             typ, arg = int(w0) & 3, int(w0) >> 2
-            assert typ in (0, 1, 2)
             if typ == 0:
-                cur = [(arg >> (5 * i)) & 31 for i in range(r)]
-                assert cur == sorted(cur) and cur[-1] < k
+                reg, thr = _layout(k, r, arg, int(mat))
             elif typ == 1:
                 assert (arg & 7) < r
                 M = dump["mats"][mat: mat + 4]
-                psi = _apply_local(psi, n, q, (cur[arg & 7], 0xFF), M, False)
-            else:
+                psi = _apply_local(psi, n, q, (reg[arg & 7], 0xFF), M, False)
+            elif typ == 2:
                 assert r > (arg & 7) > ((arg >> 3) & 7)
                 M = dump["mats"][mat: mat + 16]
-                psi = _apply_local(psi, n, q, (cur[arg & 7], cur[(arg >> 3) & 7]), M, False)
-        assert cur == list(range(k - r, k))
+                psi = _apply_local(psi, n, q, (reg[arg & 7], reg[(arg >> 3) & 7]), M, False)
+            else:
+                # lane exchange: thread bits 4 and 5 are lane bits of full wavefronts
+                assert k - r >= 6
+                ri, h = arg & 7, (arg >> 3) & 1
+                assert ri < r
+                reg[ri], thr[4 + h] = thr[4 + h], reg[ri]
+        assert (reg, thr) == (end_reg, end_thr)
     return acc
 
 
+@pytest.mark.parametrize("kernel", [0, 1, 5])
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 @pytest.mark.parametrize("trav", ["dftt", "hybrid"])
-@pytest.mark.parametrize("kmax,low,maxops", [(6, 2, 4), (7, 3, 12), (16, 5, 12)])
-def test_register_programs_reproduce_oracle(precision, trav, kmax, low, maxops):
-    c = brickwork(8, 8, 0.02, 0.05, 12)
+@pytest.mark.parametrize("n,kmax,low,maxops", [(8, 6, 2, 4), (8, 7, 3, 12), (8, 16, 5, 12),
+                                               (12, 10, 4, 16), (13, 12, 4, 24)])
+def test_register_programs_reproduce_oracle(kernel, precision, trav, n, kmax, low, maxops):
+    c = brickwork(n, 6, 0.02, 0.05, 12)
     S = 3000
     ot = oracle.ecm(c, S, 4, prune=True, alpha=(1, 50), beta=20)
     dist, _, _, _ = oracle.run(c, ot, 4, traversal=trav, want_samples=False)
     ec = tq.Circuit(c)
     o = tq.tusq_opts_default(shots=S, seed=4, alpha=(1, 50), beta=20, traversal=trav,
                              precision=precision, fusion_max_qubits=kmax,
-                             fusion_low_qubits=low, fusion_max_ops=maxops)
+                             fusion_low_qubits=low, fusion_max_ops=maxops, sweep_kernel=kernel)
     et = tq.Tree(ec, o)
     dump = tq.tusq_plan_dump(ec, et, o)
     progs = tq.tusq_plan_dump_programs(ec, et, o)
-    assert progs["reg_qubits"] == 4
+    assert progs["reg_qubits"] == (3 if kernel in (3, 5) else 4)
     acc = _run_programs_numpy(c, dump, progs, ot.weights())
     np.testing.assert_allclose(acc, dist, atol=1e-12)
+    if kernel in (1, 2, 3):     # one-tile kernels: start and end in the top R qubits
+        assert all(int(r[5]) == 0xFFFFFFFF and int(r[9]) == 0xFFFFFFFF
+                   for r in progs["ranges"])
+        assert not any(int(w) & 3 == 3 for w, _ in progs["instr"])
 
 
 def test_fused_plan_ising_and_soup():

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import paper_2508_04880_amd as tq
+from conftest import same_bits
 from workloads import Circuit, brickwork, ising, random_small_circuit
 from workloads.circuits import depol1
 
@@ -182,8 +183,8 @@ def test_repeat_run_is_bitwise_identical(ctx):
     c = brickwork(12, 10, 2e-3, 2e-2, 4)
     a = _engine(ctx, c, 5000, 3, fusion_max_qubits=8)[3]
     b = _engine(ctx, c, 5000, 3, fusion_max_qubits=8)[3]
-    assert a.distribution().tobytes() == b.distribution().tobytes()
-    assert a.samples().tobytes() == b.samples().tobytes()
+    assert same_bits(a.distribution(), b.distribution())
+    assert same_bits(a.samples(), b.samples())
 
 
 def test_injected_failure_and_budget(ctx):
@@ -215,7 +216,7 @@ def test_pipelined_sweep_matches_oracle(ctx, precision, n, kmax, low):
     tol = TOL_C128 if precision == "c128" else TOL_C64
     np.testing.assert_allclose(rp.distribution(), dist, atol=tol, rtol=0)
     # same ops in the same order: both kernels agree bit for bit
-    assert rp.distribution().tobytes() == rr.distribution().tobytes()
+    assert same_bits(rp.distribution(), rr.distribution())
 
 
 def test_autotuned_shape_is_valid_and_correct(ctx):
@@ -256,9 +257,10 @@ def test_eight_amplitude_sweep_matches_oracle(ctx, precision):
 @pytest.mark.parametrize("n,kmax,low,pair", [(14, 10, 4, (4, 1)), (17, 12, 4, (4, 1)),
                                               (15, 11, 4, (5, 3)), (17, 13, 4, (4, None))])
 def test_persistent_sweep_matches_oracle(ctx, precision, n, kmax, low, pair):
-    """Persistent register-prefetching sweep (16 or 8 amplitudes per thread)
-    against the oracle, and bit for bit against the one-tile-per-workgroup
-    kernel running the same programs."""
+    """Persistent register-prefetching sweep (16 or 8 amplitudes per thread,
+    its own start/end layouts and lane exchanges) against the oracle and
+    against the one-tile-per-workgroup kernel (whose programs keep the
+    initial layout, so the two round differently)."""
     _say(f"[gpu] persistent sweep {precision} n={n} k={kmax} kernels={pair}")
     c = brickwork(n, 8, 1e-3, 1e-2, 41 + n)
     S, seed = 4000, 19
@@ -271,7 +273,8 @@ def test_persistent_sweep_matches_oracle(ctx, precision, n, kmax, low, pair):
     np.testing.assert_allclose(rp.distribution(), dist, atol=tol, rtol=0)
     if pair[1] is not None:   # (512-thread tiles exist in the persistent kernel only)
         _, _, _, rr = _engine(ctx, c, S, seed, sweep_kernel=pair[1], **kw)
-        assert rp.distribution().tobytes() == rr.distribution().tobytes()
+        np.testing.assert_allclose(rp.distribution(), rr.distribution(),
+                                   atol=1e-13 if precision == "c128" else 1e-5, rtol=0)
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
@@ -285,7 +288,13 @@ def test_persistent_sweep_several_tiles_per_workgroup(ctx, precision):
               precision=precision, drift_bound=1.0, want=3)
     _, _, _, rp = _engine(ctx, c, S, seed, sweep_kernel=4, **kw)
     _, _, _, rr = _engine(ctx, c, S, seed, sweep_kernel=1, **kw)
-    assert rp.distribution().tobytes() == rr.distribution().tobytes()
-    assert rp.samples().tobytes() == rr.samples().tobytes()
+    _, _, _, rq = _engine(ctx, c, S, seed, sweep_kernel=4, **kw)
+    assert same_bits(rp.distribution(), rq.distribution())   # deterministic
+    np.testing.assert_allclose(rp.distribution(), rr.distribution(),
+                               atol=1e-13 if precision == "c128" else 1e-5, rtol=0)
+    # a draw may only move where rounding moves a CDF boundary across it:
+    # rarely in complex128; in complex64 the CDF over 2^22 entries of ~2e-7
+    # carries ~1e-6 of rounding, a few entries' width
+    assert np.mean(rp.samples() == rr.samples()) > (0.99 if precision == "c128" else 0.9)
     tol = 1e-12 if precision == "c128" else 1e-5
     assert abs(rp.distribution().sum() - 1.0) < tol
