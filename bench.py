@@ -65,7 +65,8 @@ def _args():
     p.add_argument("--no-autotune", action="store_true")
     p.add_argument("--drift-bound", type=float, default=1e-5,
                    help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
-    p.add_argument("--batch-jobs", type=int, default=1024)
+    p.add_argument("--batch-jobs", type=int, default=4096)
+    p.add_argument("--batch-chunk", type=int, default=256)
     p.add_argument("--serve-count", type=int, default=60)
     p.add_argument("--serve-nmax", type=int, default=24)
     p.add_argument("--serve-load", type=float, default=0.7)
@@ -307,29 +308,48 @@ def bench_ising30(a, tq):
 
 
 def bench_batch(a, tq):
+    """Config-3 jobs through tusq_run_batch: each call plans its jobs on host
+    threads and runs all their trajectories in one persistent, graph-captured
+    launch.  Jobs go in calls of --batch-chunk (one launch each) so that the
+    run reports progress; the device time is the sum over launches."""
     from workloads import batch_job_params, batch_jobs
     params = batch_job_params(a.batch_jobs)
     circs = batch_jobs(params)
     ecs = [tq.Circuit(c) for c in circs]
     ctx = tq.Context(0)
-    out = {"metric": "batched noisy jobs: shots/sec in one persistent launch",
+    out = {"metric": "batched noisy jobs: shots/sec in persistent launches",
            "unit": "shots/s", "n_gpus": 1, "data": "synthetic",
            "config": {"workload": f"{a.batch_jobs} random-brickwork jobs, n~U{{10..16}}, "
                                   f"L~U{{10..60}}, p2~U[1e-3,2e-2], p1=p2/10, S=1e4, "
-                                  f"{a.traversal}"}}
+                                  f"{a.traversal}, {a.batch_chunk} jobs per launch"}}
     for prec in ("c128", "c64"):
-        o = tq.tusq_opts_default(shots=10_000, seed=100_000, precision=prec,
-                                 traversal=a.traversal, want=2)
-        t0 = time.perf_counter()
-        res = tq.tusq_run_batch(ctx, ecs, o)
-        wall = time.perf_counter() - t0
-        ct = res[0].counters()
-        shots = sum(len(r.samples()) for r in res)
-        out[prec] = {"wall_s": round(wall, 3), "device_s": round(ct["device_seconds"], 3),
-                     "host_ecm_s": round(ct["host_ecm_seconds"], 3),
-                     "host_plan_s": round(ct["host_plan_seconds"], 3),
-                     "shots_per_s_device": round(shots / ct["device_seconds"], 1),
-                     "shots_per_s_wall": round(shots / wall, 1)}
+        tot = {"wall": 0.0, "device": 0.0, "ecm": 0.0, "plan": 0.0, "shots": 0, "leaves": 0,
+               "passes": 0}
+        for c0 in range(0, len(ecs), a.batch_chunk):
+            chunk = ecs[c0:c0 + a.batch_chunk]
+            o = tq.tusq_opts_default(shots=10_000, seed=100_000, precision=prec,
+                                     traversal=a.traversal, want=2)
+            t0 = time.perf_counter()
+            res = tq.tusq_run_batch(ctx, chunk, o)
+            wall = time.perf_counter() - t0
+            ct = res[0].counters()
+            tot["wall"] += wall
+            tot["device"] += ct["device_seconds"]
+            tot["ecm"] += ct["host_ecm_seconds"]
+            tot["plan"] += ct["host_plan_seconds"]
+            tot["shots"] += sum(len(r.samples()) for r in res)
+            cts = [r.counters() for r in res]     # per job (times: the whole call)
+            tot["leaves"] += sum(int(c["leaves"]) for c in cts)
+            tot["passes"] += sum(int(c["passes_fwd"] + c["passes_inv"]) for c in cts)
+            _log(f"[bench] batch {prec} jobs [{c0},{c0 + len(chunk)}): wall {wall:.2f}s "
+                 f"device {ct['device_seconds']:.2f}s host ECM {ct['host_ecm_seconds']:.2f}s "
+                 f"plan {ct['host_plan_seconds']:.2f}s")
+        out[prec] = {"wall_s": round(tot["wall"], 3), "device_s": round(tot["device"], 3),
+                     "host_ecm_s": round(tot["ecm"], 3), "host_plan_s": round(tot["plan"], 3),
+                     "leaves": tot["leaves"], "sweeps": tot["passes"],
+                     "launches": -(-len(ecs) // a.batch_chunk),
+                     "shots_per_s_device": round(tot["shots"] / tot["device"], 1),
+                     "shots_per_s_wall": round(tot["shots"] / tot["wall"], 1)}
         _log(f"[bench] batch {prec}: {out[prec]}")
     out["value"] = out["c128"]["shots_per_s_device"]
     out["dtype"] = "c128"
@@ -369,11 +389,13 @@ def bench_serve(a, tq):
     th.join()
     lat, shots = [], 0
     first_sub, last_fin = None, None
-    for (rq, ec), j in zip(prepared, ids):
+    for i, ((rq, ec), j) in enumerate(zip(prepared, ids)):
         r = tq.tusq_wait(ctx, j, rq.n)
         shots += len(r.samples())
         sub, adm, fin = tq.tusq_job_times(ctx, j)
         lat.append(fin - sub)
+        _log(f"[bench] serve request {i}: n={rq.n} {rq.precision} S={rq.shots} "
+             f"latency {fin - sub:.3f}s")
         first_sub = sub if first_sub is None else min(first_sub, sub)
         last_fin = fin if last_fin is None else max(last_fin, fin)
     lat = np.array(lat)

@@ -135,7 +135,8 @@ typedef struct {
     uint64_t pass_events;               /* sweeps timed with events (profile)    */
     double pass_seconds;                /* their summed device time               */
     double host_ecm_seconds, host_plan_seconds, device_seconds;
-    double max_norm_drift;              /* max |norm - 1| over leaves (FP64)     */
+    double max_norm_drift;              /* max |norm - 1| over leaves (FP64);
+                                           complex64: before any recompute       */
 } tusq_counters;
 
 typedef struct {
@@ -207,7 +208,7 @@ int tusq_plan_dump(const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o
  *   type 1  2x2 op on register bit arg & 7, matrix offset m (complex);
  *   type 2  4x4 op on register bits arg & 7 (high bit of the 4x4 index)
  *           and (arg >> 3) & 7, matrix offset m;
- *   type 3  swap register bit arg & 7 with thread bit 4 + ((arg >> 3) & 1).
+ *   type 3  swap register bit arg & 7 with thread (lane) bit (arg >> 3) & 7.
  * ranges holds 12 u32 per sweep: forward begin, end, undo begin, end, then
  * the forward program's start layout (2 words) and end layout (2 words),
  * then the same for the undo program.  *reg_qubits receives R.  Arrays may

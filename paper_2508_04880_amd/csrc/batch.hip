@@ -327,6 +327,8 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
                     }
                 } catch (const Error &e) {
                     errs[t] = e.msg;
+                } catch (const std::exception &e) {
+                    errs[t] = e.what();
                 }
             });
         for (auto &x : th) x.join();
@@ -365,8 +367,7 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         for (uint64_t a = 0; a < L; a += per) ups.push_back(UnitPlan{j, a, std::min(L, a + per)});
         job_unit_off[j + 1] = ups.size();
     }
-    for (size_t ui = 0; ui < ups.size(); ++ui) {
-        const UnitPlan &up = ups[ui];
+    auto unit_opts = [&](const UnitPlan &up) {
         const Circuit &c = *circs[up.job];
         tusq_opts ou = o;
         ou.seed = o.seed + up.job;
@@ -375,7 +376,41 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         ou.fusion_max_qubits = c.n <= KL ? c.n : KT;
         ou.fusion_low_qubits = c.n <= KL ? 0 : 5;
         if (c.n > KL && o.fusion_max_ops) ou.fusion_max_ops = o.fusion_max_ops;
-        Plan p = build_plan(c, trees[up.job], ou, false);
+        return ou;
+    };
+    // units are planned on host threads a window at a time (op lists only)
+    // and appended in order, so the arrays do not depend on the thread count
+    const unsigned nt_plan = host_threads(o);
+    const size_t window = std::max<size_t>(4 * nt_plan, 1);
+    std::vector<Plan> win;
+    for (size_t ui = 0; ui < ups.size(); ++ui) {
+        if (ui % window == 0) {
+            const size_t w1 = std::min(ups.size(), ui + window);
+            win.clear();
+            win.resize(w1 - ui);
+            std::vector<std::thread> th;
+            std::atomic<size_t> next{ui};
+            std::vector<std::string> errs(nt_plan);
+            for (unsigned t = 0; t < nt_plan; ++t)
+                th.emplace_back([&, t, ui, w1] {
+                    try {
+                        for (size_t x; (x = next++) < w1;)
+                            win[x - ui] = build_plan(*circs[ups[x].job], trees[ups[x].job],
+                                                     unit_opts(ups[x]), false, false);
+                    } catch (const Error &e) {
+                        errs[t] = e.msg;
+                    } catch (const std::exception &e) {
+                        errs[t] = e.what();
+                    }
+                });
+            for (auto &x : th) x.join();
+            for (auto &e : errs)
+                if (!e.empty()) fail(TUSQ_EINVAL, e);
+        }
+        const UnitPlan &up = ups[ui];
+        const Circuit &c = *circs[up.job];
+        const tusq_opts ou = unit_opts(up);
+        Plan p = std::move(win[ui % window]);
         BUnit U{};
         U.job = static_cast<uint32_t>(up.job);
         U.n = c.n;

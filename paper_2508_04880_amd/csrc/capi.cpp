@@ -200,7 +200,7 @@ int tusq_plan_counters(const tusq_circuit *c, const tusq_tree *t, const tusq_opt
         cc->c.finalize();
         need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
         const double t0 = now_seconds();
-        Plan p = build_plan(cc->c, t->t, *o, false);
+        Plan p = build_plan(cc->c, t->t, *o, false, false);
         p.counters.host_plan_seconds = now_seconds() - t0;
         *out = p.counters;
     });
@@ -376,8 +376,8 @@ int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, cons
         // (tile qubits, low qubits, ops per sweep, kernel): kernel 1 = one tile
         // per workgroup, 4 = persistent with register prefetch (16 amplitudes
         // per thread), 5 = persistent with 8 per thread
-        static const uint32_t cand[][4] = {{12, 4, 16, 1}, {12, 4, 24, 1}, {12, 4, 16, 4},
-                                           {12, 4, 24, 4}, {13, 4, 24, 4}, {11, 4, 16, 5}};
+        static const uint32_t cand[][4] = {{12, 4, 24, 1}, {12, 4, 16, 4}, {12, 4, 24, 4},
+                                           {12, 4, 32, 4}, {11, 4, 24, 4}, {11, 4, 16, 5}};
         const uint64_t L = t->t.leaves();
         const uint64_t lb = std::min<uint64_t>(o->leaf_begin, L ? L - 1 : 0);
         const uint64_t le = std::min<uint64_t>(L, lb + std::max<uint32_t>(1, probe_leaves));

@@ -121,7 +121,7 @@ struct Pass {
 //   IN_OP2:      4x4 matrix on register bits a = arg & 7 (high bit of the
 //                4x4 index) and b = (arg >> 3) & 7, with a > b;
 //   IN_EXCH:     swap register bit r = arg & 7 with thread-index bit
-//                4 + ((arg >> 3) & 1) (a lane exchange inside the wavefront).
+//                h = (arg >> 3) & 7 < 6 (a lane exchange inside the wavefront).
 // mat is an offset (complex numbers) into the matrix pool for ops; undo
 // programs reference the adjoint matrices, in reverse op order.  Every
 // program has even length (padded with a 2x2 identity).
@@ -154,6 +154,9 @@ struct Plan {
     uint32_t reg_qubits = 4;  // R of the register-blocked programs
     bool general_layouts = false;  // programs for the persistent kernel (see build_programs)
     std::unordered_map<uint32_t, uint32_t> swapped;  // 4x4 offset -> same op, qubits swapped
+    // matrix pool entries by content (bitwise), so that repeated fused ops
+    // share one copy: hash -> offset of the matrix (its adjoint follows it)
+    std::unordered_multimap<uint64_t, std::pair<uint32_t, int>> mat_index;  // -> (offset, dim)
     uint32_t identity2 = UINT32_MAX;  // pool offset of the 2x2 identity (program padding)
     // per leaf in the range: the passes forming its path from the root, used
     // to recompute a leaf exactly (c64 drift control)
@@ -163,7 +166,10 @@ struct Plan {
 };
 
 FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o);
-Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths);
+// programs = false skips the register-blocked programs (callers that run the
+// op lists only, or count)
+Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths,
+                bool programs = true);
 
 double now_seconds();
 unsigned host_threads(const tusq_opts &o);

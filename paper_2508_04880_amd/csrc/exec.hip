@@ -223,6 +223,7 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
                 hip_check(hipMemcpyAsync(hnorm.data(), nrm, 8, hipMemcpyDeviceToHost, s), "norm readback");
                 hip_check(hipStreamSynchronize(s), "sync");
                 const double drift = std::fabs(hnorm[0] - 1.0);
+                ct.max_norm_drift = std::max(ct.max_norm_drift, drift);
                 const bool by_count = o.max_passes_between_recompute &&
                                       passes_since_exact > o.max_passes_between_recompute;
                 if (drift > o.drift_bound || by_count) {

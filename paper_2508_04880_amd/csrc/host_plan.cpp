@@ -128,32 +128,33 @@ struct Layout {
 
 uint32_t op_mask(const Op &op) { return (1u << op.a) | (op.b == 0xFF ? 0u : 1u << op.b); }
 
-// Ops of `rem` (in order) that a register set covers, respecting the order
-// of ops on shared qubits; returns the rest.
-std::vector<uint32_t> uncovered(const Plan &plan, const std::vector<uint32_t> &rem, uint32_t set) {
-    std::vector<uint32_t> keep;
-    uint32_t blocked = 0;
-    for (uint32_t idx : rem) {
-        const uint32_t qm = op_mask(plan.ops[idx]);
-        if ((qm & blocked) || (qm & set) != qm) {
-            blocked |= qm;
-            keep.push_back(idx);
-        }
+// The ops of one program still to emit, in order: `done` marks emitted
+// ones, `head` is the first not emitted.  Scans stop as soon as their answer
+// is fixed, so building a program stays close to linear in its ops.
+struct Pending {
+    std::vector<uint32_t> ops;  // op indices in program order
+    std::vector<uint8_t> done;
+    size_t head = 0;
+    bool empty() const { return head == ops.size(); }
+    void advance() {
+        while (head < ops.size() && done[head]) ++head;
     }
-    return keep;
-}
+};
 
 // Next register set: the qubits of the next applicable ops (in order, while
 // R qubits suffice), topped up with `fill` positions (lowest first) and then
 // any others outside `avoid`.
-uint32_t greedy_set(const Plan &plan, const std::vector<uint32_t> &rem, uint32_t R, uint32_t k,
-                    uint32_t fill, uint32_t avoid) {
+uint32_t greedy_set(const Plan &plan, const Pending &pd, uint32_t R, uint32_t k, uint32_t fill,
+                    uint32_t avoid) {
+    const uint32_t all = (1u << k) - 1u;
     uint32_t nw = 0, blocked = 0;
-    for (uint32_t idx : rem) {
-        const uint32_t qm = op_mask(plan.ops[idx]);
-        if ((qm & blocked) || (qm & avoid)) { blocked |= qm; continue; }
-        if (static_cast<uint32_t>(__builtin_popcount(nw | qm)) <= R) nw |= qm;
+    for (size_t i = pd.head; i < pd.ops.size(); ++i) {
+        if (pd.done[i]) continue;
+        const uint32_t qm = op_mask(plan.ops[pd.ops[i]]);
+        if ((qm & blocked) || (qm & avoid)) blocked |= qm;
+        else if (static_cast<uint32_t>(__builtin_popcount(nw | qm)) <= R) nw |= qm;
         else blocked |= qm;
+        if (static_cast<uint32_t>(__builtin_popcount(nw)) == R || ((blocked | avoid) & all) == all) break;
     }
     for (uint32_t q = 0; q < k && static_cast<uint32_t>(__builtin_popcount(nw)) < R; ++q)
         if ((fill >> q & 1u) && !(avoid >> q & 1u)) nw |= 1u << q;
@@ -170,10 +171,10 @@ uint32_t greedy_set(const Plan &plan, const std::vector<uint32_t> &rem, uint32_t
 // For the persistent kernel (general layouts) a program starts and ends in
 // layouts of its own choosing whose thread bits 0 .. lowc-1 hold the local
 // positions 0 .. lowc-1 (the lowest global qubits, so loads and stores move
-// contiguous runs); a move whose new register qubits sit at thread bits 4
-// and 5 is a lane exchange inside the wavefront (no LDS), and every LDS
-// re-layout places the qubits the following move will need at those two
-// thread bits.  Otherwise (other kernels) programs start and end in the
+// contiguous runs); a move whose new register qubits all sit on lane bits
+// (thread bits 0 .. 5) is a sequence of lane exchanges inside the wavefront
+// (no LDS), and every LDS re-layout puts the qubits needed last on the wave
+// bits (thread bits 6 and up).  Otherwise (other kernels) programs start and end in the
 // initial layout (the top R local qubits) and every move is an LDS
 // re-layout to an ascending register set.
 void build_programs(Plan &plan, Pass &p) {
@@ -221,22 +222,40 @@ void build_programs(Plan &plan, Pass &p) {
         return L;
     };
     // explicit layout with register set `set`: positions 0 .. lowc-1 stay at
-    // their thread bits, `hot` (up to two positions) go to thread bits 4 and
-    // 5, the rest fill the other thread bits in ascending order
-    auto make_layout = [&](uint32_t set, const std::vector<uint32_t> &hot) {
+    // their thread bits; the wave bits (thread bits 6 and up, which only an
+    // LDS re-layout can reach) take the positions the remaining ops `rem`
+    // need last; the other lane bits take the rest in ascending order
+    auto make_layout = [&](uint32_t set, const Pending *rem) {
         Layout L = sorted_layout(set);
         L.asc = false;
         bool used[16] = {};
         bool placed[16] = {};
         for (uint32_t q = 0; q < lowc; ++q)
             if (!(set >> q & 1u)) { L.thr[q] = q; used[q] = placed[q] = true; }
-        uint32_t slot = 4;
-        for (uint32_t q : hot)
-            if (slot < 6 && slot < T && !(set >> q & 1u) && !placed[q]) {
-                L.thr[slot] = q;
-                used[slot] = placed[q] = true;
-                ++slot;
+        if (T > 6) {
+            uint32_t first[16];
+            for (uint32_t q = 0; q < k; ++q) first[q] = UINT32_MAX;
+            if (rem) {
+                const uint32_t want = ((1u << k) - 1u) & ~set;
+                uint32_t seen = 0;
+                for (size_t i = rem->head; i < rem->ops.size() && (seen & want) != want; ++i) {
+                    if (rem->done[i]) continue;
+                    const Op &op = plan.ops[rem->ops[i]];
+                    if (first[op.a] == UINT32_MAX) first[op.a] = static_cast<uint32_t>(i);
+                    if (op.b != 0xFF && first[op.b] == UINT32_MAX) first[op.b] = static_cast<uint32_t>(i);
+                    seen |= op_mask(op);
+                }
             }
+            for (uint32_t b = 6; b < T; ++b) {
+                int pick = -1;
+                for (uint32_t q = 0; q < k; ++q) {
+                    if ((set >> q & 1u) || placed[q]) continue;
+                    if (pick < 0 || first[q] >= first[pick]) pick = static_cast<int>(q);
+                }
+                L.thr[b] = static_cast<uint32_t>(pick);
+                used[b] = placed[pick] = true;
+            }
+        }
         uint32_t b = 0;
         for (uint32_t q = 0; q < k; ++q) {
             if ((set >> q & 1u) || placed[q]) continue;
@@ -246,15 +265,15 @@ void build_programs(Plan &plan, Pass &p) {
         }
         return L;
     };
-    // positions the move after reaching `set` will bring into registers
-    auto lookahead = [&](const std::vector<uint32_t> &rem, uint32_t set) {
-        std::vector<uint32_t> hot;
-        const std::vector<uint32_t> rest = uncovered(plan, rem, set);
-        if (rest.empty()) return hot;
-        const uint32_t nx = greedy_set(plan, rest, R, k, set, 0);
-        for (uint32_t q = 0; q < k; ++q)
-            if ((nx >> q & 1u) && !(set >> q & 1u)) hot.push_back(q);
-        return hot;
+    // thread bit holding position q (-1: a register)
+    auto thread_bit = [&](const Layout &L, uint32_t q) {
+        for (uint32_t b = 0; b < T; ++b)
+            if (L.thr[b] == q) return static_cast<int>(b);
+        return -1;
+    };
+    auto exchange = [&](Layout &L, uint32_t r, uint32_t h) {
+        plan.prog.push_back(Instr{IN_EXCH | ((r | (h << 3)) << 2), 0});
+        std::swap(L.reg[r], L.thr[h]);
     };
     auto emit_relayout = [&](const Layout &L) {
         plan.prog.push_back(Instr{IN_RELAYOUT | (L.reg_word() << 2), L.thr_word()});
@@ -262,33 +281,36 @@ void build_programs(Plan &plan, Pass &p) {
 
     for (int pass_dir = 0; pass_dir < 2; ++pass_dir) {
         const bool inverse = pass_dir == 1;
-        std::vector<uint32_t> rem;
-        for (uint32_t i = p.op_begin; i < p.op_end; ++i) rem.push_back(i);
-        if (inverse) std::reverse(rem.begin(), rem.end());
+        Pending rem;
+        for (uint32_t i = p.op_begin; i < p.op_end; ++i) rem.ops.push_back(i);
+        if (inverse) std::reverse(rem.ops.begin(), rem.ops.end());
+        rem.done.assign(rem.ops.size(), 0);
         const uint32_t begin = static_cast<uint32_t>(plan.prog.size());
         const uint32_t init_set = ((1u << R) - 1u) << (k - R);
         Layout cur;
         if (general) {
             // start: registers from the first ops that avoid the coalesced positions
             const uint32_t s0 = greedy_set(plan, rem, R, k, init_set, lowmask);
-            cur = make_layout(s0, exch_ok ? lookahead(rem, s0) : std::vector<uint32_t>{});
+            cur = make_layout(s0, &rem);
         } else {
             cur = sorted_layout(init_set);
         }
         const Layout start = cur;
         while (!rem.empty()) {
-            // apply what the registers cover
+            // apply what the registers cover (no later op can once every
+            // register qubit is held by an op left behind)
             const uint32_t set = cur.set();
             uint32_t blocked = 0;
-            std::vector<uint32_t> keep;
-            for (uint32_t idx : rem) {
-                const Op &op = plan.ops[idx];
+            for (size_t i = rem.head; i < rem.ops.size(); ++i) {
+                if (rem.done[i]) continue;
+                const Op &op = plan.ops[rem.ops[i]];
                 const uint32_t qm = op_mask(op);
                 if ((qm & blocked) || (qm & set) != qm) {
                     blocked |= qm;
-                    keep.push_back(idx);
+                    if ((blocked & set) == set) break;
                     continue;
                 }
+                rem.done[i] = 1;
                 uint32_t mat = inverse ? op.adj : op.mat;
                 const uint32_t A = static_cast<uint32_t>(cur.reg_index(op.a));
                 if (op.b == 0xFF) {
@@ -300,30 +322,38 @@ void build_programs(Plan &plan, Pass &p) {
                     plan.prog.push_back(Instr{IN_OP2 | ((hi | (lo << 3)) << 2), mat});
                 }
             }
-            rem.swap(keep);
+            rem.advance();
             if (rem.empty()) break;
-            // move to the next register set
+            // move to the next register set: lane exchanges when every new
+            // register qubit sits on a lane bit, else an LDS re-layout
             const uint32_t nw = greedy_set(plan, rem, R, k, set, 0);
-            uint32_t missing = nw & ~set;
+            const uint32_t missing = nw & ~set;
             bool by_exchange = exch_ok;
             for (uint32_t q = 0; q < k && by_exchange; ++q)
-                if ((missing >> q & 1u) && cur.thr[4] != q && cur.thr[5] != q) by_exchange = false;
+                if ((missing >> q & 1u) && thread_bit(cur, q) >= 6) by_exchange = false;
             if (by_exchange) {
                 for (uint32_t q = 0; q < k; ++q) {
                     if (!(missing >> q & 1u)) continue;
-                    const uint32_t h = cur.thr[4] == q ? 0u : 1u;
                     uint32_t r = 0;
                     while (nw >> cur.reg[r] & 1u) ++r;  // a register qubit the new set drops
-                    plan.prog.push_back(Instr{IN_EXCH | ((r | (h << 3)) << 2), 0});
-                    std::swap(cur.reg[r], cur.thr[4 + h]);
+                    exchange(cur, r, static_cast<uint32_t>(thread_bit(cur, q)));
                 }
             } else {
-                cur = general ? make_layout(nw, exch_ok ? lookahead(rem, nw) : std::vector<uint32_t>{})
-                              : sorted_layout(nw);
+                cur = general ? make_layout(nw, &rem) : sorted_layout(nw);
                 emit_relayout(cur);
             }
         }
-        // end: a layout the store moves coalesced
+        // end: a layout the store moves coalesced (positions 0 .. lowc-1 on
+        // thread bits 0 .. lowc-1), by lane exchanges where they reach
+        if (general && exch_ok) {
+            for (uint32_t q = 0; q < lowc; ++q) {
+                if (cur.thr[q] == q) continue;
+                const int b = thread_bit(cur, q);
+                if (b >= 6) break;  // on a wave bit: LDS re-layout below
+                if (b >= 0) exchange(cur, 0, static_cast<uint32_t>(b));  // into register 0
+                exchange(cur, static_cast<uint32_t>(cur.reg_index(q)), q);
+            }
+        }
         bool ok_end = true;
         if (general) {
             for (uint32_t b = 0; b < lowc; ++b) ok_end = ok_end && cur.thr[b] == b;
@@ -335,7 +365,7 @@ void build_programs(Plan &plan, Pass &p) {
                 uint32_t keepset = cur.set() & ~lowmask;
                 for (uint32_t q = k; q-- > lowc && static_cast<uint32_t>(__builtin_popcount(keepset)) < R;)
                     keepset |= 1u << q;
-                cur = make_layout(keepset, {});
+                cur = make_layout(keepset, nullptr);
             } else {
                 cur = sorted_layout(init_set);
             }
@@ -367,6 +397,26 @@ struct Fuser {
     const Circuit &c;
     const FusionParams fp;
     Plan &plan;
+    bool programs;
+
+    // pool offset of a d x d matrix followed by its adjoint, shared with an
+    // earlier op of identical (bitwise) matrix
+    uint32_t pool(const cd *m, int d) {
+        const size_t nb = sizeof(cd) * d * d;
+        uint64_t h = 1469598103934665603ull;  // FNV-1a over the bytes
+        const unsigned char *b = reinterpret_cast<const unsigned char *>(m);
+        for (size_t i = 0; i < nb; ++i) h = (h ^ b[i]) * 1099511628211ull;
+        auto range = plan.mat_index.equal_range(h);
+        for (auto it = range.first; it != range.second; ++it)
+            if (it->second.second == d && std::memcmp(plan.mats.data() + it->second.first, m, nb) == 0)
+                return it->second.first;
+        const uint32_t off = static_cast<uint32_t>(plan.mats.size());
+        plan.mats.insert(plan.mats.end(), m, m + d * d);
+        for (int r = 0; r < d; ++r)
+            for (int cc = 0; cc < d; ++cc) plan.mats.push_back(std::conj(m[cc * d + r]));
+        plan.mat_index.emplace(h, std::make_pair(off, d));
+        return off;
+    }
 
     struct Item {
         uint32_t qa, qb;  // qubits
@@ -468,19 +518,15 @@ struct Fuser {
                     std::swap(op.a, op.b);
                     m4 = swap_halves(m4);
                 }
-                op.mat = static_cast<uint32_t>(plan.mats.size());
                 const int d = o.qb == NONE ? 2 : 4;
-                const cd *m = o.qb == NONE ? o.m2.data() : m4.data();
-                plan.mats.insert(plan.mats.end(), m, m + d * d);
-                op.adj = static_cast<uint32_t>(plan.mats.size());
-                for (int r = 0; r < d; ++r)
-                    for (int cc = 0; cc < d; ++cc) plan.mats.push_back(std::conj(m[cc * d + r]));
+                op.mat = pool(o.qb == NONE ? o.m2.data() : m4.data(), d);
+                op.adj = op.mat + static_cast<uint32_t>(d * d);
                 plan.ops.push_back(op);
             }
             p.op_end = static_cast<uint32_t>(plan.ops.size());
             p.n_gates = gates;
             p.n_paulis = paulis;
-            build_programs(plan, p);
+            if (programs) build_programs(plan, p);
             plan.passes.push_back(p);
         }
         return {first, static_cast<uint32_t>(plan.passes.size())};
@@ -504,7 +550,8 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
     return fp;
 }
 
-Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths) {
+Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths,
+                bool programs) {
     Plan plan;
     plan.n = c.n;
     // register qubits per thread: 4 (16 amplitudes) unless an 8-amplitude
@@ -556,7 +603,7 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     }
 
     // Pass 2: segments, fused sweeps and the step list.
-    Fuser fu{c, fp, plan};
+    Fuser fu{c, fp, plan, programs};
     struct Seg {
         uint32_t p0, p1;
         uint64_t start;

@@ -509,11 +509,39 @@ __device__ __forceinline__ void pp_op2(const V (&x)[1 << R], V (&y)[1 << R],
     }
 }
 
-// Swap register bit B with lane bit 4 (HI = false: 16-lane rows) or 5
-// (HI = true: 32-lane halves): for each pair (x[j], x[j | 1 << B]) the odd
-// rows / upper half of the first trade places with the even rows / lower
-// half of the second.
-template <typename V, int R, int B, bool HI>
+// Swap register bit B with lane bit H: for each pair a = x[j], b = x[j | 1 << B]
+// the lanes with bit H set take a's place in b and the others b's place in
+// a, i.e. element (lane L, bit B = c) moves to (lane L with bit H = c, bit
+// B = bit H of L).  Lane bits 4 and 5 use the row / half swaps
+// (permlane16/32_swap); lane bits 0 .. 3 fetch the partner lane with a
+// data-parallel move (quad permutation, or a rotation inside the 16-lane
+// row) and select by the lane's bit.
+template <int H>
+__device__ __forceinline__ void lane_exchange(uint32_t a, uint32_t b, uint32_t &na, uint32_t &nb) {
+    if constexpr (H == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        na = r[0];
+        nb = r[1];
+    } else if constexpr (H == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        na = r[0];
+        nb = r[1];
+    } else {
+        // partner of lane L is L ^ (1 << H): quad_perm [1,0,3,2] / [2,3,0,1],
+        // row rotations by 4 and 12 (bit 2 set / clear) and by 8
+        constexpr int up = H == 0 ? 0xB1 : H == 1 ? 0x4E : H == 2 ? 0x124 : 0x128;
+        constexpr int dn = H == 0 ? 0xB1 : H == 1 ? 0x4E : H == 2 ? 0x12C : 0x128;
+        const bool hi = (__lane_id() >> H) & 1u;
+        const uint32_t fb = static_cast<uint32_t>(
+            __builtin_amdgcn_mov_dpp(static_cast<int>(b), up, 0xF, 0xF, false));
+        const uint32_t fa = static_cast<uint32_t>(
+            __builtin_amdgcn_mov_dpp(static_cast<int>(a), dn, 0xF, 0xF, false));
+        na = hi ? fb : a;
+        nb = hi ? b : fa;
+    }
+}
+
+template <typename V, int R, int B, int H>
 __device__ __forceinline__ void pp_exch(const V (&x)[1 << R], V (&y)[1 << R]) {
     constexpr int W = sizeof(V) / 4;
     struct Words {
@@ -526,17 +554,7 @@ __device__ __forceinline__ void pp_exch(const V (&x)[1 << R], V (&y)[1 << R]) {
         const Words b = __builtin_bit_cast(Words, x[j | (1 << B)]);
         Words na, nb;
 #pragma unroll
-        for (int i = 0; i < W; ++i) {
-            if constexpr (HI) {
-                const auto r = __builtin_amdgcn_permlane32_swap(a.w[i], b.w[i], false, false);
-                na.w[i] = r[0];
-                nb.w[i] = r[1];
-            } else {
-                const auto r = __builtin_amdgcn_permlane16_swap(a.w[i], b.w[i], false, false);
-                na.w[i] = r[0];
-                nb.w[i] = r[1];
-            }
-        }
+        for (int i = 0; i < W; ++i) lane_exchange<H>(a.w[i], b.w[i], na.w[i], nb.w[i]);
         y[j] = __builtin_bit_cast(V, na);
         y[j | (1 << B)] = __builtin_bit_cast(V, nb);
     }
@@ -594,20 +612,19 @@ __device__ __forceinline__ void pp_step(const V (&x)[1 << R], V (&y)[1 << R], In
         case 3 | (2 << 3): if constexpr (R > 3) { pp_op2<V, R, 3, 2>(x, y, m); break; } [[fallthrough]];
         default: __builtin_unreachable();
         }
-    } else {  // lane exchange of register bit r with thread bit 4 + h
-        const uint32_t r = arg & 7u, h = (arg >> 3) & 1u;
+    } else {  // lane exchange of register bit r with thread (lane) bit h
+        const uint32_t r = arg & 7u, h = (arg >> 3) & 7u;
         switch (r | (h << 3)) {
-        case 0: pp_exch<V, R, 0, false>(x, y); break;
-        case 1: pp_exch<V, R, 1, false>(x, y); break;
-        case 2: pp_exch<V, R, 2, false>(x, y); break;
-        case 8: pp_exch<V, R, 0, true>(x, y); break;
-        case 9: pp_exch<V, R, 1, true>(x, y); break;
-        case 10: pp_exch<V, R, 2, true>(x, y); break;
-        case 3: if constexpr (R > 3) { pp_exch<V, R, 3, false>(x, y); break; } [[fallthrough]];
-        case 11: if constexpr (R > 3) { pp_exch<V, R, 3, true>(x, y); break; } [[fallthrough]];
+#define TUSQ_EXCH_CASE(B, H) \
+    case (B) | ((H) << 3): if constexpr ((B) < R) { pp_exch<V, R, B, H>(x, y); break; } [[fallthrough]];
+#define TUSQ_EXCH_ROW(H) TUSQ_EXCH_CASE(0, H) TUSQ_EXCH_CASE(1, H) TUSQ_EXCH_CASE(2, H) TUSQ_EXCH_CASE(3, H)
+            TUSQ_EXCH_ROW(0) TUSQ_EXCH_ROW(1) TUSQ_EXCH_ROW(2)
+            TUSQ_EXCH_ROW(3) TUSQ_EXCH_ROW(4) TUSQ_EXCH_ROW(5)
+#undef TUSQ_EXCH_ROW
+#undef TUSQ_EXCH_CASE
         default: __builtin_unreachable();
         }
-        const uint32_t ts = 4u * (4u + h), rs = 5u * r;
+        const uint32_t ts = 4u * h, rs = 5u * r;
         const uint32_t rp = (reg >> rs) & 31u, tp = (thr >> ts) & 15u;
         reg = (reg & ~(31u << rs)) | (tp << rs);
         thr = (thr & ~(15u << ts)) | (rp << ts);

@@ -234,11 +234,11 @@ def _run_programs_numpy(c, dump, progs, weights):
                 M = dump["mats"][mat: mat + 16]
                 psi = _apply_local(psi, n, q, (reg[arg & 7], reg[(arg >> 3) & 7]), M, False)
             else:
-                # lane exchange: thread bits 4 and 5 are lane bits of full wavefronts
+                # lane exchange: thread bits 0 .. 5 are the lane bits of full wavefronts
                 assert k - r >= 6
-                ri, h = arg & 7, (arg >> 3) & 1
-                assert ri < r
-                reg[ri], thr[4 + h] = thr[4 + h], reg[ri]
+                ri, h = arg & 7, (arg >> 3) & 7
+                assert ri < r and h < 6
+                reg[ri], thr[h] = thr[h], reg[ri]
         assert (reg, thr) == (end_reg, end_thr)
     return acc
 
