@@ -70,6 +70,7 @@ def _args():
                    help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
     p.add_argument("--batch-jobs", type=int, default=4096)
     p.add_argument("--batch-chunk", type=int, default=256)
+    p.add_argument("--batch-precisions", default="c128,c64")
     p.add_argument("--serve-count", type=int, default=60)
     p.add_argument("--serve-nmax", type=int, default=28)
     p.add_argument("--serve-load", type=float, default=0.7)
@@ -380,7 +381,8 @@ def bench_batch(a, tq):
            "config": {"workload": f"{a.batch_jobs} random-brickwork jobs, n~U{{10..16}}, "
                                   f"L~U{{10..60}}, p2~U[1e-3,2e-2], p1=p2/10, S=1e4, "
                                   f"{a.traversal}, {a.batch_chunk} jobs per launch"}}
-    for prec in ("c128", "c64"):
+    precs = [x for x in a.batch_precisions.split(",") if x]
+    for prec in precs:
         tot = {"wall": 0.0, "device": 0.0, "ecm": 0.0, "plan": 0.0, "shots": 0, "leaves": 0,
                "passes": 0}
         for c0 in range(0, len(ecs), a.batch_chunk):
@@ -409,8 +411,8 @@ def bench_batch(a, tq):
                      "shots_per_s_device": round(tot["shots"] / tot["device"], 1),
                      "shots_per_s_wall": round(tot["shots"] / tot["wall"], 1)}
         _log(f"[bench] batch {prec}: {out[prec]}")
-    out["value"] = out["c128"]["shots_per_s_device"]
-    out["dtype"] = "c128"
+    out["value"] = out[precs[0]]["shots_per_s_device"]
+    out["dtype"] = precs[0]
     return out
 
 

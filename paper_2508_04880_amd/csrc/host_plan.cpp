@@ -113,15 +113,18 @@ struct Layout {
             if (reg[i] == pos) return static_cast<int>(i);
         return -1;
     }
+    // register word; an explicit layout with 9 thread bits keeps thread bit
+    // 8's position in bits 20..23 of it
     uint32_t reg_word() const {
         uint32_t w = 0;
         for (uint32_t i = 0; i < R; ++i) w |= reg[i] << (5 * i);
+        if (!asc && T > 8) w |= thr[8] << 20;
         return w;
     }
     uint32_t thr_word() const {
         if (asc) return THR_ASC;
         uint32_t w = 0;
-        for (uint32_t b = 0; b < T; ++b) w |= thr[b] << (4 * b);
+        for (uint32_t b = 0; b < T && b < 8; ++b) w |= thr[b] << (4 * b);
         return w;
     }
 };
@@ -187,7 +190,7 @@ void build_programs(Plan &plan, Pass &p) {
     // (at most 4, and leaving R positions for the registers)
     const uint32_t lowc = std::min<uint32_t>(std::min<uint32_t>(low, 4), T);
     const uint32_t lowmask = (1u << lowc) - 1u;
-    const bool general = plan.general_layouts && T <= 8;
+    const bool general = plan.general_layouts && T <= 9;
     const bool exch_ok = general && T >= 6;
 
     auto identity2 = [&]() {

@@ -390,7 +390,8 @@ __global__ void __launch_bounds__(256) k_sweep_reg(V *__restrict__ psi, SweepArg
 constexpr int PP_TBITS = 9;
 
 // thread word of a layout whose thread-index bits take the positions outside
-// the register set in ascending order
+// the register set in ascending order (an explicit layout with 9 thread bits
+// keeps thread bit 8's position in bits 20..23 of the register word)
 constexpr uint32_t PP_THR_ASC = 0xFFFFFFFFu;
 
 // LDS byte offset of this thread's part of a layout: the XOR over set
@@ -403,9 +404,9 @@ __device__ __forceinline__ uint32_t lds_thread_part(uint32_t tid, uint32_t k, ui
     uint32_t pd = 0;
     if (thr != PP_THR_ASC) {
 #pragma unroll
-        for (uint32_t b = 0; b < 8; ++b) {
+        for (uint32_t b = 0; b < static_cast<uint32_t>(PP_TBITS); ++b) {
             if (b + R < k) {
-                const uint32_t p = (thr >> (4 * b)) & 15u;
+                const uint32_t p = b < 8 ? (thr >> (4 * b)) & 15u : (reg >> 20) & 15u;
                 pd ^= (0u - ((tid >> b) & 1u)) &
                       (Swz<V>::phys(1u << p) * static_cast<uint32_t>(sizeof(V)));
             }
@@ -435,9 +436,10 @@ __device__ __forceinline__ uint64_t layout_thread_offset(uint32_t tid, const QMa
     uint64_t off = 0;
     if (thr != PP_THR_ASC) {
 #pragma unroll
-        for (uint32_t b = 0; b < 8; ++b)
+        for (uint32_t b = 0; b < static_cast<uint32_t>(PP_TBITS); ++b)
             if (b + R < k)
-                off |= static_cast<uint64_t>((tid >> b) & 1u) << qat(qm, (thr >> (4 * b)) & 15u);
+                off |= static_cast<uint64_t>((tid >> b) & 1u)
+                       << qat(qm, b < 8 ? (thr >> (4 * b)) & 15u : (reg >> 20) & 15u);
     } else {
         uint32_t set = 0;
 #pragma unroll

@@ -181,8 +181,9 @@ def _layout(k, r, reg_word, thr_word):
     reg = [(reg_word >> (5 * i)) & 31 for i in range(r)]
     if thr_word == THR_ASC:
         thr = [p for p in range(k) if p not in reg]
-    else:
-        thr = [(thr_word >> (4 * b)) & 15 for b in range(k - r)]
+    else:   # a 9th thread bit's position sits in bits 20..23 of the register word
+        thr = [(thr_word >> (4 * b)) & 15 if b < 8 else (reg_word >> 20) & 15
+               for b in range(k - r)]
     assert sorted(reg + thr) == list(range(k)), (reg, thr)
     return reg, thr
 
@@ -247,7 +248,7 @@ def _run_programs_numpy(c, dump, progs, weights):
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 @pytest.mark.parametrize("trav", ["dftt", "hybrid"])
 @pytest.mark.parametrize("n,kmax,low,maxops", [(8, 6, 2, 4), (8, 7, 3, 12), (8, 16, 5, 12),
-                                               (12, 10, 4, 16), (13, 12, 4, 24)])
+                                               (12, 10, 4, 16), (13, 12, 4, 24), (14, 13, 4, 32)])
 def test_register_programs_reproduce_oracle(kernel, precision, trav, n, kmax, low, maxops):
     c = brickwork(n, 6, 0.02, 0.05, 12)
     S = 3000

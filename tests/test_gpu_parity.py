@@ -178,6 +178,25 @@ def test_mirror_circuit_returns_to_zero_at_26_qubits(ctx):
     assert d[1:].max() < 1e-12
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_mirror_ising_returns_to_zero_at_30_qubits(ctx, precision):
+    """The 30-qubit Trotter-Ising circuit of the precision workload (16 GiB
+    complex128 / 8 GiB complex64 state) followed by its inverse is the
+    identity: every shot samples |0...0> and the FP64 norm stays 1."""
+    _say(f"[gpu] mirror Ising n=30 {precision}")
+    fwd = ising(30, 20, 0.0, 0.0)
+    c = Circuit(30)
+    for k, q, p in zip(fwd.kinds, fwd.qubits, fwd.params):
+        c.add(k, q, p)
+    for k, q, p in reversed(list(zip(fwd.kinds, fwd.qubits, fwd.params))):
+        c.add(k, q, tuple(-x for x in p) if k in ("RX", "RZ") else p)
+    ec, t, o, r = _engine(ctx, c, 2000, 5, precision=precision, want=6, drift_bound=1.0)
+    assert t.info()["n_leaves"] == 1
+    assert not r.samples().any()
+    tol = 1e-10 if precision == "c128" else 1e-4
+    assert abs(r.norms(1)[0] - 1.0) < tol
+
+
 def test_repeat_run_is_bitwise_identical(ctx):
     _say("[gpu] determinism")
     c = brickwork(12, 10, 2e-3, 2e-2, 4)
