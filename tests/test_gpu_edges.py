@@ -1,0 +1,125 @@
+"""GPU edge cases through the C ABI: degenerate circuits and shot counts,
+closed forms, tiles that span the whole state or leave a ragged set of
+qubits, every traversal on a noise-only tree, and the complex64 path on the
+smallest inputs.  Each case is checked against the oracle or an exact
+answer."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2508_04880_amd as tq
+from workloads import Circuit, bell_pair, brickwork, random_small_circuit
+from workloads.circuits import depol1, depol2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = tq.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _run(ctx, c, S, seed, **kw):
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=seed, **kw)
+    t = tq.Tree(ec, o)
+    return t, tq.tusq_run_tree(ctx, ec, t, o)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_empty_circuit_is_the_zero_state(ctx, precision):
+    _say(f"[gpu] empty circuit {precision}")
+    c = Circuit(5)
+    t, r = _run(ctx, c, 100, 1, precision=precision)
+    d = r.distribution()
+    assert d[0] == 1.0 and not d[1:].any()
+    assert len(r.samples()) == 100 and not r.samples().any()
+
+
+@pytest.mark.parametrize("S", [1, 2, 7])
+def test_few_shots_single_qubit(ctx, S):
+    _say(f"[gpu] one qubit S={S}")
+    c = Circuit(1)
+    c.add("H", (0,), (), depol1(0.3))
+    c.add("T", (0,), (), depol1(0.2))
+    seed = 11
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    t, r = _run(ctx, c, S, seed)
+    assert t.serialize() == ot.serialize()
+    np.testing.assert_allclose(r.distribution(), dist, atol=1e-12, rtol=0)
+    assert len(r.samples()) == S
+
+
+def test_bell_pair_closed_form_through_the_engine(ctx):
+    """Lossless: every noisy instance is its own leaf, so the averaged
+    distribution is the empirical mixture; with many shots it approaches the
+    channel output P(00)=P(11)=(1-8p/15)/2, P(01)=P(10)=4p/15."""
+    _say("[gpu] bell pair")
+    p = 0.3
+    c = bell_pair(0.0, p)
+    S, seed = 400_000, 3
+    ot = oracle.ecm(c, S, seed, prune=False)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    t, r = _run(ctx, c, S, seed, prune=0)
+    d = r.distribution()
+    np.testing.assert_allclose(d, dist, atol=1e-12, rtol=0)
+    exact = np.array([(1 - 8 * p / 15) / 2, 4 * p / 15, 4 * p / 15, (1 - 8 * p / 15) / 2])
+    # binomial spread of the sampled error frequencies at S shots
+    assert np.max(np.abs(d - exact)) < 5 * np.sqrt(0.25 / S)
+
+
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+def test_noise_only_tree(ctx, trav):
+    """Identity gates only (X twice) with strong noise: the tree is all
+    error branches; every traversal equals the oracle."""
+    _say(f"[gpu] noise-only tree {trav}")
+    c = Circuit(3)
+    for _ in range(4):
+        for q in range(3):
+            c.add("X", (q,), (), depol1(0.2))
+        c.add("CX", (0, 2), (), depol2(0.2))
+        c.add("CX", (0, 2), ())
+    S, seed = 5000, 9
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, traversal=trav, want_samples=False)
+    t, r = _run(ctx, c, S, seed, traversal=trav)
+    np.testing.assert_allclose(r.distribution(), dist, atol=1e-12, rtol=0)
+
+
+@pytest.mark.parametrize("n,kmax", [(12, 12), (13, 12), (12, 16), (17, 12), (9, 4)])
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_tile_spans_state_or_leaves_ragged_qubits(ctx, n, kmax, precision):
+    """Tiles of the whole state (k = n, one workgroup), one qubit more than a
+    tile, tiles larger than the state, and tiles smaller than a wavefront's
+    register block."""
+    _say(f"[gpu] tiles n={n} k={kmax} {precision}")
+    c = brickwork(n, 6, 2e-3, 2e-2, 40 + n)
+    S, seed = 3000, 13
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    t, r = _run(ctx, c, S, seed, precision=precision, fusion_max_qubits=kmax,
+                fusion_low_qubits=min(4, max(kmax - 2, 1)), drift_bound=1.0)
+    tol = 1e-10 if precision == "c128" else 1e-4
+    np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
+
+
+def test_noiseless_circuit_is_one_leaf_with_all_shots(ctx):
+    _say("[gpu] noiseless")
+    c = random_small_circuit(6, 40, 3, p1=0.0, p2=0.0)
+    S, seed = 1234, 5
+    ot = oracle.ecm(c, S, seed)
+    assert ot.n_leaves == 1
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    t, r = _run(ctx, c, S, seed)
+    np.testing.assert_allclose(r.distribution(), dist, atol=1e-12, rtol=0)
+    assert len(r.samples()) == S
