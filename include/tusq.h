@@ -166,6 +166,18 @@ int tusq_circuit_gate(tusq_circuit *c, uint32_t kind, const uint32_t *qubits,
  * The identity takes the remaining probability.  One channel per gate.      */
 int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double *probs,
                              uint32_t n_probs);
+/* Pauli-twirled thermal relaxation (Sec. VI-A, Eq. (4)): over a duration t
+ * with relaxation time T1 and dephasing time T2 the channel becomes
+ * pX = pY = (1 - exp(-t/T1)) / 4, pZ = (1 - exp(-t/T2)) / 2 - (1 - exp(-t/T1)) / 4.
+ * probs[0..2] receive (pX, pY, pZ).  EINVAL unless t >= 0, T1 > 0,
+ * 0 < T2 <= 2 T1 (pZ >= 0) and probs is not NULL.                          */
+int tusq_thermal_pauli_probs(double t, double t1, double t2, double *probs);
+/* Attach that channel after a gate: a 1-qubit gate gets (pX, pY, pZ); a CX
+ * gets the product of the two qubits' independent channels (15 outcomes,
+ * ordered as in tusq_circuit_pauli_noise).  Same rules as
+ * tusq_circuit_pauli_noise otherwise.                                      */
+int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, double t1,
+                               double t2);
 int tusq_circuit_destroy(tusq_circuit *c);
 
 /* ---- host-only error characterisation (no GPU needed) -------------------- */

@@ -23,6 +23,7 @@ from .oracle import (  # noqa: F401
     run,
     sample_shot,
     set_threads,
+    thermal_probs,
     thresholds,
     trajectory,
 )

@@ -113,6 +113,17 @@ def thresholds(p: Sequence[float]) -> List[int]:
     return [int(x) for x in out]
 
 
+def thermal_probs(t: float, t1: float, t2: float, two_qubit: bool = False) -> List[float]:
+    """Pauli-twirled thermal-relaxation channel (Sec. VI-A, Eq. (4)): 3
+    probabilities (pX, pY, pZ), or the 15 of the same channel on both qubits
+    of a CX.  Raises ValueError outside t >= 0, T1 > 0, 0 < T2 <= 2 T1."""
+    out = np.zeros(15 if two_qubit else 3, dtype=np.float64)
+    f = lib().oc_thermal_probs2 if two_qubit else lib().oc_thermal_probs
+    if f(C.c_double(t), C.c_double(t1), C.c_double(t2), _ptr(out)) != 0:
+        raise ValueError("need t >= 0, T1 > 0, 0 < T2 <= 2 T1")
+    return [float(x) for x in out]
+
+
 def sample_shot(circ, seed: int, shot: int):
     h = _CircuitHandle(circ)
     nch = max(1, circ.n_channels)

@@ -96,6 +96,36 @@ static uint64_t draw64(uint64_t seed, uint32_t sub, uint32_t primary, uint32_t a
     return (uint64_t)o[2] | ((uint64_t)o[3] << 32);
 }
 
+/* Pauli-twirled thermal relaxation, Sec. VI-A Eq. (4): over a duration t with
+ * relaxation time T1 and dephasing time T2,
+ *   pX = pY = (1 - e^{-t/T1}) / 4,   pZ = (1 - e^{-t/T2}) / 2 - (1 - e^{-t/T1}) / 4
+ * (1 - e^{-x} evaluated as -expm1(-x)).  Returns -1 unless t >= 0, T1 > 0 and
+ * 0 < T2 <= 2 T1. */
+int oc_thermal_probs(double t, double t1, double t2, double out[3])
+{
+    if (!(t >= 0.0 && t1 > 0.0 && t2 > 0.0 && t2 <= 2.0 * t1)) return -1;
+    double a = -expm1(-t / t1), b = -expm1(-t / t2);
+    out[0] = a / 4.0;
+    out[1] = a / 4.0;
+    out[2] = b / 2.0 - a / 4.0;
+    if (out[2] < 0.0) out[2] = 0.0;
+    return 0;
+}
+
+/* The same channel acting independently on both qubits of a CX: outcome
+ * k = 4a + b (a on the control, b on the target) has probability q_a q_b,
+ * q = (1 - pX - pY - pZ, pX, pY, pZ); out[k - 1] for k = 1..15. */
+int oc_thermal_probs2(double t, double t1, double t2, double out[15])
+{
+    double p[3];
+    if (oc_thermal_probs(t, t1, t2, p)) return -1;
+    double q[4] = {1.0 - p[0] - p[1] - p[2], p[0], p[1], p[2]};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b)
+            if (a || b) out[4 * a + b - 1] = q[a] * q[b];
+    return 0;
+}
+
 /* Integer cumulative thresholds of a Pauli channel: S_k is the plain
  * left-to-right double sum p_1 + ... + p_k; C_k = floor(S_k * 2^64), or
  * 2^64 - 1 once S_k reaches 1.  A uniform u64 u selects the smallest k with

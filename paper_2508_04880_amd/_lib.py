@@ -77,6 +77,8 @@ _SIGS = {
     "tusq_circuit_create": (C.c_int, [C.c_uint32, P]),
     "tusq_circuit_gate": (C.c_int, [P, C.c_uint32, P, P, P]),
     "tusq_circuit_pauli_noise": (C.c_int, [P, C.c_uint32, P, C.c_uint32]),
+    "tusq_thermal_pauli_probs": (C.c_int, [C.c_double, C.c_double, C.c_double, P]),
+    "tusq_circuit_thermal_noise": (C.c_int, [P, C.c_uint32, C.c_double, C.c_double, C.c_double]),
     "tusq_circuit_destroy": (C.c_int, [P]),
     "tusq_ecm_build": (C.c_int, [P, P, P]),
     "tusq_tree_get_info": (C.c_int, [P, P]),
@@ -168,10 +170,22 @@ class Circuit:
                 arr = (C.c_double * len(noise))(*noise)
                 check(lib.tusq_circuit_pauli_noise(self.h, gi, arr, C.c_uint32(len(noise))))
 
+    def thermal_noise(self, gate_index: int, t: float, t1: float, t2: float) -> None:
+        """Attach the twirled thermal-relaxation channel after a gate that has
+        no channel yet (tusq_circuit_thermal_noise)."""
+        check(lib.tusq_circuit_thermal_noise(self.h, C.c_uint32(gate_index), C.c_double(t),
+                                             C.c_double(t1), C.c_double(t2)))
+
     def __del__(self):
         if getattr(self, "h", None):
             lib.tusq_circuit_destroy(self.h)
             self.h = None
+
+
+def tusq_thermal_pauli_probs(t: float, t1: float, t2: float) -> np.ndarray:
+    out = np.zeros(3, np.float64)
+    check(lib.tusq_thermal_pauli_probs(C.c_double(t), C.c_double(t1), C.c_double(t2), _ptr(out)))
+    return out
 
 
 class Tree:

@@ -130,6 +130,45 @@ int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double 
     });
 }
 
+static void thermal_probs(double t, double t1, double t2, double out[3]) {
+    need(std::isfinite(t) && std::isfinite(t1) && std::isfinite(t2), "times must be finite");
+    need(t >= 0.0 && t1 > 0.0 && t2 > 0.0, "need t >= 0, T1 > 0, T2 > 0");
+    need(t2 <= 2.0 * t1, "need T2 <= 2 T1");
+    const double a = -std::expm1(-t / t1);  // 1 - exp(-t/T1)
+    const double b = -std::expm1(-t / t2);  // 1 - exp(-t/T2)
+    out[0] = out[1] = a / 4.0;
+    out[2] = std::max(0.0, b / 2.0 - a / 4.0);
+}
+
+int tusq_thermal_pauli_probs(double t, double t1, double t2, double *probs) {
+    return guarded([&] {
+        need(probs != nullptr, "probs is NULL");
+        thermal_probs(t, t1, t2, probs);
+    });
+}
+
+int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, double t1,
+                               double t2) {
+    double p1[3];
+    double p[15];
+    uint32_t m = 3;
+    const int rc = guarded([&] {
+        need(c != nullptr, "circuit is NULL");
+        need(gate_index < c->c.gates.size(), "gate index out of range");
+        thermal_probs(t, t1, t2, p1);
+        if (is_cx(c->c.gates[gate_index].kind)) {
+            // independent channels on control (a) and target (b): outcome 4a + b
+            const double q[4] = {1.0 - p1[0] - p1[1] - p1[2], p1[0], p1[1], p1[2]};
+            m = 15;
+            for (int k = 1; k < 16; ++k) p[k - 1] = q[k >> 2] * q[k & 3];
+        } else {
+            std::copy(p1, p1 + 3, p);
+        }
+    });
+    if (rc != TUSQ_OK) return rc;
+    return tusq_circuit_pauli_noise(c, gate_index, p, m);
+}
+
 int tusq_circuit_destroy(tusq_circuit *c) {
     delete c;
     return TUSQ_OK;

@@ -8,6 +8,13 @@
 //              III-B), and writes the tile back.  The sweep's qubit set
 //              always holds the lowest qubits, so every wavefront moves
 //              contiguous runs of amplitudes.
+//              This op-list form serves tiles smaller than a register block.
+//  k_sweep_pp  the default sweep: the same tiles held in registers (16 or 8
+//              amplitudes per thread), a host-compiled program of register
+//              ops, in-wave lane exchanges and LDS re-layouts, a persistent
+//              grid that prefetches the next tile while one computes.
+//  k_sweep_reg, k_sweep_pipe   one tile per workgroup, and LDS double
+//              buffering with global_load_lds (selectable variants).
 //  k_leaf      acc += w |psi|^2 in FP64 and per-chunk FP64 probability sums
 //              (fixed reduction order: results are bitwise reproducible).
 //  k_scan      inclusive prefix of the chunk sums and the leaf norm (one

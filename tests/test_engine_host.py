@@ -314,3 +314,43 @@ def test_invalid_inputs_are_rejected():
     assert lib.tusq_circuit_destroy(h) == 0
     assert lib.tusq_circuit_destroy(None) == 0
     assert lib.tusq_result_destroy(None) == 0
+
+
+# --------------------------------------------------------------------------
+# Twirled thermal relaxation at the boundary (Eq. (4))
+
+def test_thermal_probs_match_oracle_and_reject_bad_times():
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        t1 = float(rng.uniform(0.1, 10))
+        t2 = float(rng.uniform(0.05, 2 * t1))
+        t = float(rng.uniform(0, 3))
+        got = tq.tusq_thermal_pauli_probs(t, t1, t2)
+        assert list(got) == oracle.thermal_probs(t, t1, t2)
+    for bad in ((-1.0, 1.0, 1.0), (1.0, 0.0, 1.0), (1.0, 1.0, -1.0), (1.0, 1.0, 2.5),
+                (float("nan"), 1.0, 1.0)):
+        with pytest.raises(tq.TusqError) as e:
+            tq.tusq_thermal_pauli_probs(*bad)
+        assert e.value.code == -1
+
+
+def test_thermal_noise_attached_by_the_library_gives_the_oracle_tree():
+    """A brickwork circuit with the twirled channel after every gate: built
+    through tusq_circuit_thermal_noise it yields the same tree, byte for byte,
+    as the oracle's own circuit with oracle-computed probabilities."""
+    base = brickwork(6, 6, 0.0, 0.0, 21)
+    t_1q, t_2q, T1, T2 = 0.02, 0.1, 1.0, 0.8
+    c = Circuit(6)
+    for k, q, p in zip(base.kinds, base.qubits, base.params):
+        c.add(k, q, p, oracle.thermal_probs(t_2q if k == "CX" else t_1q, T1, T2,
+                                            two_qubit=(k == "CX")))
+    ec = tq.Circuit(Circuit(6, kinds=list(base.kinds), qubits=list(base.qubits),
+                            params=list(base.params), noise=[None] * base.n_gates))
+    for g, k in enumerate(base.kinds):
+        ec.thermal_noise(g, t_2q if k == "CX" else t_1q, T1, T2)
+    S, seed = 4000, 3
+    ot = oracle.ecm(c, S, seed)
+    o = tq.tusq_opts_default(shots=S, seed=seed)
+    assert tq.Tree(ec, o).serialize() == ot.serialize()
+    with pytest.raises(tq.TusqError):
+        ec.thermal_noise(0, 0.1, 1.0, 1.0)       # the gate already has a channel

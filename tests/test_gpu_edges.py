@@ -123,3 +123,29 @@ def test_noiseless_circuit_is_one_leaf_with_all_shots(ctx):
     t, r = _run(ctx, c, S, seed)
     np.testing.assert_allclose(r.distribution(), dist, atol=1e-12, rtol=0)
     assert len(r.samples()) == S
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_thermal_relaxation_noise_matches_oracle(ctx, precision):
+    """Brickwork with the Pauli-twirled thermal-relaxation channel (Eq. (4))
+    after every gate, attached through tusq_circuit_thermal_noise, against the
+    oracle run on oracle-computed probabilities."""
+    _say(f"[gpu] thermal noise {precision}")
+    base = brickwork(9, 10, 0.0, 0.0, 23)
+    t_1q, t_2q, T1, T2 = 0.01, 0.05, 1.0, 0.7
+    c = Circuit(9)
+    ec = tq.Circuit(Circuit(9, kinds=list(base.kinds), qubits=list(base.qubits),
+                            params=list(base.params), noise=[None] * base.n_gates))
+    for g, (k, q, p) in enumerate(zip(base.kinds, base.qubits, base.params)):
+        t = t_2q if k == "CX" else t_1q
+        c.add(k, q, p, oracle.thermal_probs(t, T1, T2, two_qubit=(k == "CX")))
+        ec.thermal_noise(g, t, T1, T2)
+    S, seed = 20_000, 4
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    o = tq.tusq_opts_default(shots=S, seed=seed, precision=precision, drift_bound=1.0)
+    t = tq.Tree(ec, o)
+    assert t.serialize() == ot.serialize()
+    r = tq.tusq_run_tree(ctx, ec, t, o)
+    tol = 1e-10 if precision == "c128" else 1e-4
+    np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)

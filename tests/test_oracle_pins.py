@@ -514,3 +514,61 @@ def test_sample_indices_and_margins_consistent():
         probs = np.abs(psi[idx.astype(np.int64)]) ** 2
         assert np.all(probs > 0)
         off += k
+
+
+# --------------------------------------------------------------------------
+# Pauli-twirled thermal relaxation (Sec. VI-A, Eq. (4))
+
+_PAULI = {"X": np.array([[0, 1], [1, 0]], complex), "Y": np.array([[0, -1j], [1j, 0]]),
+          "Z": np.array([[1, 0], [0, -1]], complex)}
+THERMAL_CASES = [(0.05, 1.0, 1.5), (0.3, 2.0, 0.7), (1.0, 1.0, 2.0), (2e-3, 100.0, 60.0),
+                 (0.0, 1.0, 1.0), (5.0, 1.0, 0.1)]
+
+
+def _relaxation_kraus(t, t1, t2):
+    """Amplitude damping (gamma = 1 - e^{-t/T1}) followed by pure dephasing
+    that brings the coherence decay to e^{-t/T2}."""
+    g = 1.0 - math.exp(-t / t1)
+    ad = [np.array([[1, 0], [0, math.sqrt(1 - g)]], complex),
+          np.array([[0, math.sqrt(g)], [0, 0]], complex)]
+    rest = math.exp(-t / t2) / math.sqrt(1 - g) if g < 1 else 1.0   # 1 - 2q
+    q = (1.0 - rest) / 2.0
+    pd = [math.sqrt(1 - q) * np.eye(2, dtype=complex), math.sqrt(q) * _PAULI["Z"]]
+    return [b @ a for a in ad for b in pd]
+
+
+@pytest.mark.parametrize("t,t1,t2", THERMAL_CASES)
+def test_thermal_twirl_is_the_chi_diagonal_of_relaxation(t, t1, t2):
+    """The Pauli twirl of a channel keeps the diagonal of its chi matrix,
+    p_P = sum_K |Tr(P K)|^2 / 4: Eq. (4) must equal it for amplitude damping
+    plus dephasing (computed here from Kraus operators)."""
+    ks = _relaxation_kraus(t, t1, t2)
+    assert np.allclose(sum(k.conj().T @ k for k in ks), np.eye(2), atol=1e-14)
+    chi = [sum(abs(np.trace(_PAULI[P] @ k)) ** 2 for k in ks) / 4 for P in "XYZ"]
+    np.testing.assert_allclose(oracle.thermal_probs(t, t1, t2), chi, atol=1e-15, rtol=0)
+
+
+@pytest.mark.parametrize("t,t1,t2", THERMAL_CASES)
+def test_thermal_twirl_decay_rates(t, t1, t2):
+    """The twirled channel contracts <Z> by e^{-t/T1} and <X>, <Y> by e^{-t/T2}
+    (density-matrix check on |+> and |1>)."""
+    px, py, pz = oracle.thermal_probs(t, t1, t2)
+    def apply(rho):
+        return ((1 - px - py - pz) * rho + px * _PAULI["X"] @ rho @ _PAULI["X"]
+                + py * _PAULI["Y"] @ rho @ _PAULI["Y"] + pz * _PAULI["Z"] @ rho @ _PAULI["Z"])
+    plus = np.full((2, 2), 0.5, complex)
+    one = np.array([[0, 0], [0, 1]], complex)
+    assert abs(np.trace(_PAULI["X"] @ apply(plus)).real - math.exp(-t / t2)) < 1e-14
+    assert abs(np.trace(_PAULI["Z"] @ apply(one)).real + math.exp(-t / t1)) < 1e-14
+
+
+def test_thermal_twirl_on_cx_is_the_product_channel():
+    p1 = oracle.thermal_probs(0.2, 1.3, 0.9)
+    p2 = oracle.thermal_probs(0.2, 1.3, 0.9, two_qubit=True)
+    q = [1 - sum(p1)] + p1
+    for k in range(1, 16):
+        assert p2[k - 1] == q[k >> 2] * q[k & 3]
+    assert abs(sum(p2) + q[0] * q[0] - 1) < 1e-15
+    for bad in ((-1.0, 1.0, 1.0), (1.0, 0.0, 1.0), (1.0, 1.0, 0.0), (1.0, 1.0, 2.5)):
+        with pytest.raises(ValueError):
+            oracle.thermal_probs(*bad)
