@@ -54,7 +54,7 @@ def _args():
     p.add_argument("--shots", type=int, default=1_000_000)
     p.add_argument("--qubits", type=int, default=26)
     p.add_argument("--layers", type=int, default=100)
-    p.add_argument("--traversal", default="dftt", choices=["dftt", "naive", "hybrid"])
+    p.add_argument("--traversal", default="dftt", choices=["dftt", "naive", "hybrid", "checkpoint"])
     p.add_argument("--no-c64", action="store_true")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 3u
+#define TUSQ_ABI_VERSION 4u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -70,7 +70,11 @@ enum { TUSQ_C128 = 0, TUSQ_C64 = 1 };
  *   NAIVE  recompute every leaf from |0...0> ("DFTT switched off");
  *   HYBRID undo only when that costs strictly fewer gate and Pauli
  *          applications than recomputing from the root.                     */
-enum { TUSQ_DFTT = 0, TUSQ_NAIVE = 1, TUSQ_HYBRID = 2 };
+/* traversals: plain DFTT (undo to the shared node), naive (restart from the
+ * root), hybrid (undo only when cheaper), checkpoint (DFTT whose branch
+ * states are kept in spare device memory: the next leaf restores the state
+ * at its branch depth instead of undoing; Fig. 6E)                        */
+enum { TUSQ_DFTT = 0, TUSQ_NAIVE = 1, TUSQ_HYBRID = 2, TUSQ_CHECKPOINT = 3 };
 
 /* what a run returns */
 #define TUSQ_WANT_DIST 1u      /* FP64 averaged distribution, 2^n values */
@@ -90,7 +94,7 @@ typedef struct {
     uint32_t alpha_den;        /*   alpha_num * s_max (Sec. III-A.4)          */
     uint32_t beta;             /* insignificant circuits kept (Eq. (2))       */
     uint32_t precision;        /* TUSQ_C128 | TUSQ_C64                        */
-    uint32_t traversal;        /* TUSQ_DFTT | TUSQ_NAIVE | TUSQ_HYBRID        */
+    uint32_t traversal;        /* TUSQ_DFTT | NAIVE | HYBRID | CHECKPOINT     */
     uint32_t commute;          /* ER commutation on/off (Sec. III-A.2)         */
     uint32_t prune;            /* pruning on/off                               */
     double drift_bound;        /* C64 only: recompute a leaf from the root in
@@ -128,6 +132,7 @@ typedef struct {
     uint64_t leaf_sweeps;               /* leaf accumulation sweeps               */
     uint64_t recomputes, recompute_passes;
     uint64_t sweep_bytes;               /* algorithmic bytes of all sweeps        */
+    uint64_t checkpoint_saves, checkpoint_restores; /* checkpoint traversal */
     uint64_t sweep_flops;               /* real floating-point operations of the
                                            sweeps' dense ops: 16 per amplitude for
                                            a 2x2, 32 for a 4x4 (one complex

@@ -267,8 +267,8 @@ def ecm(circ, shots: int, seed: int, do_commute: bool = True, prune: bool = True
 
 
 COUNTER_NAMES = ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
-                 "draws", "ret_gates", "ret_paulis")
-TRAVERSAL = {"dftt": 0, "naive": 1, "hybrid": 2}
+                 "draws", "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores")
+TRAVERSAL = {"dftt": 0, "naive": 1, "hybrid": 2, "checkpoint": 3}
 
 
 def run(circ, tree: OracleTree, seed: int, traversal: str = "dftt", leaf_begin: int = 0,

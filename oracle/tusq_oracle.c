@@ -921,7 +921,7 @@ static uint64_t leaf_tokens(const oc_circuit *c, const uint64_t *keys, uint64_t 
 }
 
 typedef struct { uint64_t fwd_gates, inv_gates, fwd_paulis, inv_paulis, resets, leaves, draws,
-                          ret_gates, ret_paulis; } counters_t;
+                          ret_gates, ret_paulis, saves, restores; } counters_t;
 
 static void apply_token(const oc_circuit *c, const uint64_t *keys, int64_t t, cplx *psi,
                         int inverse, counters_t *ct)
@@ -1037,13 +1037,44 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
     if (dist) for (uint64_t i = 0; i < N; ++i) dist[i] = 0.0;
     uint64_t so = 0, na = 0, nka = 0;
     const uint64_t *ka = NULL;
+    /* Checkpoint traversal (3): plain DFTT, except that the state at every
+     * depth where a later leaf branches off the current path is kept, and a
+     * leaf starts from the kept state at its branch depth instead of undoing
+     * the previous leaf.  bd[l - lb] = branch depth of leaf l (shared with
+     * leaf l - 1); a depth x is kept while leaf l runs forward through it if
+     * some later leaf m branches at x and no leaf in between branches
+     * shallower than x. */
+    uint64_t *bd = NULL, *kdepth = NULL, nk = 0;
+    cplx **kstate = NULL;
+    if (traversal == 3 && le > lb) {
+        bd = calloc(le - lb, sizeof(uint64_t));
+        for (uint64_t l = lb + 1; l < le; ++l) {
+            const uint64_t *k0 = t->ev_key + t->ev_off[l - 1], *k1 = t->ev_key + t->ev_off[l];
+            bd[l - lb] = shared_depth(c, k0, t->ev_off[l] - t->ev_off[l - 1], k1,
+                                      t->ev_off[l + 1] - t->ev_off[l]);
+        }
+        kdepth = malloc(sizeof(uint64_t) * (c->G + c->n * (size_t)c->G + 2));
+        kstate = malloc(sizeof(cplx *) * (c->G + c->n * (size_t)c->G + 2));
+    }
     for (uint64_t l = lb; l < le; ++l) {
         const uint64_t *kb = t->ev_key + t->ev_off[l];
         uint64_t nkb = t->ev_off[l + 1] - t->ev_off[l];
         uint64_t nb = leaf_tokens(c, kb, nkb, tb);
         uint64_t from = 0;
         int reset = 1;
-        if (l > lb && traversal != 1) {
+        if (l > lb && traversal == 3) {
+            uint64_t d = bd[l - lb];
+            while (nk > 0 && kdepth[nk - 1] > d) free(kstate[--nk]);
+            if (d > 0) {
+                if (nk == 0 || kdepth[nk - 1] != d) return -2;  /* unreachable by construction */
+                memcpy(psi, kstate[nk - 1], sizeof(cplx) * N);
+                ct.restores++;
+                from = d;
+                reset = 0;
+            } else {
+                while (nk > 0) free(kstate[--nk]);
+            }
+        } else if (l > lb && traversal != 1) {
             uint64_t d = shared_depth(c, ka, nka, kb, nkb);
             if (traversal == 0 || (na - d) + (nb - d) < nb) {
                 for (uint64_t i = na; i > d; --i) apply_token(c, ka, ta[i - 1], psi, 1, &ct);
@@ -1052,7 +1083,27 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
             }
         }
         if (reset) { reset_state(psi, c->n); ct.resets++; }
-        for (uint64_t i = from; i < nb; ++i) apply_token(c, kb, tb[i], psi, 0, &ct);
+        for (uint64_t i = from; i < nb; ++i) {
+            if (traversal == 3 && i > from) {
+                /* keep depth i if a later leaf branches here (running minimum) */
+                int keep = 0;
+                uint64_t r = UINT64_MAX;
+                for (uint64_t m = l + 1; m < le; ++m) {
+                    uint64_t dm = bd[m - lb];
+                    if (dm < r) r = dm;
+                    if (r < i) break;
+                    if (dm == i) { keep = 1; break; }
+                }
+                if (keep) {
+                    kdepth[nk] = i;
+                    kstate[nk] = malloc(sizeof(cplx) * N);
+                    memcpy(kstate[nk], psi, sizeof(cplx) * N);
+                    ++nk;
+                    ct.saves++;
+                }
+            }
+            apply_token(c, kb, tb[i], psi, 0, &ct);
+        }
         ct.leaves++;
         double w = (double)t->wnum[l] / (double)t->wden[l];
         double nrm = 0.0;
@@ -1075,6 +1126,8 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
         na = nb; ka = kb; nka = nkb;
     }
     if (le > lb) { ct.ret_gates = c->G; ct.ret_paulis = nka; }
+    while (nk > 0) free(kstate[--nk]);
+    free(bd); free(kdepth); free(kstate);
     free(psi); free(cdf); free(ta); free(tb);
     if (counters) memcpy(counters, &ct, sizeof(ct));
     return 0;

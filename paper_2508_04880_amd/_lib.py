@@ -29,9 +29,9 @@ TUSQ_EINVAL, TUSQ_ENOMEM, TUSQ_EUNSUPPORTED, TUSQ_EDEVICE, TUSQ_EBUSY, TUSQ_ECAN
 KINDS = {name: i for i, name in enumerate(
     ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX"))}
 C128, C64 = 0, 1
-DFTT, NAIVE, HYBRID = 0, 1, 2
+DFTT, NAIVE, HYBRID, CHECKPOINT = 0, 1, 2, 3
 WANT_DIST, WANT_SAMPLES, WANT_NORMS = 1, 2, 4
-TRAVERSALS = {"dftt": DFTT, "naive": NAIVE, "hybrid": HYBRID}
+TRAVERSALS = {"dftt": DFTT, "naive": NAIVE, "hybrid": HYBRID, "checkpoint": CHECKPOINT}
 PRECISIONS = {"c128": C128, "c64": C64}
 
 
@@ -52,7 +52,8 @@ class tusq_counters(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in (
         "fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws",
         "ret_gates", "ret_paulis", "passes_fwd", "passes_inv", "leaf_sweeps", "recomputes",
-        "recompute_passes", "sweep_bytes", "sweep_flops", "pass_events")] + \
+        "recompute_passes", "sweep_bytes", "checkpoint_saves", "checkpoint_restores",
+        "sweep_flops", "pass_events")] + \
         [(k, C.c_double) for k in ("pass_seconds", "host_ecm_seconds", "host_plan_seconds",
                                    "device_seconds", "max_norm_drift")]
 
@@ -112,7 +113,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 3
+ABI_VERSION = 4
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")

@@ -45,7 +45,7 @@ void check_opts(const tusq_opts *o) {
     need(o->shots >= 1 && o->shots <= 0xFFFFFFFFull, "shots must be in [1, 2^32)");
     need(o->alpha_den > 0, "alpha_den must be positive");
     need(o->precision == TUSQ_C128 || o->precision == TUSQ_C64, "unknown precision");
-    need(o->traversal <= TUSQ_HYBRID, "unknown traversal");
+    need(o->traversal <= TUSQ_CHECKPOINT, "unknown traversal");
     need(!(o->leaf_begin > o->leaf_end && o->leaf_end != 0), "leaf_begin > leaf_end");
     need(o->drift_bound >= 0.0, "drift_bound must be >= 0");
 }
@@ -365,6 +365,8 @@ static void run_common(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *gi
         t0 = now_seconds();
         Plan p = build_plan(cc->c, *t, *o, o->precision == TUSQ_C64);
         const double plan_s = now_seconds() - t0;
+        if (need_b + checkpoint_bytes(cc->c.n, o->precision, p.checkpoint_slots) > ctx->c->budget)
+            fail(TUSQ_ENOMEM, "checkpoints exceed the device memory budget");
         execute_plan(*ctx->c, *t, p, *o, static_cast<hipStream_t>(stream), r->r);
         r->r.counters.host_ecm_seconds = ecm_s;
         r->r.counters.host_plan_seconds = plan_s;

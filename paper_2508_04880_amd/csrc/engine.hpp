@@ -132,7 +132,10 @@ struct Instr {
     uint32_t mat;
 };
 
-enum StepKind : int64_t { ST_RESET = 0, ST_FWD = 1, ST_INV = 2, ST_LEAF = 3 };
+// ST_SAVE / ST_RESTORE (checkpoint traversal): copy the state into / out of
+// checkpoint slot `id`
+enum StepKind : int64_t { ST_RESET = 0, ST_FWD = 1, ST_INV = 2, ST_LEAF = 3, ST_SAVE = 4,
+                          ST_RESTORE = 5 };
 struct Step {
     StepKind kind;
     uint64_t id;  // pass index (FWD/INV) or leaf index (LEAF)
@@ -158,6 +161,7 @@ struct Plan {
     // share one copy: hash -> offset of the matrix (its adjoint follows it)
     std::unordered_multimap<uint64_t, std::pair<uint32_t, int>> mat_index;  // -> (offset, dim)
     uint32_t identity2 = UINT32_MAX;  // pool offset of the 2x2 identity (program padding)
+    uint64_t checkpoint_slots = 0;    // states the checkpoint traversal keeps at once
     // per leaf in the range: the passes forming its path from the root, used
     // to recompute a leaf exactly (c64 drift control)
     std::vector<uint64_t> path_off;

@@ -38,13 +38,13 @@ void DevBuf::ensure(size_t b) {
 uint64_t Workspace::bytes() const {
     uint64_t b = 0;
     for (const DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats,
-                            &mats128, &prog})
+                            &mats128, &prog, &ckpt})
         b += d->bytes;
     return b;
 }
 void Workspace::release() {
     for (DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats, &mats128,
-                      &prog})
+                      &prog, &ckpt})
         d->release();
 }
 
@@ -56,6 +56,10 @@ uint64_t job_device_bytes(uint32_t n, uint32_t precision, uint64_t shots, bool w
     const uint32_t lc = std::min<uint32_t>(n, 11);
     b += 2 * (N >> lc) * 8 + shots * 8 + (64ull << 20);  // chunk sums, prefix, samples, plan
     return b;
+}
+
+uint64_t checkpoint_bytes(uint32_t n, uint32_t precision, uint64_t slots) {
+    return slots * ((1ull << n) * (precision == TUSQ_C64 ? 8 : 16));
 }
 
 static_assert(sizeof(Instr) == sizeof(Instr2), "program layout shared with the kernels");
@@ -115,6 +119,8 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     prefix.ensure(nc * 8);
     norms.ensure(std::max<uint64_t>(le - lb, 1) * 8);
     if (want_samples && total_shots) samples.ensure(total_shots * 8);
+    if (plan.checkpoint_slots) ws.ckpt.ensure(plan.checkpoint_slots * N * sizeof(V));
+    V *ckpt = static_cast<V *>(ws.ckpt.p);
 
     std::vector<DOp> dops;
     to_device_ops(plan, dops);
@@ -195,6 +201,14 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
         case ST_RESET:
             hip_check(launch_reset<V>(st, n, s), "reset");
             passes_since_exact = 0;
+            break;
+        case ST_SAVE:
+            hip_check(hipMemcpyAsync(ckpt + sp.id * N, st, N * sizeof(V), hipMemcpyDeviceToDevice, s),
+                      "checkpoint save");
+            break;
+        case ST_RESTORE:
+            hip_check(hipMemcpyAsync(st, ckpt + sp.id * N, N * sizeof(V), hipMemcpyDeviceToDevice, s),
+                      "checkpoint restore");
             break;
         case ST_FWD:
         case ST_INV: {

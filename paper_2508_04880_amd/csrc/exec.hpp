@@ -31,6 +31,7 @@ struct DevBuf {
 // execution lane (they only grow).
 struct Workspace {
     DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops, mats, mats128, prog;
+    DevBuf ckpt;  // checkpoint traversal: saved branch states
     uint64_t bytes() const;
     void release();
 };
@@ -64,6 +65,8 @@ struct Ctx {
 // Device bytes a job needs (state, recompute buffer, accumulator, sampler
 // scratch, samples, plan) -- used for admission.
 uint64_t job_device_bytes(uint32_t n, uint32_t precision, uint64_t shots, bool want_dist);
+// device bytes of a plan's checkpoint slots (checkpoint traversal)
+uint64_t checkpoint_bytes(uint32_t n, uint32_t precision, uint64_t slots);
 
 void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
                   Result &res, Workspace *ws = nullptr, const std::atomic<bool> *cancel = nullptr);

@@ -587,7 +587,8 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
             const uint64_t p = l - 1;
             const uint64_t d = shared_depth(G, t.evs(p), t.nev(p), t.evs(l), t.nev(l));
             const uint64_t lp = G + t.nev(p);
-            if (o.traversal == TUSQ_DFTT || (lp - d) + (cp.len - d) < cp.len) {
+            if (o.traversal == TUSQ_DFTT || o.traversal == TUSQ_CHECKPOINT ||
+                (lp - d) + (cp.len - d) < cp.len) {
                 cp.reset = false;
                 cp.from = d;
             }
@@ -616,12 +617,32 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     std::vector<Tok> toks;
     std::vector<Fuser::Item> items;
     auto &ct = plan.counters;
+    // checkpoint traversal: the states at the cut depths of the current path,
+    // innermost last (slot = position in this stack)
+    const bool ckpt = o.traversal == TUSQ_CHECKPOINT;
+    std::vector<uint64_t> saved;
     if (keep_paths) plan.path_off.push_back(0);
     for (const Comp &cp : comps) {
         if (cp.reset) {
             plan.steps.push_back(Step{ST_RESET, 0});
             ct.resets++;
             applied.clear();
+            saved.clear();
+        } else if (ckpt) {
+            // branch depth is a cut: its state was saved on the way down
+            while (!applied.empty() && applied.back().start >= cp.from) applied.pop_back();
+            while (!saved.empty() && saved.back() > cp.from) saved.pop_back();
+            if (cp.from == 0) {
+                plan.steps.push_back(Step{ST_RESET, 0});
+                ct.resets++;
+                applied.clear();
+                saved.clear();
+            } else {
+                if (saved.empty() || saved.back() != cp.from)
+                    fail(TUSQ_EINVAL, "internal: no checkpoint at a branch depth");
+                plan.steps.push_back(Step{ST_RESTORE, saved.size() - 1});
+                ct.checkpoint_restores++;
+            }
         } else {
             while (!applied.empty() && applied.back().start >= cp.from) {
                 const Seg &s = applied.back();
@@ -678,6 +699,12 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
             ct.fwd_gates += ng;
             ct.fwd_paulis += np;
             applied.push_back(Seg{pr.first, pr.second, a, ng, np});
+            if (ckpt && b < cp.len) {  // a later leaf branches here
+                plan.steps.push_back(Step{ST_SAVE, saved.size()});
+                saved.push_back(b);
+                ct.checkpoint_saves++;
+                plan.checkpoint_slots = std::max<uint64_t>(plan.checkpoint_slots, saved.size());
+            }
             a = b;
         }
         plan.steps.push_back(Step{ST_LEAF, cp.leaf});

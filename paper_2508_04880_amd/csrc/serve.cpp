@@ -107,6 +107,10 @@ struct Serving {
                 j->plan = build_plan(j->c, j->tree, j->o, j->o.precision == TUSQ_C64);
                 j->ecm_s = t1 - t0;
                 j->plan_s = now_seconds() - t1;
+                // checkpoint slots join the job's device memory
+                j->need += checkpoint_bytes(j->c.n, j->o.precision, j->plan.checkpoint_slots);
+                if (j->need > ctx.budget)
+                    fail(TUSQ_ENOMEM, "job's checkpoints exceed the device memory budget");
             } catch (const Error &e) {
                 finish(j, JS_FAILED, e.code, e.msg);
                 continue;

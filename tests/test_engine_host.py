@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 3
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 4
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -82,7 +82,7 @@ def test_tree_independent_of_host_thread_count():
     assert outs[0] == outs[1] == outs[2]
 
 
-@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid", "checkpoint"])
 @pytest.mark.parametrize("name,make,S", CASES[:4], ids=[c[0] for c in CASES[:4]])
 def test_schedule_counts_match_oracle(trav, name, make, S):
     c = make()
@@ -93,7 +93,7 @@ def test_schedule_counts_match_oracle(trav, name, make, S):
     pc = tq.tusq_plan_counters(ec, et, o)
     _, _, oc, _ = oracle.run(c, ot, 5, traversal=trav, want_dist=False, want_samples=False)
     for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
-              "ret_gates", "ret_paulis"):
+              "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores"):
         assert pc[k] == oc[k], k
     # a leaf range starts from the root
     nl = et.info()["n_leaves"]
@@ -103,7 +103,8 @@ def test_schedule_counts_match_oracle(trav, name, make, S):
         pc2 = tq.tusq_plan_counters(ec, et, o2)
         _, _, oc2, _ = oracle.run(c, ot, 5, traversal=trav, leaf_begin=2, leaf_end=nl - 3,
                                   want_dist=False, want_samples=False)
-        for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves"):
+        for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
+                  "checkpoint_saves", "checkpoint_restores"):
             assert pc2[k] == oc2[k], k
 
 
@@ -135,7 +136,14 @@ def _run_plan_numpy(c, dump, weights, lb):
     n = c.n
     psi = np.zeros(1 << n, complex)
     acc = np.zeros(1 << n)
+    slots = {}
     for kind, ident in dump["steps"]:
+        if kind == 4:            # checkpoint save
+            slots[ident] = psi.copy()
+            continue
+        if kind == 5:            # checkpoint restore
+            psi = slots[ident].copy()
+            continue
         if kind == 0:
             psi[:] = 0
             psi[0] = 1
@@ -154,7 +162,7 @@ def _run_plan_numpy(c, dump, weights, lb):
     return acc
 
 
-@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid", "checkpoint"])
 @pytest.mark.parametrize("kmax,low,maxops", [(3, 1, 2), (4, 2, 5), (5, 3, 12), (16, 5, 12)])
 def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops):
     c = brickwork(7, 8, 0.02, 0.05, 11)
@@ -196,7 +204,14 @@ def _run_programs_numpy(c, dump, progs, weights):
     R = progs["reg_qubits"]
     psi = np.zeros(1 << n, complex)
     acc = np.zeros(1 << n)
+    slots = {}
     for kind, ident in dump["steps"]:
+        if kind == 4:
+            slots[ident] = psi.copy()
+            continue
+        if kind == 5:
+            psi = slots[ident].copy()
+            continue
         if kind == 0:
             psi[:] = 0
             psi[0] = 1
@@ -246,7 +261,7 @@ def _run_programs_numpy(c, dump, progs, weights):
 
 @pytest.mark.parametrize("kernel", [0, 1, 5])
 @pytest.mark.parametrize("precision", ["c128", "c64"])
-@pytest.mark.parametrize("trav", ["dftt", "hybrid"])
+@pytest.mark.parametrize("trav", ["dftt", "hybrid", "checkpoint"])
 @pytest.mark.parametrize("n,kmax,low,maxops", [(8, 6, 2, 4), (8, 7, 3, 12), (8, 16, 5, 12),
                                                (12, 10, 4, 16), (13, 12, 4, 24), (14, 13, 4, 32)])
 def test_register_programs_reproduce_oracle(kernel, precision, trav, n, kmax, low, maxops):

@@ -78,7 +78,7 @@ def test_bell_pair_closed_form_through_the_engine(ctx):
     assert np.max(np.abs(d - exact)) < 5 * np.sqrt(0.25 / S)
 
 
-@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid", "checkpoint"])
 def test_noise_only_tree(ctx, trav):
     """Identity gates only (X twice) with strong noise: the tree is all
     error branches; every traversal equals the oracle."""
@@ -149,3 +149,50 @@ def test_thermal_relaxation_noise_matches_oracle(ctx, precision):
     r = tq.tusq_run_tree(ctx, ec, t, o)
     tol = 1e-10 if precision == "c128" else 1e-4
     np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("n,kmax", [(10, 6), (18, 12)])
+def test_checkpoint_traversal_matches_oracle(ctx, precision, n, kmax):
+    """Branch checkpoints kept in device memory: the distribution equals the
+    oracle's, no gate or Pauli is ever undone, and the save and restore
+    counts equal the oracle's walk of the same tree."""
+    _say(f"[gpu] checkpoint n={n} kmax={kmax} {precision}")
+    c = brickwork(n, 8, 3e-3, 2e-2, 31)
+    S, seed = 4000, 13
+    ot = oracle.ecm(c, S, seed)
+    dist, _, oc, _ = oracle.run(c, ot, seed, traversal="checkpoint", want_samples=False)
+    t, r = _run(ctx, c, S, seed, traversal="checkpoint", precision=precision,
+                fusion_max_qubits=kmax, drift_bound=1.0)
+    assert t.serialize() == ot.serialize()
+    tol = 1e-10 if precision == "c128" else 1e-4
+    np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
+    ct = r.counters()
+    assert ct["inv_gates"] == 0 and ct["inv_paulis"] == 0
+    for k in ("checkpoint_saves", "checkpoint_restores", "resets", "leaves"):
+        assert ct[k] == oc[k], k
+    assert ct["checkpoint_restores"] == ot.n_leaves - 1
+
+
+def test_checkpoint_budget_is_enforced(ctx):
+    """A budget that holds the state but not its checkpoints is refused
+    before any device work, and the same run fits with plain DFTT."""
+    _say("[gpu] checkpoint budget")
+    c = brickwork(16, 6, 5e-3, 3e-2, 3)
+    N, S = 1 << 16, 3000
+    ot = oracle.ecm(c, S, 2)
+    _, _, oc, _ = oracle.run(c, ot, 2, traversal="checkpoint", want_dist=False,
+                             want_samples=False)
+    assert oc["checkpoint_saves"] > 0
+    # a job's device memory: state, FP64 accumulator, sampler chunk sums and
+    # prefix, samples and a 64 MiB plan reserve; half a state more is too
+    # little for one checkpoint slot
+    job = N * 16 + N * 8 + 2 * (N >> 11) * 8 + S * 8 + (64 << 20)
+    small = tq.Context(0, hbm_budget=job + N * 8)
+    try:
+        _run(small, c, S, 2)
+        with pytest.raises(tq.TusqError) as e:
+            _run(small, c, S, 2, traversal="checkpoint")
+        assert e.value.code == -2 and "checkpoint" in str(e.value)
+    finally:
+        small.close()

@@ -64,7 +64,7 @@ def _check_samples(c, ot, seed, samples, lb=0, le=None):
 
 
 @pytest.mark.parametrize("prune", [True, False])
-@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid"])
+@pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid", "checkpoint"])
 def test_config0_brickwork_8q(ctx, prune, trav):
     _say(f"[gpu] config0 prune={prune} trav={trav}")
     c = brickwork(8, 20, 1e-3, 1e-2, 1)
@@ -77,7 +77,8 @@ def test_config0_brickwork_8q(ctx, prune, trav):
     ex = _check_samples(c, ot, seed, r.samples())
     assert ex <= 2
     ct = r.counters()
-    for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws"):
+    for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws",
+              "checkpoint_saves", "checkpoint_restores"):
         assert ct[k] == oc[k], k
     np.testing.assert_allclose(r.norms(ot.n_leaves), onorm, atol=1e-12)
 

@@ -356,7 +356,7 @@ def test_lossless_pipeline_equals_definition(fam):
     for commute in (False, True):
         t = oracle.ecm(c, S, seed, do_commute=commute, prune=False)
         assert int(t.count.sum()) == S
-        for trav in ("dftt", "naive", "hybrid"):
+        for trav in ("dftt", "naive", "hybrid", "checkpoint"):
             dist, _, _, _ = oracle.run(c, t, seed, traversal=trav, want_samples=False)
             np.testing.assert_allclose(dist, want, atol=1e-12)
 
@@ -436,6 +436,13 @@ def test_dftt_forward_tokens_equal_trie_size():
     _, _, chy, _ = oracle.run(c, t, 9, traversal="hybrid", want_dist=False, want_samples=False)
     tot = lambda x: x["fwd_gates"] + x["fwd_paulis"] + x["inv_gates"] + x["inv_paulis"]
     assert tot(chy) <= min(tot(ct), tot(cn))
+    # branch checkpoints: the same forward trie walk with every undo replaced
+    # by a restore, one save per branching node that still has siblings
+    _, _, cc, _ = oracle.run(c, t, 9, traversal="checkpoint", want_dist=False, want_samples=False)
+    assert cc["fwd_gates"] + cc["fwd_paulis"] == len(nodes)
+    assert cc["inv_gates"] + cc["inv_paulis"] == 0
+    assert cc["checkpoint_restores"] == t.n_leaves - 1
+    assert 1 <= cc["checkpoint_saves"] <= t.n_leaves - 1
 
 
 # --------------------------------------------------------------------------
