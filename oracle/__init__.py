@@ -21,9 +21,11 @@ from .oracle import (  # noqa: F401
     philox,
     roundtrip,
     run,
+    run_mcm,
     sample_shot,
     set_threads,
     thermal_probs,
     thresholds,
     trajectory,
+    uniform53,
 )

@@ -107,11 +107,33 @@ def channel_terms(kind: str, qubits, probs) -> List[Tuple[float, List[Tuple[int,
     return terms
 
 
+def measure_kraus(n: int, qubits: Sequence[int], reset: bool) -> List[np.ndarray]:
+    """Kraus operators of a Z-basis measurement of `qubits` whose outcome is
+    discarded: the projectors onto each outcome pattern, each followed (for a
+    reset) by the X flips that return the measured qubits to 0."""
+    out = []
+    N = 1 << n
+    for o in range(1 << len(qubits)):
+        K = np.zeros((N, N), dtype=np.complex128)
+        for i in range(N):
+            if all(((i >> q) & 1) == ((o >> b) & 1) for b, q in enumerate(qubits)):
+                j = i
+                if reset:
+                    for q in qubits:
+                        j &= ~(1 << q)
+                K[j, i] = 1.0
+        out.append(K)
+    return out
+
+
 def density_matrix(circ) -> np.ndarray:
     n = circ.n
     rho = np.zeros((1 << n, 1 << n), dtype=np.complex128)
     rho[0, 0] = 1.0
     for kind, qs, pr, noise in zip(circ.kinds, circ.qubits, circ.params, circ.noise):
+        if kind in ("M", "MR"):
+            rho = sum(K @ rho @ K.conj().T for K in measure_kraus(n, qs, kind == "MR"))
+            continue
         U = gate_full(n, kind, qs, pr)
         rho = U @ rho @ U.conj().T
         if noise is not None:

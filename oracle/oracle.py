@@ -16,7 +16,7 @@ _SRC = os.path.join(_HERE, "tusq_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 KIND_CODES = {name: i for i, name in enumerate(
-    ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX"))}
+    ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX", "M", "MR"))}
 
 
 def build_library(force: bool = False) -> str:
@@ -65,6 +65,11 @@ def lib():
                                      C.c_void_p, C.c_void_p]
         L.oc_commute.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p, C.c_int,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oc_run_mcm.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64,
+                                 C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oc_uniform53.restype = C.c_double
+        L.oc_uniform53.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                   C.c_int]
     return _lib
 
 
@@ -267,7 +272,8 @@ def ecm(circ, shots: int, seed: int, do_commute: bool = True, prune: bool = True
 
 
 COUNTER_NAMES = ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
-                 "draws", "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores")
+                 "draws", "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores",
+                 "mcm_edges", "paper_ops")
 TRAVERSAL = {"dftt": 0, "naive": 1, "hybrid": 2, "checkpoint": 3}
 
 
@@ -291,6 +297,37 @@ def run(circ, tree: OracleTree, seed: int, traversal: str = "dftt", leaf_begin: 
     counters = {k: int(v) for k, v in zip(COUNTER_NAMES, ctr)}
     return dist, (samples[:nshots] if samples is not None else None), counters, \
         norms[: le - leaf_begin]
+
+
+def run_mcm(circ, tree: OracleTree, seed: int, cache_capacity: int, leaf_begin: int = 0,
+            leaf_end: int = 0, want_dist: bool = True, want_samples: bool = True):
+    """DFTT+Caching over a tree whose circuit has measurement layers (Sec.
+    III-B.2) with a LIFO cache of `cache_capacity` pre-measurement states
+    (0: every leaf from the root).  Returns (dist or None, samples or None,
+    counters dict, most states cached at once).  Checkpoint saves/restores
+    count cache pushes/fetches; paper_ops is the operation count of Eq. (3)."""
+    h = _CircuitHandle(circ)
+    le = leaf_end or tree.n_leaves
+    dist = np.zeros(1 << circ.n, np.float64) if want_dist else None
+    nshots = int(tree.shots[leaf_begin:le].sum())
+    samples = np.zeros(max(nshots, 1), np.uint64) if want_samples else None
+    ctr = np.zeros(len(COUNTER_NAMES), np.uint64)
+    st = np.zeros(1, np.uint64)
+    rc = lib().oc_run_mcm(h.ref, C.c_void_p(tree.handle), C.c_uint64(seed),
+                          C.c_uint32(cache_capacity), C.c_uint64(leaf_begin), C.c_uint64(le),
+                          _ptr(dist) if dist is not None else None,
+                          _ptr(samples) if samples is not None else None, _ptr(ctr), _ptr(st))
+    if rc:
+        raise ValueError(f"oracle measurement walk failed ({rc})")
+    counters = {k: int(v) for k, v in zip(COUNTER_NAMES, ctr)}
+    return dist, (samples[:nshots] if samples is not None else None), counters, int(st[0])
+
+
+def uniform53(seed: int, sub: int, primary: int, aux: int, stream: int, half: int = 0) -> float:
+    """(v >> 11) 2^-53 of one Philox draw with counter (sub, primary, aux,
+    stream) and key seed."""
+    return float(lib().oc_uniform53(C.c_uint64(seed), C.c_uint32(sub), C.c_uint32(primary),
+                                    C.c_uint32(aux), C.c_uint32(stream), C.c_int(half)))
 
 
 def leaf_margins(circ, state: np.ndarray, seed: int, leaf: int, shots: int):

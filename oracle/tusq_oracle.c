@@ -24,6 +24,9 @@
  *   Sec. III-A.4, Eq. (2)   pruning with alpha, beta; S_final
  *   Sec. III-B              DFTT: forward = U, backtrack = U^-1
  *   Sec. III-B.1            T_dftt = 2|E|, T_naive = N_l * h
+ *   Sec. III-B.2, Eq. (3)   non-invertible edges (mid-circuit measurement
+ *                           layers), DFTT+Caching with a LIFO cache of
+ *                           capacity K, alpha(K)
  *
  * Parity status: every function here is pinned by tests against values
  * that do not come from this file (published Philox vectors, density-matrix
@@ -43,7 +46,11 @@
 /* ------------------------------------------------------------------------ */
 /* Gate kinds (the oracle's own numbering; the Python wrapper maps names).   */
 enum { OK_U3 = 0, OK_RX, OK_RY, OK_RZ, OK_H, OK_S, OK_SDG, OK_T, OK_TDG,
-       OK_X, OK_Y, OK_Z, OK_CX, OK_NKINDS };
+       OK_X, OK_Y, OK_Z, OK_CX, OK_M, OK_MR, OK_NKINDS };
+/* OK_M / OK_MR: a layer of concurrent Z-basis measurements (MR: the measured
+ * qubits are reset to |0> afterwards).  Its qubit set is a 64-bit mask held
+ * as q0 (low word) and q1 (high word); at most 8 qubits, no noise channel. */
+#define MAX_MEASURED 8
 
 /* Pauli codes: I=0, X=1, Y=2, Z=3. */
 
@@ -158,12 +165,29 @@ typedef struct {
 } prep_t;
 
 static int is_two_qubit(uint8_t k) { return k == OK_CX; }
+static int is_measure(uint8_t k) { return k == OK_M || k == OK_MR; }
+static uint64_t meas_mask(const oc_circuit *c, uint32_t g)
+{
+    return (uint64_t)c->q0[g] | ((uint64_t)c->q1[g] << 32);
+}
+static int has_measure(const oc_circuit *c)
+{
+    for (uint32_t g = 0; g < c->G; ++g) if (is_measure(c->kind[g])) return 1;
+    return 0;
+}
 
 static int validate(const oc_circuit *c)
 {
     size_t off = 0;
     for (uint32_t g = 0; g < c->G; ++g) {
         if (c->kind[g] >= OK_NKINDS) return -1;
+        if (is_measure(c->kind[g])) {
+            uint64_t mk = meas_mask(c, g);
+            if (!mk || (c->n < 64 && (mk >> c->n)) || __builtin_popcountll(mk) > MAX_MEASURED ||
+                c->nprob[g])
+                return -1;
+            continue;
+        }
         if (c->q0[g] >= c->n) return -1;
         if (is_two_qubit(c->kind[g]) && (c->q1[g] >= c->n || c->q1[g] == c->q0[g])) return -1;
         int m = c->nprob[g];
@@ -335,6 +359,11 @@ static void stacks_alloc(stacks_t *S, const oc_circuit *c)
     S->st = calloc(c->n, sizeof(stack_t_));
     size_t *cnt = calloc(c->n, sizeof(size_t));
     for (uint32_t g = 0; g < c->G; ++g) {
+        if (is_measure(c->kind[g])) {
+            for (uint32_t q = 0; q < c->n; ++q)
+                if ((meas_mask(c, g) >> q) & 1) cnt[q]++;
+            continue;
+        }
         cnt[c->q0[g]]++;
         if (is_two_qubit(c->kind[g])) cnt[c->q1[g]]++;
     }
@@ -361,6 +390,13 @@ static int commute_one(const prep_t *P, stacks_t *S, int nraw, const uint32_t *c
     int ri = 0;
     for (uint32_t g = 0; g < c->G; ++g) {
         uint8_t k = c->kind[g];
+        if (is_measure(k)) {
+            /* no noisy gate moves through a measurement of its qubit: it
+             * stays below and is reported at the measurement's slot */
+            for (uint32_t q = 0; q < c->n; ++q)
+                if ((meas_mask(c, g) >> q) & 1) push(&S->st[q], (int32_t)g);
+            continue;
+        }
         if (is_two_qubit(k)) {
             stack_t_ *sc = &S->st[c->q0[g]], *stt = &S->st[c->q1[g]];
             int pc = 0, pt = 0;
@@ -920,8 +956,10 @@ static uint64_t leaf_tokens(const oc_circuit *c, const uint64_t *keys, uint64_t 
     return k;
 }
 
+/* ops: the paper's operation count (Sec. III-B.2): 1 per 1-qubit matrix
+ * (gate or Pauli), 4 per 2-qubit matrix, 1 per forward measurement edge. */
 typedef struct { uint64_t fwd_gates, inv_gates, fwd_paulis, inv_paulis, resets, leaves, draws,
-                          ret_gates, ret_paulis, saves, restores; } counters_t;
+                          ret_gates, ret_paulis, saves, restores, mcm, ops; } counters_t;
 
 static void apply_token(const oc_circuit *c, const uint64_t *keys, int64_t t, cplx *psi,
                         int inverse, counters_t *ct)
@@ -929,10 +967,12 @@ static void apply_token(const oc_circuit *c, const uint64_t *keys, int64_t t, cp
     if (t >= 0) {
         apply_gate(c, (uint32_t)t, psi, inverse);
         if (inverse) ct->inv_gates++; else ct->fwd_gates++;
+        ct->ops += is_two_qubit(c->kind[t]) ? 4 : 1;
     } else {
         uint64_t k = keys[-t - 1];
         apply_pauli(psi, c->n, EV_QUBIT(k), EV_PAULI(k));
         if (inverse) ct->inv_paulis++; else ct->fwd_paulis++;
+        ct->ops += 1;
     }
 }
 
@@ -955,7 +995,7 @@ static uint64_t shared_depth(const oc_circuit *c, const uint64_t *a, uint64_t na
 int oc_trajectory(const oc_circuit *c, uint32_t ne, const uint32_t *slot, const uint32_t *qubit,
                   const uint8_t *pauli, uint64_t max_tokens, double *state_out)
 {
-    if (validate(c)) return -1;
+    if (validate(c) || has_measure(c)) return -1;
     uint64_t *keys = malloc(sizeof(uint64_t) * (ne + 1));
     for (uint32_t i = 0; i < ne; ++i) keys[i] = EVKEY(slot[i], qubit[i], pauli[i]);
     for (uint32_t i = 1; i < ne; ++i) if (keys[i] <= keys[i - 1]) { free(keys); return -1; }
@@ -975,7 +1015,7 @@ int oc_trajectory(const oc_circuit *c, uint32_t ne, const uint32_t *slot, const 
 int oc_roundtrip(const oc_circuit *c, uint32_t ne, const uint32_t *slot, const uint32_t *qubit,
                  const uint8_t *pauli, uint64_t depth, double *maxdiff)
 {
-    if (validate(c)) return -1;
+    if (validate(c) || has_measure(c)) return -1;
     uint64_t N = 1ull << c->n;
     uint64_t *keys = malloc(sizeof(uint64_t) * (ne + 1));
     for (uint32_t i = 0; i < ne; ++i) keys[i] = EVKEY(slot[i], qubit[i], pauli[i]);
@@ -1025,6 +1065,7 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
            uint64_t le, double *dist, uint64_t *samples, uint64_t *counters, double *norms)
 {
     if (validate(c)) return -1;
+    if (has_measure(c)) return -3;  /* non-invertible edges: oc_run_mcm */
     if (le == 0 && lb == 0) le = t->n_leaves;
     if (lb > le || le > t->n_leaves) return -1;
     uint64_t N = 1ull << c->n;
@@ -1158,4 +1199,390 @@ int oc_leaf_margins(const oc_circuit *c, const double *state, uint64_t seed, uin
     }
     free(cdf);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-invertible edges: mid-circuit measurement layers (Sec. III-B.2).
+ *
+ * Semantics (readings; the paper fixes the tree structure and the caching
+ * protocol, not the trajectory rule):
+ *   - a layer of m <= 8 measured qubits q_0 < ... < q_{m-1} is one edge;
+ *     outcome o has bit b = the value of q_b, weight P_o = the sum of
+ *     |psi_i|^2 over the basis states i of that pattern (left to right);
+ *   - every shot picks its own outcome: shot j (0-based within leaf l) at
+ *     layer k draws v on stream 3, counter (j, l, k), half 0;
+ *     u = (v >> 11) 2^-53, and the outcome is the smallest o with
+ *     u T < C_o, C_o = P_0 + ... + P_o, T = C_{2^m-1} (if rounding leaves
+ *     none, the last o with P_o > 0);
+ *   - the state becomes P_o psi / sqrt(P_o); MR then flips the measured
+ *     qubits back to 0 (psi'[i] = psi[i ^ deposit(o)] / sqrt(P_o) on the
+ *     all-zero pattern);
+ *   - a node's shots thereby split into outcome branches; a final leaf
+ *     reached with c shots of tree leaf l weighs c / S (trees without
+ *     pruning only).
+ *
+ * DFTT+Caching with cache capacity K, over stages (stage s = the tokens
+ * between layers s-1 and s):
+ *   - within a stage the walk is plain DFTT: undo to the node shared with
+ *     the next path, then go down;
+ *   - a pre-measurement node of layer k is pushed on the LIFO cache when
+ *     the walk reaches it if k is one of the K layers closest to the leaves
+ *     (k >= M - K), and popped once all of its outcome branches are done;
+ *   - crossing a measurement edge backwards fetches the node from the
+ *     cache; an uncached node is recomputed from the root (replaying the
+ *     recorded outcomes), after which the walk continues with DFTT;
+ *   - K = 0 switches DFTT off: every final leaf is computed from the root.
+ * Samples: final leaf (l, c shots) draws c indices with the shot-sampling
+ * stream, counter (d >> 1, l, 0), half d & 1, d running over the draws of
+ * tree leaf l in walk order.
+ * The operation counts of Eq. (3): 1 per 1-qubit matrix, 4 per CX, 1 per
+ * forward measurement edge, 0 for a fetch; N_1 is the count with K = 0 and
+ * N_2 the count with K >= M (every pre-measurement node cached). */
+
+typedef struct {
+    uint64_t n;
+    uint64_t *leaf;   /* tree leaf of entry i */
+    uint64_t *off;    /* shots of entry i: shot[off[i] .. off[i+1]) */
+    uint32_t *shot;
+} mgroup_t;
+
+typedef struct {
+    const oc_circuit *c;
+    const oc_tree *t;
+    uint64_t seed, N, lb;
+    uint32_t M, K;
+    int naive;
+    uint32_t *lgate;          /* gate index of layer k */
+    int64_t **tok;            /* per leaf in range: token list */
+    uint64_t *ntok;
+    uint64_t **lpos;          /* per leaf: token position of layer k */
+    cplx *psi, *tmp;
+    cplx **cache;             /* per layer (only cached layers used) */
+    uint64_t *rep;            /* per stage: a leaf of the current path */
+    uint32_t *out;            /* per layer: outcome of the current path */
+    double *dist, *cdf;
+    uint64_t *samples, so, *sbase;
+    counters_t ct;
+    uint64_t max_cached;
+    uint64_t cached_now;
+} mwalk_t;
+
+static const uint64_t *mw_keys(const mwalk_t *W, uint64_t l) { return W->t->ev_key + W->t->ev_off[l]; }
+static uint64_t st_begin(const mwalk_t *W, uint64_t l, uint32_t s)
+{
+    return s == 0 ? 0 : W->lpos[l - W->lb][s - 1] + 1;
+}
+static uint64_t st_end(const mwalk_t *W, uint64_t l, uint32_t s)
+{
+    return s < W->M ? W->lpos[l - W->lb][s] : W->ntok[l - W->lb];
+}
+static int tok_same(const mwalk_t *W, uint64_t la, int64_t ta, uint64_t lb_, int64_t tb)
+{
+    if ((ta >= 0) != (tb >= 0)) return 0;
+    if (ta >= 0) return ta == tb;
+    return mw_keys(W, la)[-ta - 1] == mw_keys(W, lb_)[-tb - 1];
+}
+/* tokens the stage-s parts of leaves a and b share from the stage start */
+static uint64_t stage_lcp(const mwalk_t *W, uint64_t a, uint64_t b, uint32_t s)
+{
+    uint64_t a0 = st_begin(W, a, s), a1 = st_end(W, a, s);
+    uint64_t b0 = st_begin(W, b, s), b1 = st_end(W, b, s);
+    uint64_t d = 0;
+    while (a0 + d < a1 && b0 + d < b1 &&
+           tok_same(W, a, W->tok[a - W->lb][a0 + d], b, W->tok[b - W->lb][b0 + d]))
+        ++d;
+    return d;
+}
+static void fwd_range(mwalk_t *W, uint64_t l, uint32_t s, uint64_t from, uint64_t to)
+{
+    uint64_t b = st_begin(W, l, s);
+    for (uint64_t i = from; i < to; ++i)
+        apply_token(W->c, mw_keys(W, l), W->tok[l - W->lb][b + i], W->psi, 0, &W->ct);
+}
+static void inv_range(mwalk_t *W, uint64_t l, uint32_t s, uint64_t from, uint64_t to)
+{
+    uint64_t b = st_begin(W, l, s);
+    for (uint64_t i = from; i > to; --i)
+        apply_token(W->c, mw_keys(W, l), W->tok[l - W->lb][b + i - 1], W->psi, 1, &W->ct);
+}
+
+/* outcome weights of layer k's qubits over the current state */
+static void layer_weights(const mwalk_t *W, uint32_t k, double *P, uint32_t *qs, uint32_t *m)
+{
+    uint64_t mk = meas_mask(W->c, W->lgate[k]);
+    uint32_t mm = 0;
+    for (uint32_t q = 0; q < W->c->n; ++q) if ((mk >> q) & 1) qs[mm++] = q;
+    *m = mm;
+    for (uint32_t o = 0; o < (1u << mm); ++o) P[o] = 0.0;
+    for (uint64_t i = 0; i < W->N; ++i) {
+        uint32_t o = 0;
+        for (uint32_t b = 0; b < mm; ++b) o |= (uint32_t)((i >> qs[b]) & 1) << b;
+        P[o] = P[o] + (creal(W->psi[i]) * creal(W->psi[i]) + cimag(W->psi[i]) * cimag(W->psi[i]));
+    }
+}
+
+static uint32_t pick_branch(const double *P, uint32_t no, double u)
+{
+    double T = 0.0;
+    for (uint32_t o = 0; o < no; ++o) T = T + P[o];
+    double x = u * T, C = 0.0;
+    for (uint32_t o = 0; o < no; ++o) {
+        C = C + P[o];
+        if (x < C) return o;
+    }
+    uint32_t o = no - 1;
+    while (o > 0 && P[o] == 0.0) --o;
+    return o;
+}
+
+/* measurement edge of layer k with outcome o: project, renormalise, reset */
+static void apply_mcm(mwalk_t *W, uint32_t k, uint32_t o)
+{
+    double P[1 << MAX_MEASURED];
+    uint32_t qs[MAX_MEASURED], m;
+    layer_weights(W, k, P, qs, &m);
+    int reset = W->c->kind[W->lgate[k]] == OK_MR;
+    uint64_t dep = 0;
+    for (uint32_t b = 0; b < m; ++b) if ((o >> b) & 1) dep |= 1ull << qs[b];
+    uint32_t want = reset ? 0u : o;
+    uint64_t flip = reset ? dep : 0;
+    double sc = 1.0 / sqrt(P[o]);
+    for (uint64_t i = 0; i < W->N; ++i) {
+        uint32_t pat = 0;
+        for (uint32_t b = 0; b < m; ++b) pat |= (uint32_t)((i >> qs[b]) & 1) << b;
+        W->tmp[i] = pat == want ? W->psi[i ^ flip] * sc : 0.0;
+    }
+    memcpy(W->psi, W->tmp, sizeof(cplx) * W->N);
+    W->ct.mcm++;
+    W->ct.ops++;
+}
+
+static int layer_cached(const mwalk_t *W, uint32_t k)
+{
+    return !W->naive && W->K > 0 && k + W->K >= W->M;
+}
+
+static void reach_pre(mwalk_t *W, uint32_t k);
+/* state := the root of stage s on the current path */
+static void reach_root(mwalk_t *W, uint32_t s)
+{
+    if (s == 0) {
+        reset_state(W->psi, W->c->n);
+        W->ct.resets++;
+        return;
+    }
+    reach_pre(W, s - 1);
+    apply_mcm(W, s - 1, W->out[s - 1]);
+}
+/* state := the pre-measurement node of layer k on the current path */
+static void reach_pre(mwalk_t *W, uint32_t k)
+{
+    if (layer_cached(W, k)) {
+        memcpy(W->psi, W->cache[k], sizeof(cplx) * W->N);
+        W->ct.restores++;
+        return;
+    }
+    reach_root(W, k);
+    uint64_t l = W->rep[k];
+    fwd_range(W, l, k, 0, st_end(W, l, k) - st_begin(W, l, k));
+}
+
+static void final_leaf(mwalk_t *W, uint64_t l, uint64_t c)
+{
+    double w = (double)c / (double)W->t->S, nrm = 0.0;
+    for (uint64_t i = 0; i < W->N; ++i) {
+        double pr = creal(W->psi[i]) * creal(W->psi[i]) + cimag(W->psi[i]) * cimag(W->psi[i]);
+        nrm = nrm + pr;
+        if (W->dist) W->dist[i] = W->dist[i] + w * pr;
+        if (W->cdf) W->cdf[i] = nrm;
+    }
+    if (W->samples) {
+        for (uint64_t k = 0; k < c; ++k) {
+            uint64_t d = W->sbase[l - W->lb] + k;
+            uint64_t v = draw64(W->seed, (uint32_t)(d >> 1), (uint32_t)l, 0, 2, (int)(d & 1));
+            double u = (double)(v >> 11) * 0x1p-53;
+            W->samples[W->so++] = draw_index(W->cdf, W->N, u * nrm);
+        }
+    }
+    W->sbase[l - W->lb] += c;
+    W->ct.leaves++;
+    W->ct.draws += c;
+}
+
+static int mwalk(mwalk_t *W, uint32_t s, const mgroup_t *G)
+{
+    uint64_t i = 0, prev = UINT64_MAX;
+    int valid = 1;
+    while (i < G->n) {
+        uint64_t l = G->leaf[i], j = i + 1;
+        uint64_t len = st_end(W, l, s) - st_begin(W, l, s);
+        while (j < G->n) {
+            uint64_t l2 = G->leaf[j];
+            if (st_end(W, l2, s) - st_begin(W, l2, s) != len || stage_lcp(W, l, l2, s) != len) break;
+            ++j;
+        }
+        if (prev != UINT64_MAX) {
+            uint64_t lp = G->leaf[prev];
+            uint64_t d = stage_lcp(W, lp, l, s);
+            if (valid && !W->naive) {
+                inv_range(W, lp, s, st_end(W, lp, s) - st_begin(W, lp, s), d);
+            } else {
+                reach_root(W, s);
+                fwd_range(W, l, s, 0, d);
+            }
+            fwd_range(W, l, s, d, len);
+        } else {
+            fwd_range(W, l, s, 0, len);
+        }
+        if (s == W->M) {
+            if (j != i + 1) return -2;  /* distinct leaves differ somewhere */
+            final_leaf(W, l, G->off[i + 1] - G->off[i]);
+            valid = !W->naive;
+        } else {
+            W->rep[s] = l;
+            double P[1 << MAX_MEASURED];
+            uint32_t qs[MAX_MEASURED], m;
+            layer_weights(W, s, P, qs, &m);
+            uint32_t no = 1u << m;
+            /* split the shots of entries i..j-1 by outcome */
+            uint64_t tot = G->off[j] - G->off[i];
+            uint32_t *oc = malloc(sizeof(uint32_t) * (tot + 1));
+            uint64_t *cnt = calloc(no, sizeof(uint64_t));
+            for (uint64_t e = i; e < j; ++e)
+                for (uint64_t x = G->off[e]; x < G->off[e + 1]; ++x) {
+                    uint64_t v = draw64(W->seed, G->shot[x], (uint32_t)G->leaf[e], s, 3, 0);
+                    uint32_t o = pick_branch(P, no, (double)(v >> 11) * 0x1p-53);
+                    oc[x - G->off[i]] = o;
+                    cnt[o]++;
+                }
+            int cached = layer_cached(W, s);
+            if (cached) {
+                memcpy(W->cache[s], W->psi, sizeof(cplx) * W->N);
+                W->ct.saves++;
+                W->cached_now++;
+                if (W->cached_now > W->max_cached) W->max_cached = W->cached_now;
+            }
+            int first = 1;
+            for (uint32_t o = 0; o < no; ++o) {
+                if (!cnt[o]) continue;
+                mgroup_t H;
+                H.leaf = malloc(sizeof(uint64_t) * (j - i));
+                H.off = malloc(sizeof(uint64_t) * (j - i + 1));
+                H.shot = malloc(sizeof(uint32_t) * (cnt[o] + 1));
+                H.n = 0;
+                H.off[0] = 0;
+                uint64_t y = 0;
+                for (uint64_t e = i; e < j; ++e) {
+                    uint64_t y0 = y;
+                    for (uint64_t x = G->off[e]; x < G->off[e + 1]; ++x)
+                        if (oc[x - G->off[i]] == o) H.shot[y++] = G->shot[x];
+                    if (y > y0) { H.leaf[H.n] = G->leaf[e]; H.off[++H.n] = y; }
+                }
+                if (!first) reach_pre(W, s);
+                W->out[s] = o;
+                apply_mcm(W, s, o);
+                int rc = mwalk(W, s + 1, &H);
+                free(H.leaf); free(H.off); free(H.shot);
+                if (rc) { free(oc); free(cnt); return rc; }
+                first = 0;
+            }
+            free(oc); free(cnt);
+            if (cached) {
+                memcpy(W->psi, W->cache[s], sizeof(cplx) * W->N);
+                W->ct.restores++;
+                W->cached_now--;
+                valid = 1;
+            } else {
+                valid = 0;
+            }
+        }
+        prev = i;
+        i = j;
+    }
+    return 0;
+}
+
+/* counters as oc_run's, then the measurement edges applied and the
+ * operation count; stats[0] = most states held in the cache at once. */
+int oc_run_mcm(const oc_circuit *c, const oc_tree *t, uint64_t seed, uint32_t K, uint64_t lb,
+               uint64_t le, double *dist, uint64_t *samples, uint64_t *counters, uint64_t *stats)
+{
+    if (validate(c)) return -1;
+    if (le == 0 && lb == 0) le = t->n_leaves;
+    if (lb > le || le > t->n_leaves) return -1;
+    for (uint64_t l = lb; l < le; ++l)
+        if (t->shots[l] != t->count[l] || t->wnum[l] != t->count[l] || t->wden[l] != t->S)
+            return -4;  /* pruned trees are not split into outcome branches */
+    mwalk_t W;
+    memset(&W, 0, sizeof(W));
+    W.c = c; W.t = t; W.seed = seed; W.N = 1ull << c->n; W.lb = lb;
+    W.naive = K == 0;
+    uint32_t M = 0;
+    for (uint32_t g = 0; g < c->G; ++g) M += is_measure(c->kind[g]) ? 1 : 0;
+    W.M = M;
+    W.K = K > M ? M : K;
+    W.lgate = malloc(sizeof(uint32_t) * (M + 1));
+    for (uint32_t g = 0, k = 0; g < c->G; ++g) if (is_measure(c->kind[g])) W.lgate[k++] = g;
+    uint64_t L = le - lb;
+    W.tok = calloc(L + 1, sizeof(int64_t *));
+    W.ntok = calloc(L + 1, sizeof(uint64_t));
+    W.lpos = calloc(L + 1, sizeof(uint64_t *));
+    for (uint64_t l = lb; l < le; ++l) {
+        uint64_t ne = t->ev_off[l + 1] - t->ev_off[l];
+        W.tok[l - lb] = malloc(sizeof(int64_t) * (c->G + ne + 1));
+        W.ntok[l - lb] = leaf_tokens(c, t->ev_key + t->ev_off[l], ne, W.tok[l - lb]);
+        W.lpos[l - lb] = malloc(sizeof(uint64_t) * (M + 1));
+        for (uint64_t i = 0, k = 0; i < W.ntok[l - lb]; ++i) {
+            int64_t tk = W.tok[l - lb][i];
+            if (tk >= 0 && is_measure(c->kind[tk])) W.lpos[l - lb][k++] = i;
+        }
+    }
+    W.psi = malloc(sizeof(cplx) * W.N);
+    W.tmp = malloc(sizeof(cplx) * W.N);
+    W.cache = calloc(M + 1, sizeof(cplx *));
+    for (uint32_t k = 0; k < M; ++k)
+        if (layer_cached(&W, k)) W.cache[k] = malloc(sizeof(cplx) * W.N);
+    W.rep = calloc(M + 1, sizeof(uint64_t));
+    W.out = calloc(M + 1, sizeof(uint32_t));
+    W.dist = dist;
+    if (dist) for (uint64_t i = 0; i < W.N; ++i) dist[i] = 0.0;
+    W.samples = samples;
+    W.cdf = samples ? malloc(sizeof(double) * W.N) : NULL;
+    W.sbase = calloc(L + 1, sizeof(uint64_t));
+    /* the root group: every leaf in range with all of its shots */
+    mgroup_t G;
+    uint64_t tot = 0;
+    for (uint64_t l = lb; l < le; ++l) tot += t->shots[l];
+    G.n = L;
+    G.leaf = malloc(sizeof(uint64_t) * (L + 1));
+    G.off = malloc(sizeof(uint64_t) * (L + 1));
+    G.shot = malloc(sizeof(uint32_t) * (tot + 1));
+    G.off[0] = 0;
+    for (uint64_t l = lb, y = 0; l < le; ++l) {
+        G.leaf[l - lb] = l;
+        for (uint64_t j = 0; j < t->shots[l]; ++j) G.shot[y++] = (uint32_t)j;
+        G.off[l - lb + 1] = G.off[l - lb] + t->shots[l];
+    }
+    int rc = 0;
+    if (L > 0) {
+        reset_state(W.psi, c->n);
+        W.ct.resets++;
+        rc = mwalk(&W, 0, &G);
+    }
+    if (counters) memcpy(counters, &W.ct, sizeof(W.ct));
+    if (stats) stats[0] = W.max_cached;
+    for (uint64_t l = 0; l < L; ++l) { free(W.tok[l]); free(W.lpos[l]); }
+    for (uint32_t k = 0; k < M; ++k) free(W.cache[k]);
+    free(W.tok); free(W.ntok); free(W.lpos); free(W.cache); free(W.rep); free(W.out);
+    free(W.psi); free(W.tmp); free(W.cdf); free(W.sbase); free(W.lgate);
+    free(G.leaf); free(G.off); free(G.shot);
+    return rc;
+}
+
+/* One uniform double in [0, 1) of the method's streams: (v >> 11) 2^-53 with
+ * v = draw64(seed, counter (sub, primary, aux, stream), half). */
+double oc_uniform53(uint64_t seed, uint32_t sub, uint32_t primary, uint32_t aux, uint32_t stream,
+                    int half)
+{
+    return (double)(draw64(seed, sub, primary, aux, stream, half) >> 11) * 0x1p-53;
 }

@@ -22,6 +22,7 @@ Paulis each with p/15), attached after the gate it follows.
 
 from .circuits import (  # noqa: F401
     GATE_NAMES,
+    MEASURE_KINDS,
     Circuit,
     brickwork,
     ising,
@@ -30,4 +31,5 @@ from .circuits import (  # noqa: F401
     batch_jobs,
     serving_requests,
     random_small_circuit,
+    syndrome_rounds,
 )

@@ -25,6 +25,10 @@ import numpy as np
 GATE_NAMES = ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX")
 TWO_QUBIT = frozenset({"CX"})
 N_PARAMS = {"U3": 3, "RX": 1, "RY": 1, "RZ": 1}
+# mid-circuit Z-basis measurement layers: "M" keeps the measured qubits in
+# their outcome, "MR" resets them to |0> afterwards
+MEASURE_KINDS = ("M", "MR")
+MAX_MEASURED = 8
 
 
 @dataclass
@@ -54,9 +58,29 @@ class Circuit:
         self.noise.append(noise)
         return len(self.kinds) - 1
 
+    def add_measure(self, qubits: Sequence[int], reset: bool = True) -> int:
+        """A layer of concurrent Z-basis measurements of `qubits` (at most
+        8, distinct), one non-invertible edge of the circuit tree; with
+        `reset` the measured qubits are returned to |0>.  Carries no noise
+        channel."""
+        qs = tuple(sorted(int(q) for q in qubits))
+        if not qs or len(qs) > MAX_MEASURED or len(set(qs)) != len(qs):
+            raise ValueError(f"a measurement layer takes 1..{MAX_MEASURED} distinct qubits")
+        if qs[0] < 0 or qs[-1] >= self.n:
+            raise ValueError("measured qubit out of range")
+        self.kinds.append("MR" if reset else "M")
+        self.qubits.append(qs)
+        self.params.append((0.0, 0.0, 0.0))
+        self.noise.append(None)
+        return len(self.kinds) - 1
+
     @property
     def n_gates(self) -> int:
         return len(self.kinds)
+
+    @property
+    def n_measure_layers(self) -> int:
+        return sum(1 for k in self.kinds if k in MEASURE_KINDS)
 
     @property
     def n_channels(self) -> int:
@@ -72,6 +96,13 @@ class Circuit:
         q0 = np.zeros(G, dtype=np.uint32)
         q1 = np.zeros(G, dtype=np.uint32)
         for g, qs in enumerate(self.qubits):
+            if self.kinds[g] in MEASURE_KINDS:
+                # a measurement layer's qubit set as a 64-bit mask split
+                # over the two qubit fields (low word, high word)
+                mask = sum(1 << q for q in qs)
+                q0[g] = mask & 0xFFFFFFFF
+                q1[g] = mask >> 32
+                continue
             q0[g] = qs[0]
             q1[g] = qs[1] if len(qs) > 1 else 0
         params = np.array(self.params, dtype=np.float64).reshape(G, 3)
@@ -124,6 +155,28 @@ def bell_pair(p_h: float = 0.0, p_cx: float = 0.0) -> Circuit:
     c = Circuit(2, name="bell")
     c.add("H", (0,), (), depol1(p_h) if p_h > 0 else None)
     c.add("CX", (0, 1), (), depol2(p_cx) if p_cx > 0 else None)
+    return c
+
+
+def syndrome_rounds(d: int, rounds: int, p1: float, p2: float, theta: float = 0.0,
+                    reset: bool = True) -> Circuit:
+    """Repetition-code memory: data qubits 0..d-1, ancillas d..2d-2; an
+    optional RY(theta) on every data qubit first (theta != 0 makes the
+    measurement outcomes random), then per round CX(i, d+i), CX(i+1, d+i)
+    for every neighbour pair and one measurement layer of all ancillas
+    (with reset unless told otherwise).  Stands in for the surface-code
+    memory circuits with d rounds of mid-circuit measurement."""
+    if d < 2 or 2 * d - 1 > 64 or d - 1 > MAX_MEASURED:
+        raise ValueError("need 2 <= d <= 9")
+    c = Circuit(2 * d - 1, name=f"syndrome_d{d}_r{rounds}")
+    if theta:
+        for q in range(d):
+            c.add("RY", (q,), (theta,), depol1(p1) if p1 > 0 else None)
+    for _ in range(rounds):
+        for i in range(d - 1):
+            c.add("CX", (i, d + i), (), depol2(p2) if p2 > 0 else None)
+            c.add("CX", (i + 1, d + i), (), depol2(p2) if p2 > 0 else None)
+        c.add_measure(range(d, 2 * d - 1), reset=reset)
     return c
 
 
