@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 4u
+#define TUSQ_ABI_VERSION 5u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -60,6 +60,10 @@ enum {
     TUSQ_U3 = 0, TUSQ_RX, TUSQ_RY, TUSQ_RZ, TUSQ_H, TUSQ_S, TUSQ_SDG, TUSQ_T,
     TUSQ_TDG, TUSQ_X, TUSQ_Y, TUSQ_Z, TUSQ_CX, TUSQ_NUM_KINDS
 };
+/* kinds of the mid-circuit measurement layers tusq_circuit_measure appends
+ * (not accepted by tusq_circuit_gate) */
+enum { TUSQ_MEASURE = 13, TUSQ_MEASURE_RESET = 14 };
+#define TUSQ_MAX_MEASURED 8u
 
 /* amplitude precision of the sweeps; reductions are always FP64 */
 enum { TUSQ_C128 = 0, TUSQ_C64 = 1 };
@@ -73,8 +77,17 @@ enum { TUSQ_C128 = 0, TUSQ_C64 = 1 };
 /* traversals: plain DFTT (undo to the shared node), naive (restart from the
  * root), hybrid (undo only when cheaper), checkpoint (DFTT whose branch
  * states are kept in spare device memory: the next leaf restores the state
- * at its branch depth instead of undoing; Fig. 6E)                        */
-enum { TUSQ_DFTT = 0, TUSQ_NAIVE = 1, TUSQ_HYBRID = 2, TUSQ_CHECKPOINT = 3 };
+ * at its branch depth instead of undoing; Fig. 6E), caching (DFTT+Caching
+ * for circuits with mid-circuit measurement layers, Sec. III-B.2: DFTT
+ * within the stretches between layers, a LIFO cache of the pre-measurement
+ * states of the cache_capacity layers closest to the leaves, uncached ones
+ * recomputed from the root; cache_capacity 0 switches DFTT off).  Circuits
+ * with measurement layers run only with TUSQ_CACHING, and without pruning:
+ * every shot draws its own outcome from the Born weights of the layer (Philox
+ * stream 3, counter (shot within its leaf, leaf, layer), half 0; the
+ * smallest outcome o with u T < P_0 + ... + P_o), so a node's shots split
+ * into outcome branches, each weighing its shots / S.                       */
+enum { TUSQ_DFTT = 0, TUSQ_NAIVE = 1, TUSQ_HYBRID = 2, TUSQ_CHECKPOINT = 3, TUSQ_CACHING = 4 };
 
 /* what a run returns */
 #define TUSQ_WANT_DIST 1u      /* FP64 averaged distribution, 2^n values */
@@ -94,7 +107,8 @@ typedef struct {
     uint32_t alpha_den;        /*   alpha_num * s_max (Sec. III-A.4)          */
     uint32_t beta;             /* insignificant circuits kept (Eq. (2))       */
     uint32_t precision;        /* TUSQ_C128 | TUSQ_C64                        */
-    uint32_t traversal;        /* TUSQ_DFTT | NAIVE | HYBRID | CHECKPOINT     */
+    uint32_t traversal;        /* TUSQ_DFTT | NAIVE | HYBRID | CHECKPOINT |
+                                  CACHING                                     */
     uint32_t commute;          /* ER commutation on/off (Sec. III-A.2)         */
     uint32_t prune;            /* pruning on/off                               */
     double drift_bound;        /* C64 only: recompute a leaf from the root in
@@ -120,6 +134,9 @@ typedef struct {
                                   register-blocked with the next tile
                                   prefetched into registers (16 per thread),
                                   5 as 4 with 8 per thread                   */
+    uint32_t cache_capacity;   /* TUSQ_CACHING: pre-measurement states kept
+                                  (K of Sec. III-B.2; device slots of one
+                                  state each)                                 */
 } tusq_opts;
 
 typedef struct {
@@ -137,6 +154,12 @@ typedef struct {
                                            sweeps' dense ops: 16 per amplitude for
                                            a 2x2, 32 for a 4x4 (one complex
                                            multiply-add = 8)                     */
+    uint64_t mcm_edges;                 /* measurement edges applied (forward)   */
+    uint64_t paper_ops;                 /* the operation count of Sec. III-B.2:
+                                           1 per 1-qubit gate or Pauli applied
+                                           (either direction), 4 per CX, 1 per
+                                           measurement edge, 0 for resets and
+                                           cache fetches (Eq. (3)'s N)           */
     uint64_t pass_events;               /* sweeps timed with events (profile)    */
     double pass_seconds;                /* their summed device time               */
     double host_ecm_seconds, host_plan_seconds, device_seconds;
@@ -183,6 +206,14 @@ int tusq_thermal_pauli_probs(double t, double t1, double t2, double *probs);
  * tusq_circuit_pauli_noise otherwise.                                      */
 int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, double t1,
                                double t2);
+/* Append a layer of concurrent Z-basis measurements of `count` distinct
+ * qubits (1 .. TUSQ_MAX_MEASURED), one non-invertible edge of the circuit
+ * tree (Sec. III-B.2); reset != 0 returns the measured qubits to |0>
+ * afterwards.  Outcome o of the layer has bit b = the value of the b-th
+ * measured qubit in ascending order.  A layer takes no noise channel;
+ * errors do not commute through a measurement of their qubit.            */
+int tusq_circuit_measure(tusq_circuit *c, const uint32_t *qubits, uint32_t count, int reset,
+                         uint32_t *gate_index_out);
 int tusq_circuit_destroy(tusq_circuit *c);
 
 /* ---- host-only error characterisation (no GPU needed) -------------------- */

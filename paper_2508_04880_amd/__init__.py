@@ -8,7 +8,7 @@ fallback path.  (The package itself imports without the library so that
 ``python -m paper_2508_04880_amd.build`` can build it.)"""
 
 _EXPORTS = (
-    "C64", "C128", "CHECKPOINT", "DFTT", "HYBRID", "NAIVE", "WANT_DIST", "WANT_NORMS", "WANT_SAMPLES",
+    "C64", "C128", "CACHING", "CHECKPOINT", "DFTT", "HYBRID", "NAIVE", "WANT_DIST", "WANT_NORMS", "WANT_SAMPLES",
     "Circuit", "Context", "Result", "Tree", "TusqError", "lib", "tusq_cancel",
     "tusq_ctx_create", "tusq_ecm_build", "tusq_job_times", "tusq_opts", "tusq_opts_default",
     "tusq_plan_counters", "tusq_plan_dump", "tusq_plan_dump_programs", "tusq_poll", "tusq_run", "tusq_run_batch",

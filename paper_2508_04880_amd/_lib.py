@@ -29,9 +29,10 @@ TUSQ_EINVAL, TUSQ_ENOMEM, TUSQ_EUNSUPPORTED, TUSQ_EDEVICE, TUSQ_EBUSY, TUSQ_ECAN
 KINDS = {name: i for i, name in enumerate(
     ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX"))}
 C128, C64 = 0, 1
-DFTT, NAIVE, HYBRID, CHECKPOINT = 0, 1, 2, 3
+DFTT, NAIVE, HYBRID, CHECKPOINT, CACHING = 0, 1, 2, 3, 4
 WANT_DIST, WANT_SAMPLES, WANT_NORMS = 1, 2, 4
-TRAVERSALS = {"dftt": DFTT, "naive": NAIVE, "hybrid": HYBRID, "checkpoint": CHECKPOINT}
+TRAVERSALS = {"dftt": DFTT, "naive": NAIVE, "hybrid": HYBRID, "checkpoint": CHECKPOINT,
+              "caching": CACHING}
 PRECISIONS = {"c128": C128, "c64": C64}
 
 
@@ -45,7 +46,8 @@ class tusq_opts(C.Structure):
                 ("want", C.c_uint32), ("fusion_max_qubits", C.c_uint32),
                 ("fusion_max_ops", C.c_uint32), ("fusion_low_qubits", C.c_uint32),
                 ("profile", C.c_uint32), ("debug_fail_at_step", C.c_int32),
-                ("host_threads", C.c_uint32), ("sweep_kernel", C.c_uint32)]
+                ("host_threads", C.c_uint32), ("sweep_kernel", C.c_uint32),
+                ("cache_capacity", C.c_uint32)]
 
 
 class tusq_counters(C.Structure):
@@ -53,7 +55,7 @@ class tusq_counters(C.Structure):
         "fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves", "draws",
         "ret_gates", "ret_paulis", "passes_fwd", "passes_inv", "leaf_sweeps", "recomputes",
         "recompute_passes", "sweep_bytes", "checkpoint_saves", "checkpoint_restores",
-        "sweep_flops", "pass_events")] + \
+        "sweep_flops", "mcm_edges", "paper_ops", "pass_events")] + \
         [(k, C.c_double) for k in ("pass_seconds", "host_ecm_seconds", "host_plan_seconds",
                                    "device_seconds", "max_norm_drift")]
 
@@ -80,6 +82,7 @@ _SIGS = {
     "tusq_circuit_pauli_noise": (C.c_int, [P, C.c_uint32, P, C.c_uint32]),
     "tusq_thermal_pauli_probs": (C.c_int, [C.c_double, C.c_double, C.c_double, P]),
     "tusq_circuit_thermal_noise": (C.c_int, [P, C.c_uint32, C.c_double, C.c_double, C.c_double]),
+    "tusq_circuit_measure": (C.c_int, [P, P, C.c_uint32, C.c_int, P]),
     "tusq_circuit_destroy": (C.c_int, [P]),
     "tusq_ecm_build": (C.c_int, [P, P, P]),
     "tusq_tree_get_info": (C.c_int, [P, P]),
@@ -113,7 +116,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 4
+ABI_VERSION = 5
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")
@@ -161,6 +164,11 @@ class Circuit:
         q = (C.c_uint32 * 2)()
         pr = (C.c_double * 3)()
         for kind, qs, params, noise in zip(circ.kinds, circ.qubits, circ.params, circ.noise):
+            if kind in ("M", "MR"):
+                mq = (C.c_uint32 * len(qs))(*qs)
+                check(lib.tusq_circuit_measure(self.h, mq, C.c_uint32(len(qs)),
+                                               C.c_int(kind == "MR"), None))
+                continue
             q[0] = qs[0]
             q[1] = qs[1] if len(qs) > 1 else 0
             for i in range(3):

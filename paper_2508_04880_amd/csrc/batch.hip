@@ -302,8 +302,8 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
     const uint32_t KT = c64 ? 13 : 12;        // tile qubits for larger states (64 KiB)
     for (const Circuit *c : circs)
         if (c->n > 16 || c->n < 1) fail(TUSQ_EUNSUPPORTED, "batched jobs need 1..16 qubits");
-    if (o.traversal == TUSQ_CHECKPOINT)
-        fail(TUSQ_EUNSUPPORTED, "the batched path has no checkpoint traversal");
+    if (o.traversal == TUSQ_CHECKPOINT || o.traversal == TUSQ_CACHING)
+        fail(TUSQ_EUNSUPPORTED, "the batched path has no checkpoint or caching traversal");
     if (J == 0) { out.clear(); return; }
     if (J > 65535) fail(TUSQ_EUNSUPPORTED, "at most 65535 jobs per batch");
     const bool want_dist = o.want & TUSQ_WANT_DIST;

@@ -45,7 +45,7 @@ void check_opts(const tusq_opts *o) {
     need(o->shots >= 1 && o->shots <= 0xFFFFFFFFull, "shots must be in [1, 2^32)");
     need(o->alpha_den > 0, "alpha_den must be positive");
     need(o->precision == TUSQ_C128 || o->precision == TUSQ_C64, "unknown precision");
-    need(o->traversal <= TUSQ_CHECKPOINT, "unknown traversal");
+    need(o->traversal <= TUSQ_CACHING, "unknown traversal");
     need(!(o->leaf_begin > o->leaf_end && o->leaf_end != 0), "leaf_begin > leaf_end");
     need(o->drift_bound >= 0.0, "drift_bound must be >= 0");
 }
@@ -72,6 +72,7 @@ void tusq_opts_default(tusq_opts *o) {
     o->max_passes_between_recompute = 0;
     o->want = TUSQ_WANT_DIST | TUSQ_WANT_SAMPLES;
     o->debug_fail_at_step = -1;
+    o->cache_capacity = 4;
 }
 
 int tusq_circuit_create(uint32_t n, tusq_circuit **out) {
@@ -113,6 +114,7 @@ int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double 
         need(c && probs, "circuit or probs is NULL");
         need(gate_index < c->c.gates.size(), "gate index out of range");
         Gate &g = c->c.gates[gate_index];
+        need(!is_measure(g.kind), "a measurement layer takes no noise channel");
         need(g.chan < 0, "gate already has a channel");
         need(n_probs == (is_cx(g.kind) ? 15u : 3u), "wrong number of probabilities for the gate");
         double s = 0.0;
@@ -167,6 +169,29 @@ int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, d
     });
     if (rc != TUSQ_OK) return rc;
     return tusq_circuit_pauli_noise(c, gate_index, p, m);
+}
+
+int tusq_circuit_measure(tusq_circuit *c, const uint32_t *qubits, uint32_t count, int reset,
+                         uint32_t *gate_index_out) {
+    return guarded([&] {
+        need(c && qubits, "circuit or qubits is NULL");
+        need(count >= 1 && count <= TUSQ_MAX_MEASURED, "a measurement layer takes 1..8 qubits");
+        uint64_t mk = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            need(qubits[i] < c->c.n, "qubit out of range");
+            need(!((mk >> qubits[i]) & 1), "measured qubit repeated");
+            mk |= 1ull << qubits[i];
+        }
+        Gate g{};
+        g.kind = static_cast<uint8_t>(reset ? TUSQ_MEASURE_RESET : TUSQ_MEASURE);
+        g.q[0] = static_cast<uint32_t>(mk);
+        g.q[1] = static_cast<uint32_t>(mk >> 32);
+        g.chan = -1;
+        need(c->c.gates.size() < 0xFFFFFFF0u, "too many gates");
+        c->c.gates.push_back(g);
+        c->c.dirty = true;
+        if (gate_index_out) *gate_index_out = static_cast<uint32_t>(c->c.gates.size() - 1);
+    });
 }
 
 int tusq_circuit_destroy(tusq_circuit *c) {
@@ -348,6 +373,12 @@ static void run_common(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *gi
     cc->c.finalize();
     const uint64_t need_b = job_device_bytes(cc->c.n, o->precision, o->shots, o->want & TUSQ_WANT_DIST);
     if (need_b > ctx->c->budget) fail(TUSQ_ENOMEM, "job needs more device memory than the budget");
+    const bool mcm = has_measure(cc->c);
+    if (mcm) {
+        if (o->traversal != TUSQ_CACHING)
+            fail(TUSQ_EUNSUPPORTED, "the circuit has measurement layers: run it with TUSQ_CACHING");
+        if (o->prune) fail(TUSQ_EUNSUPPORTED, "measurement layers need prune = 0");
+    }
     auto *r = new tusq_result;
     try {
         double t0 = now_seconds();
@@ -363,6 +394,17 @@ static void run_common(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *gi
                  "tree was built for another circuit");
         }
         t0 = now_seconds();
+        if (mcm) {
+            McmPlan mp = build_mcm_plan(cc->c, *t, *o);
+            const double plan_s = now_seconds() - t0;
+            if (need_b + mcm_bytes(cc->c.n, o->precision, mp.K) > ctx->c->budget)
+                fail(TUSQ_ENOMEM, "cached states exceed the device memory budget");
+            execute_mcm(*ctx->c, *t, mp, *o, static_cast<hipStream_t>(stream), r->r);
+            r->r.counters.host_ecm_seconds = ecm_s;
+            r->r.counters.host_plan_seconds = plan_s;
+            *out = r;
+            return;
+        }
         Plan p = build_plan(cc->c, *t, *o, o->precision == TUSQ_C64);
         const double plan_s = now_seconds() - t0;
         if (need_b + checkpoint_bytes(cc->c.n, o->precision, p.checkpoint_slots) > ctx->c->budget)
@@ -399,6 +441,8 @@ int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, cons
         cc->c.finalize();
         need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
         *tuned = *o;
+        if (has_measure(cc->c))
+            fail(TUSQ_EUNSUPPORTED, "the autotuner runs circuits without measurement layers");
         const uint32_t n = cc->c.n;
         if (n <= 12) return;  // one tile holds the state
         const uint64_t key = (static_cast<uint64_t>(n) << 48) | (static_cast<uint64_t>(o->precision) << 40) |
@@ -457,6 +501,8 @@ int tusq_submit(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *o, uint64
     return guarded([&] {
         need(ctx && c && job_id, "NULL argument");
         check_opts(o);
+        if (has_measure(c->c))
+            fail(TUSQ_EUNSUPPORTED, "serving runs circuits without measurement layers; use tusq_run");
         *job_id = serving_submit(*ctx->c, c->c, *o);
     });
 }
@@ -506,6 +552,8 @@ int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_o
         for (size_t i = 0; i < n_jobs; ++i) {
             need(circs[i] != nullptr, "NULL circuit in batch");
             auto *cc = const_cast<tusq_circuit *>(circs[i]);
+            if (has_measure(cc->c))
+                fail(TUSQ_EUNSUPPORTED, "the batched path runs circuits without measurement layers");
             cc->c.finalize();
             cs[i] = &cc->c;
         }

@@ -25,7 +25,7 @@ struct Error {
 // Circuit
 struct Gate {
     uint8_t kind;
-    uint32_t q[2];
+    uint32_t q[2];  // measurement layers: the measured-qubit mask, low word in q[0]
     double p[3];
     int32_t chan;  // channel index or -1
 };
@@ -46,6 +46,9 @@ struct Circuit {
 };
 
 bool is_cx(uint8_t kind);
+bool is_measure(uint8_t kind);
+inline uint64_t measure_mask(const Gate &g) { return uint64_t(g.q[0]) | (uint64_t(g.q[1]) << 32); }
+bool has_measure(const Circuit &c);
 void gate_matrix(const Gate &g, cd m[4]);  // 2x2 of a 1-qubit gate
 
 // ---------------------------------------------------------------------------
@@ -174,6 +177,41 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
 // op lists only, or count)
 Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths,
                 bool programs = true);
+
+// ---------------------------------------------------------------------------
+// Circuits with mid-circuit measurement layers (DFTT+Caching).  The tokens
+// of a leaf split at its measurement gates into stages (stage s: between
+// layers s-1 and s).  Every distinct stage token sequence is a McmPath whose
+// tokens are fused once, in segments cut at every depth where another path
+// of the same stage branches off, so any DFTT transition between two paths
+// of a stage moves along whole segments.
+struct McmSeg {
+    uint32_t p0, p1;        // pass range
+    uint32_t gates, paulis;
+    uint64_t ops;           // operation count: 1 per 1-qubit token, 4 per CX
+};
+struct McmPath {
+    std::vector<uint64_t> code;  // token codes (gate: 1 << 63 | g; event: its key)
+    std::vector<uint64_t> cut;   // 0 = cut[0] < ... < cut.back() = tokens
+    std::vector<McmSeg> seg;     // seg[i]: tokens [cut[i], cut[i + 1])
+};
+struct McmLayer {
+    uint32_t gate;
+    uint32_t m;                  // measured qubits
+    uint32_t q[TUSQ_MAX_MEASURED];
+    bool reset;
+};
+struct McmPlan {
+    Plan plan;                   // passes, ops, matrices and programs of every segment
+    uint64_t lb = 0, le = 0;
+    uint32_t M = 0, K = 0;       // layers, effective cache capacity (<= M)
+    std::vector<McmLayer> layers;
+    std::vector<McmPath> paths;
+    std::vector<uint32_t> leaf_path;  // (l - lb) * (M + 1) + s -> path of leaf l in stage s
+};
+McmPlan build_mcm_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool programs = true);
+// real floating-point operations of one launch of a pass (see sweep_flops)
+uint64_t plan_pass_flops(const Plan &plan, uint32_t pass);
 
 double now_seconds();
 unsigned host_threads(const tusq_opts &o);

@@ -5,11 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
 #include "exec.hpp"
 #include "kernels.hpp"
+#include "rng.hpp"
 
 namespace tusq {
 
@@ -38,13 +40,13 @@ void DevBuf::ensure(size_t b) {
 uint64_t Workspace::bytes() const {
     uint64_t b = 0;
     for (const DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats,
-                            &mats128, &prog, &ckpt})
+                            &mats128, &prog, &ckpt, &mcm})
         b += d->bytes;
     return b;
 }
 void Workspace::release() {
     for (DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats, &mats128,
-                      &prog, &ckpt})
+                      &prog, &ckpt, &mcm})
         d->release();
 }
 
@@ -94,6 +96,52 @@ SweepArgs sweep_args(const Pass &p, bool inverse) {
     return a;
 }
 
+// Copies a plan's ops, programs and matrices (complex64 and, for the
+// recompute path, complex128) into the workspace.  The host copies live in
+// `st`, which must outlive the asynchronous copies (the caller synchronises
+// the stream before it goes out of scope).
+struct Staged {
+    std::vector<DOp> dops;
+    std::vector<double2> m128;
+    std::vector<float2> m64;
+};
+
+void upload_plan_into(const Plan &plan, Workspace &ws, bool c64, hipStream_t s, Staged &st) {
+    DevBuf &dops_b = ws.dops, &mats_b = ws.mats, &mats128_b = ws.mats128, &prog_b = ws.prog;
+    std::vector<DOp> &dops = st.dops;
+    to_device_ops(plan, dops);
+    dops_b.ensure(std::max<size_t>(dops.size(), 1) * sizeof(DOp));
+    if (!dops.empty())
+        hip_check(hipMemcpyAsync(dops_b.p, dops.data(), dops.size() * sizeof(DOp), hipMemcpyHostToDevice, s),
+                  "upload ops");
+    prog_b.ensure(std::max<size_t>(plan.prog.size(), 1) * sizeof(Instr2));
+    if (!plan.prog.empty())
+        hip_check(hipMemcpyAsync(prog_b.p, plan.prog.data(), plan.prog.size() * sizeof(Instr2),
+                                 hipMemcpyHostToDevice, s), "upload programs");
+    std::vector<double2> &m128 = st.m128;
+    m128.resize(plan.mats.size());
+    for (size_t i = 0; i < plan.mats.size(); ++i) m128[i] = double2{plan.mats[i].real(), plan.mats[i].imag()};
+    if (c64) {
+        std::vector<float2> &m64 = st.m64;
+        m64.resize(plan.mats.size());
+        for (size_t i = 0; i < plan.mats.size(); ++i)
+            m64[i] = float2{static_cast<float>(plan.mats[i].real()), static_cast<float>(plan.mats[i].imag())};
+        mats_b.ensure(std::max<size_t>(m64.size(), 1) * sizeof(float2));
+        if (!m64.empty())
+            hip_check(hipMemcpyAsync(mats_b.p, m64.data(), m64.size() * sizeof(float2), hipMemcpyHostToDevice, s),
+                      "upload mats");
+        mats128_b.ensure(std::max<size_t>(m128.size(), 1) * sizeof(double2));
+        if (!m128.empty())
+            hip_check(hipMemcpyAsync(mats128_b.p, m128.data(), m128.size() * sizeof(double2),
+                                     hipMemcpyHostToDevice, s), "upload mats");
+    } else {
+        mats_b.ensure(std::max<size_t>(m128.size(), 1) * sizeof(double2));
+        if (!m128.empty())
+            hip_check(hipMemcpyAsync(mats_b.p, m128.data(), m128.size() * sizeof(double2),
+                                     hipMemcpyHostToDevice, s), "upload mats");
+    }
+}
+
 template <typename V>
 void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
                Result &res, Workspace &ws, const std::atomic<bool> *cancel) {
@@ -122,37 +170,8 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     if (plan.checkpoint_slots) ws.ckpt.ensure(plan.checkpoint_slots * N * sizeof(V));
     V *ckpt = static_cast<V *>(ws.ckpt.p);
 
-    std::vector<DOp> dops;
-    to_device_ops(plan, dops);
-    dops_b.ensure(std::max<size_t>(dops.size(), 1) * sizeof(DOp));
-    if (!dops.empty())
-        hip_check(hipMemcpyAsync(dops_b.p, dops.data(), dops.size() * sizeof(DOp), hipMemcpyHostToDevice, s),
-                  "upload ops");
-    prog_b.ensure(std::max<size_t>(plan.prog.size(), 1) * sizeof(Instr2));
-    if (!plan.prog.empty())
-        hip_check(hipMemcpyAsync(prog_b.p, plan.prog.data(), plan.prog.size() * sizeof(Instr2),
-                                 hipMemcpyHostToDevice, s), "upload programs");
-    std::vector<double2> m128(plan.mats.size());
-    for (size_t i = 0; i < plan.mats.size(); ++i) m128[i] = double2{plan.mats[i].real(), plan.mats[i].imag()};
-    std::vector<float2> m64;
-    if (c64) {
-        m64.resize(plan.mats.size());
-        for (size_t i = 0; i < plan.mats.size(); ++i)
-            m64[i] = float2{static_cast<float>(plan.mats[i].real()), static_cast<float>(plan.mats[i].imag())};
-        mats_b.ensure(std::max<size_t>(m64.size(), 1) * sizeof(float2));
-        if (!m64.empty())
-            hip_check(hipMemcpyAsync(mats_b.p, m64.data(), m64.size() * sizeof(float2), hipMemcpyHostToDevice, s),
-                      "upload mats");
-        mats128_b.ensure(std::max<size_t>(m128.size(), 1) * sizeof(double2));
-        if (!m128.empty())
-            hip_check(hipMemcpyAsync(mats128_b.p, m128.data(), m128.size() * sizeof(double2),
-                                     hipMemcpyHostToDevice, s), "upload mats");
-    } else {
-        mats_b.ensure(std::max<size_t>(m128.size(), 1) * sizeof(double2));
-        if (!m128.empty())
-            hip_check(hipMemcpyAsync(mats_b.p, m128.data(), m128.size() * sizeof(double2),
-                                     hipMemcpyHostToDevice, s), "upload mats");
-    }
+    Staged staged;
+    upload_plan_into(plan, ws, c64, s, staged);
     if (want_dist) hip_check(launch_fill(static_cast<double *>(acc.p), N, 0.0, s), "fill");
 
     V *st = static_cast<V *>(psi.p);
@@ -304,6 +323,357 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     for (double v : res.norms) ct.max_norm_drift = std::max(ct.max_norm_drift, std::fabs(v - 1.0));
 }
 
+
+// ---------------------------------------------------------------------------
+// DFTT+Caching over stages separated by measurement layers (Sec. III-B.2).
+// The walk is the oracle's: plain DFTT inside a stage; at the end of a stage
+// path (a pre-measurement node) the layer's outcome weights come back to the
+// host, every shot of the node draws its outcome (stream 3, counter (shot,
+// leaf, layer)), and each outcome with shots is walked in turn; the node is
+// pushed on the cache if its layer is one of the K closest to the leaves,
+// else it is recomputed from the root when needed again.
+template <typename V>
+struct McmWalk {
+    Ctx &ctx;
+    const Tree &t;
+    const McmPlan &mp;
+    const Plan &plan;
+    const tusq_opts &o;
+    hipStream_t s;
+    Result &res;
+    uint32_t n;
+    uint64_t N;
+    uint32_t lc;
+    V *psi;
+    V *slots;              // K cached states
+    double *partial, *Pdev;
+    const DOp *dop;
+    const V *mat;
+    const Instr2 *prog;
+    double *acc, *csum, *prefix, *norms;
+    uint64_t *samples;
+    bool want_dist, want_samples, prof;
+    std::vector<hipEvent_t> evs;
+    std::vector<uint32_t> rep, out;              // per stage / layer on the current path
+    std::vector<std::array<double, 256>> P;      // weights of each layer's node on the path
+    std::vector<uint64_t> sbase;                 // draws taken per leaf
+    uint64_t sample_off = 0, vleaf = 0;
+    tusq_counters ct{};
+
+    struct Grp {
+        std::vector<uint64_t> leaf, off;
+        std::vector<uint32_t> shot;
+    };
+
+    McmWalk(Ctx &c, const Tree &tr, const McmPlan &m, const tusq_opts &op, hipStream_t st, Result &r)
+        : ctx(c), t(tr), mp(m), plan(m.plan), o(op), s(st), res(r) {}
+
+    bool cached(uint32_t k) const { return mp.K > 0 && k + mp.K >= mp.M; }
+    V *slot(uint32_t k) { return slots + static_cast<uint64_t>(k + mp.K - mp.M) * N; }
+    uint32_t path_of(uint64_t l, uint32_t st) const { return mp.leaf_path[(l - mp.lb) * (mp.M + 1) + st]; }
+    uint64_t len(uint32_t id) const { return mp.paths[id].code.size(); }
+
+    hipError_t sweep(const Pass &p, bool inverse) {
+        const SweepArgs a = sweep_args(p, inverse);
+        if (p.k >= plan.reg_qubits) {
+            if (o.sweep_kernel == 1 || o.sweep_kernel == 3)
+                return launch_sweep_reg<V>(psi, n, a, prog, mat, plan.reg_qubits, s);
+            return launch_sweep_pp<V>(psi, n, a, prog, mat, plan.reg_qubits,
+                                      static_cast<uint32_t>(ctx.cus), s);
+        }
+        return launch_sweep<V>(psi, n, a, dop, mat, s);
+    }
+    void run_pass(uint32_t pi, bool inverse) {
+        const Pass &pp = plan.passes[pi];
+        if (prof) {
+            hipEvent_t e0 = ctx.event(), e1 = ctx.event();
+            hip_check(hipEventRecord(e0, s), "event");
+            hip_check(sweep(pp, inverse), "sweep");
+            hip_check(hipEventRecord(e1, s), "event");
+            evs.push_back(e0);
+            evs.push_back(e1);
+        } else {
+            hip_check(sweep(pp, inverse), "sweep");
+        }
+        ct.sweep_bytes += 2ull * N * sizeof(V);
+        ct.sweep_flops += plan_pass_flops(plan, pi);
+    }
+    // tokens [from, to) of a path forward, or [to, from) undone (from > to);
+    // both ends are cut points of the path
+    void fwd(uint32_t id, uint64_t from, uint64_t to) {
+        const McmPath &p = mp.paths[id];
+        for (size_t i = 0; i < p.seg.size(); ++i) {
+            if (p.cut[i] < from || p.cut[i + 1] > to) continue;
+            const McmSeg &sg = p.seg[i];
+            for (uint32_t q = sg.p0; q < sg.p1; ++q) run_pass(q, false);
+            ct.passes_fwd += sg.p1 - sg.p0;
+            ct.fwd_gates += sg.gates;
+            ct.fwd_paulis += sg.paulis;
+            ct.paper_ops += sg.ops;
+        }
+    }
+    void inv(uint32_t id, uint64_t from, uint64_t to) {
+        const McmPath &p = mp.paths[id];
+        for (size_t i = p.seg.size(); i > 0; --i) {
+            if (p.cut[i - 1] < to || p.cut[i] > from) continue;
+            const McmSeg &sg = p.seg[i - 1];
+            for (uint32_t q = sg.p1; q > sg.p0; --q) run_pass(q - 1, true);
+            ct.passes_inv += sg.p1 - sg.p0;
+            ct.inv_gates += sg.gates;
+            ct.inv_paulis += sg.paulis;
+            ct.paper_ops += sg.ops;
+        }
+    }
+    void check_cut(uint32_t id, uint64_t d) const {
+        const auto &c = mp.paths[id].cut;
+        if (!std::binary_search(c.begin(), c.end(), d))
+            fail(TUSQ_EINVAL, "internal: a transition stops inside a fused segment");
+    }
+    MeasArgs layer_args(uint32_t k) const {
+        MeasArgs a{};
+        a.m = mp.layers[k].m;
+        for (uint32_t b = 0; b < a.m; ++b) a.q[b] = static_cast<uint8_t>(mp.layers[k].q[b]);
+        return a;
+    }
+    void weights(uint32_t k) {
+        const MeasArgs a = layer_args(k);
+        hip_check(launch_mcm_probs<V>(psi, n, a, partial, Pdev, s), "measurement weights");
+        hip_check(hipMemcpyAsync(P[k].data(), Pdev, sizeof(double) << a.m, hipMemcpyDeviceToHost, s),
+                  "weights readback");
+        hip_check(hipStreamSynchronize(s), "sync");
+    }
+    // measurement edge of layer k with outcome o, reading src (psi or a slot)
+    void edge(uint32_t k, uint32_t oc, const V *src) {
+        const MeasArgs a = layer_args(k);
+        const uint32_t want = mp.layers[k].reset ? 0u : oc;
+        hip_check(launch_mcm_apply<V>(src, psi, n, a, oc, want, 1.0 / std::sqrt(P[k][oc]), s),
+                  "measurement edge");
+        ct.mcm_edges++;
+        ct.paper_ops++;
+    }
+    void reach_root(uint32_t st) {
+        if (st == 0) {
+            hip_check(launch_reset<V>(psi, n, s), "reset");
+            ct.resets++;
+            return;
+        }
+        reach_pre(st - 1);
+        edge(st - 1, out[st - 1], psi);
+    }
+    void reach_pre(uint32_t k) {
+        if (cached(k)) {
+            hip_check(hipMemcpyAsync(psi, slot(k), N * sizeof(V), hipMemcpyDeviceToDevice, s), "fetch");
+            ct.checkpoint_restores++;
+            return;
+        }
+        reach_root(k);
+        fwd(rep[k], 0, len(rep[k]));
+    }
+    void final_leaf(uint64_t l, uint64_t c) {
+        double *nrm = norms + vleaf;
+        hip_check(launch_leaf<V>(psi, n, lc, want_dist ? acc : nullptr,
+                                 static_cast<double>(c) / static_cast<double>(t.S), csum, prefix, nrm, s),
+                  "leaf");
+        if (want_samples && c)
+            hip_check(launch_sample<V>(psi, n, lc, prefix, nrm, o.seed, static_cast<uint32_t>(l), c,
+                                       samples + sample_off, s, sbase[l - mp.lb]),
+                      "sample");
+        sample_off += c;
+        sbase[l - mp.lb] += c;
+        ++vleaf;
+        ct.leaves++;
+        ct.leaf_sweeps++;
+        ct.draws += c;
+    }
+    static uint32_t pick(const double *Pw, uint32_t no, double u) {
+        double T = 0.0;
+        for (uint32_t q = 0; q < no; ++q) T = T + Pw[q];
+        const double x = u * T;
+        double C = 0.0;
+        for (uint32_t q = 0; q < no; ++q) {
+            C = C + Pw[q];
+            if (x < C) return q;
+        }
+        uint32_t q = no - 1;
+        while (q > 0 && Pw[q] == 0.0) --q;
+        return q;
+    }
+    void walk(uint32_t st, const Grp &g) {
+        const bool naive = mp.K == 0;
+        size_t i = 0, prev = SIZE_MAX;
+        bool valid = true;
+        while (i < g.leaf.size()) {
+            const uint32_t id = path_of(g.leaf[i], st);
+            size_t j = i + 1;
+            while (j < g.leaf.size() && path_of(g.leaf[j], st) == id) ++j;
+            const uint64_t L = len(id);
+            if (prev != SIZE_MAX) {
+                const uint32_t pid = path_of(g.leaf[prev], st);
+                const auto &u = mp.paths[pid].code, &v = mp.paths[id].code;
+                uint64_t d = 0;
+                while (d < u.size() && d < v.size() && u[d] == v[d]) ++d;
+                check_cut(pid, d);
+                check_cut(id, d);
+                if (valid && !naive) {
+                    inv(pid, u.size(), d);
+                } else {
+                    reach_root(st);
+                    fwd(id, 0, d);
+                }
+                fwd(id, d, L);
+            } else {
+                fwd(id, 0, L);
+            }
+            if (st == mp.M) {
+                if (j != i + 1) fail(TUSQ_EINVAL, "internal: two leaves with one final path");
+                final_leaf(g.leaf[i], g.off[i + 1] - g.off[i]);
+                valid = !naive;
+            } else {
+                rep[st] = id;
+                weights(st);
+                const uint32_t no = 1u << mp.layers[st].m;
+                std::vector<uint32_t> oc(g.off[j] - g.off[i]);
+                std::vector<uint64_t> cnt(no, 0);
+                for (size_t e = i; e < j; ++e)
+                    for (uint64_t x = g.off[e]; x < g.off[e + 1]; ++x) {
+                        const Pair64 r = philox_pair(o.seed, g.shot[x], static_cast<uint32_t>(g.leaf[e]),
+                                                     st, STREAM_OUTCOMES);
+                        const uint32_t q = pick(P[st].data(), no, static_cast<double>(r.lo >> 11) * 0x1p-53);
+                        oc[x - g.off[i]] = q;
+                        cnt[q]++;
+                    }
+                const bool cch = cached(st);
+                if (cch) {
+                    hip_check(hipMemcpyAsync(slot(st), psi, N * sizeof(V), hipMemcpyDeviceToDevice, s),
+                              "cache push");
+                    ct.checkpoint_saves++;
+                }
+                bool first = true;
+                for (uint32_t q = 0; q < no; ++q) {
+                    if (!cnt[q]) continue;
+                    Grp h;
+                    h.off.push_back(0);
+                    for (size_t e = i; e < j; ++e) {
+                        const size_t y0 = h.shot.size();
+                        for (uint64_t x = g.off[e]; x < g.off[e + 1]; ++x)
+                            if (oc[x - g.off[i]] == q) h.shot.push_back(g.shot[x]);
+                        if (h.shot.size() > y0) {
+                            h.leaf.push_back(g.leaf[e]);
+                            h.off.push_back(h.shot.size());
+                        }
+                    }
+                    out[st] = q;
+                    if (first) {
+                        edge(st, q, psi);
+                    } else if (cch) {
+                        // a fetch of the cached node fused with the edge
+                        ct.checkpoint_restores++;
+                        edge(st, q, slot(st));
+                    } else {
+                        reach_pre(st);
+                        edge(st, q, psi);
+                    }
+                    walk(st + 1, h);
+                    first = false;
+                }
+                if (cch) {
+                    hip_check(hipMemcpyAsync(psi, slot(st), N * sizeof(V), hipMemcpyDeviceToDevice, s),
+                              "fetch");
+                    ct.checkpoint_restores++;
+                    valid = true;
+                } else {
+                    valid = false;
+                }
+            }
+            prev = i;
+            i = j;
+        }
+    }
+
+    void run() {
+        n = plan.n;
+        N = 1ull << n;
+        lc = std::min<uint32_t>(n, 11);
+        const uint64_t nc = N >> lc;
+        const bool c64 = std::is_same<V, float2>::value;
+        want_dist = o.want & TUSQ_WANT_DIST;
+        want_samples = o.want & TUSQ_WANT_SAMPLES;
+        prof = o.profile != 0;
+        uint64_t total = 0;
+        for (uint64_t l = mp.lb; l < mp.le; ++l) total += t.shots[l];
+        Workspace ws;
+        ws.psi.ensure(N * sizeof(V));
+        if (want_dist) ws.acc.ensure(N * 8);
+        ws.csum.ensure(nc * 8);
+        ws.prefix.ensure(nc * 8);
+        ws.norms.ensure(std::max<uint64_t>(total, 1) * 8);  // final leaves <= shots
+        if (want_samples && total) ws.samples.ensure(total * 8);
+        if (mp.K) ws.ckpt.ensure(static_cast<uint64_t>(mp.K) * N * sizeof(V));
+        ws.mcm.ensure((512ull * 256 + 256) * 8);
+        Staged staged;
+        upload_plan_into(plan, ws, c64, s, staged);
+        psi = static_cast<V *>(ws.psi.p);
+        slots = static_cast<V *>(ws.ckpt.p);
+        partial = static_cast<double *>(ws.mcm.p);
+        Pdev = partial + 512ull * 256;
+        dop = static_cast<const DOp *>(ws.dops.p);
+        mat = static_cast<const V *>(ws.mats.p);
+        prog = static_cast<const Instr2 *>(ws.prog.p);
+        acc = static_cast<double *>(ws.acc.p);
+        csum = static_cast<double *>(ws.csum.p);
+        prefix = static_cast<double *>(ws.prefix.p);
+        norms = static_cast<double *>(ws.norms.p);
+        samples = static_cast<uint64_t *>(ws.samples.p);
+        rep.assign(mp.M + 1, 0);
+        out.assign(mp.M + 1, 0);
+        P.assign(mp.M + 1, {});
+        sbase.assign(mp.le - mp.lb, 0);
+        if (want_dist) hip_check(launch_fill(acc, N, 0.0, s), "fill");
+        const double t0 = now_seconds();
+        hip_check(hipStreamSynchronize(s), "sync");
+        if (mp.le > mp.lb) {
+            Grp g;
+            g.off.push_back(0);
+            for (uint64_t l = mp.lb; l < mp.le; ++l) {
+                g.leaf.push_back(l);
+                for (uint64_t k = 0; k < t.shots[l]; ++k) g.shot.push_back(static_cast<uint32_t>(k));
+                g.off.push_back(g.shot.size());
+            }
+            hip_check(launch_reset<V>(psi, n, s), "reset");
+            ct.resets++;
+            walk(0, g);
+        }
+        hip_check(hipStreamSynchronize(s), "sync");
+        ct.device_seconds = now_seconds() - t0;
+        if (prof) {
+            double tot = 0.0;
+            for (size_t k = 0; k < evs.size(); k += 2) {
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, evs[k], evs[k + 1]), "elapsed");
+                tot += ms * 1e-3;
+            }
+            ct.pass_seconds = tot;
+            ct.pass_events = evs.size() / 2;
+            ctx.recycle(evs);
+        }
+        res.n = n;
+        if (want_dist) {
+            res.dist.resize(N);
+            hip_check(hipMemcpy(res.dist.data(), acc, N * 8, hipMemcpyDeviceToHost), "dist readback");
+        }
+        if (want_samples && total) {
+            res.samples.resize(total);
+            hip_check(hipMemcpy(res.samples.data(), samples, total * 8, hipMemcpyDeviceToHost),
+                      "samples readback");
+        }
+        res.norms.resize(vleaf);
+        if (vleaf)
+            hip_check(hipMemcpy(res.norms.data(), norms, vleaf * 8, hipMemcpyDeviceToHost), "norms readback");
+        for (double v : res.norms) ct.max_norm_drift = std::max(ct.max_norm_drift, std::fabs(v - 1.0));
+        res.counters = ct;
+    }
+};
+
 }  // namespace
 
 Ctx::Ctx(int dev, uint64_t budget_) : device(dev) {
@@ -341,6 +711,21 @@ void Ctx::recycle(std::vector<hipEvent_t> &evs) {
     std::lock_guard<std::mutex> g(mu);
     pool.insert(pool.end(), evs.begin(), evs.end());
     evs.clear();
+}
+
+uint64_t mcm_bytes(uint32_t n, uint32_t precision, uint32_t K) {
+    return static_cast<uint64_t>(K) * ((1ull << n) * (precision == TUSQ_C64 ? 8 : 16)) +
+           (512ull * 256 + 256) * 8;
+}
+
+void execute_mcm(Ctx &ctx, const Tree &t, const McmPlan &mp, const tusq_opts &o, hipStream_t s,
+                 Result &res) {
+    hip_check(hipSetDevice(ctx.device), "hipSetDevice");
+    if (!s) s = ctx.stream;
+    if (mp.plan.n > 34) fail(TUSQ_EUNSUPPORTED, "more than 34 qubits");
+    if (o.precision == TUSQ_C64) McmWalk<float2>(ctx, t, mp, o, s, res).run();
+    else if (o.precision == TUSQ_C128) McmWalk<double2>(ctx, t, mp, o, s, res).run();
+    else fail(TUSQ_EINVAL, "unknown precision");
 }
 
 void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,

@@ -31,7 +31,8 @@ struct DevBuf {
 // execution lane (they only grow).
 struct Workspace {
     DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops, mats, mats128, prog;
-    DevBuf ckpt;  // checkpoint traversal: saved branch states
+    DevBuf ckpt;  // checkpoint traversal: saved branch states; caching: cached nodes
+    DevBuf mcm;   // measurement layers: per-block partial weights and P
     uint64_t bytes() const;
     void release();
 };
@@ -70,6 +71,14 @@ uint64_t checkpoint_bytes(uint32_t n, uint32_t precision, uint64_t slots);
 
 void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
                   Result &res, Workspace *ws = nullptr, const std::atomic<bool> *cancel = nullptr);
+// DFTT+Caching over a circuit with measurement layers (host-driven walk: the
+// outcome weights of every pre-measurement node come back to the host, which
+// splits the node's shots and chooses the next launches)
+void execute_mcm(Ctx &ctx, const Tree &t, const McmPlan &mp, const tusq_opts &o, hipStream_t s,
+                 Result &res);
+// device bytes of the measurement walk beyond a plain job: K cached states
+// and the weight scratch
+uint64_t mcm_bytes(uint32_t n, uint32_t precision, uint32_t K);
 
 }  // namespace tusq
 

@@ -29,6 +29,12 @@ unsigned host_threads(const tusq_opts &o) {
 }
 
 bool is_cx(uint8_t kind) { return kind == TUSQ_CX; }
+bool is_measure(uint8_t kind) { return kind == TUSQ_MEASURE || kind == TUSQ_MEASURE_RESET; }
+bool has_measure(const Circuit &c) {
+    for (const Gate &g : c.gates)
+        if (is_measure(g.kind)) return true;
+    return false;
+}
 
 void gate_matrix(const Gate &g, cd m[4]) {
     const cd i(0.0, 1.0);
@@ -160,6 +166,17 @@ struct Commuter {
                 heap.pop_back();
             }
             const Gate &gt = c.gates[g];
+            if (is_measure(gt.kind)) {
+                // a measurement stops every pending Pauli on its qubits (it
+                // is reported just before the layer); a layer has no channel
+                const uint64_t mk = measure_mask(gt);
+                for (uint32_t q = 0; q < c.n; ++q)
+                    if (((mk >> q) & 1) && pend[q]) {
+                        out.push_back(Ev{g, q, sym_to_code(pend[q])});
+                        pend[q] = 0;
+                    }
+                continue;
+            }
             if (is_cx(gt.kind)) {
                 const uint32_t qc = gt.q[0], qt = gt.q[1];
                 uint8_t sc = pend[qc], st = pend[qt];
@@ -358,6 +375,12 @@ Tree build_tree(const Circuit &cin, const tusq_opts &o) {
     // 3. ER commutation of every unique raw ER
     std::vector<std::vector<uint32_t>> qg(c.n);
     for (uint32_t g = 0; g < T.G; ++g) {
+        if (is_measure(c.gates[g].kind)) {
+            const uint64_t mk = measure_mask(c.gates[g]);
+            for (uint32_t q = 0; q < c.n; ++q)
+                if ((mk >> q) & 1) qg[q].push_back(g);
+            continue;
+        }
         qg[c.gates[g].q[0]].push_back(g);
         if (is_cx(c.gates[g].kind)) qg[c.gates[g].q[1]].push_back(g);
     }

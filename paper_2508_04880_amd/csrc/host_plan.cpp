@@ -10,6 +10,7 @@
 // undo is a cut: tokens between cuts form a segment, and a segment is fused
 // into sweeps that are undone as a unit (their inverses, in reverse order).
 #include <algorithm>
+#include <map>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -536,6 +537,53 @@ struct Fuser {
     }
 };
 
+// Fuser items of tokens [a, b) of a leaf (toks from leaf_tokens); counts
+// gates, Paulis and the operation count (1 per 1-qubit token, 4 per CX).
+void token_items(const Circuit &c, const Ev *ev, const std::vector<Tok> &toks, uint64_t a,
+                 uint64_t b, std::vector<Fuser::Item> &items, uint64_t &ng, uint64_t &np,
+                 uint64_t &ops) {
+    items.clear();
+    ng = np = ops = 0;
+    for (uint64_t i = a; i < b; ++i) {
+        const Tok &tk = toks[i];
+        Fuser::Item it{};
+        if (tk.is_gate) {
+            const Gate &g = c.gates[tk.idx];
+            it.is_gate = true;
+            it.qa = g.q[0];
+            if (is_cx(g.kind)) {
+                it.two = true;
+                it.qb = g.q[1];
+                ops += 4;
+            } else {
+                it.two = false;
+                it.qb = NONE;
+                cd m[4];
+                gate_matrix(g, m);
+                it.m2 = M2{m[0], m[1], m[2], m[3]};
+                ops += 1;
+            }
+            ++ng;
+        } else {
+            const Ev &e = ev[tk.idx];
+            it.is_gate = false;
+            it.two = false;
+            it.qa = e.qubit;
+            it.qb = NONE;
+            it.m2 = pauli_matrix(e.pauli);
+            ++np;
+            ops += 1;
+        }
+        items.push_back(it);
+    }
+}
+
+uint64_t pass_flops_per_amp(const Plan &plan, const Pass &p) {
+    uint64_t f = 0;
+    for (uint32_t i = p.op_begin; i < p.op_end; ++i) f += plan.ops[i].b == 0xFF ? 16 : 32;
+    return f;
+}
+
 }  // namespace
 
 FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o) {
@@ -555,6 +603,8 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
 
 Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths,
                 bool programs) {
+    if (has_measure(c))
+        fail(TUSQ_EUNSUPPORTED, "the circuit has measurement layers: run it with TUSQ_CACHING");
     Plan plan;
     plan.n = c.n;
     // register qubits per thread: 4 (16 amplitudes) unless an 8-amplitude
@@ -588,6 +638,7 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
             const uint64_t d = shared_depth(G, t.evs(p), t.nev(p), t.evs(l), t.nev(l));
             const uint64_t lp = G + t.nev(p);
             if (o.traversal == TUSQ_DFTT || o.traversal == TUSQ_CHECKPOINT ||
+                o.traversal == TUSQ_CACHING ||
                 (lp - d) + (cp.len - d) < cp.len) {
                 cp.reset = false;
                 cp.from = d;
@@ -611,7 +662,7 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     struct Seg {
         uint32_t p0, p1;
         uint64_t start;
-        uint64_t gates, paulis;
+        uint64_t gates, paulis, ops;
     };
     std::vector<Seg> applied;
     std::vector<Tok> toks;
@@ -650,6 +701,7 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
                 ct.passes_inv += s.p1 - s.p0;
                 ct.inv_gates += s.gates;
                 ct.inv_paulis += s.paulis;
+                ct.paper_ops += s.ops;
                 applied.pop_back();
             }
         }
@@ -662,43 +714,15 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
         for (size_t ci = 0; ci <= cuts.size(); ++ci) {
             const uint64_t b = ci < cuts.size() ? cuts[ci] : cp.len;
             if (b <= a) continue;
-            items.clear();
-            uint64_t ng = 0, np = 0;
-            for (uint64_t i = a; i < b; ++i) {
-                const Tok &tk = toks[i];
-                Fuser::Item it{};
-                if (tk.is_gate) {
-                    const Gate &g = c.gates[tk.idx];
-                    it.is_gate = true;
-                    it.qa = g.q[0];
-                    if (is_cx(g.kind)) {
-                        it.two = true;
-                        it.qb = g.q[1];
-                    } else {
-                        it.two = false;
-                        it.qb = NONE;
-                        cd m[4];
-                        gate_matrix(g, m);
-                        it.m2 = M2{m[0], m[1], m[2], m[3]};
-                    }
-                    ++ng;
-                } else {
-                    const Ev &e = ev[tk.idx];
-                    it.is_gate = false;
-                    it.two = false;
-                    it.qa = e.qubit;
-                    it.qb = NONE;
-                    it.m2 = pauli_matrix(e.pauli);
-                    ++np;
-                }
-                items.push_back(it);
-            }
+            uint64_t ng = 0, np = 0, nops = 0;
+            token_items(c, ev, toks, a, b, items, ng, np, nops);
             const auto pr = fu.fuse(items);
             for (uint32_t p = pr.first; p < pr.second; ++p) plan.steps.push_back(Step{ST_FWD, p});
             ct.passes_fwd += pr.second - pr.first;
             ct.fwd_gates += ng;
             ct.fwd_paulis += np;
-            applied.push_back(Seg{pr.first, pr.second, a, ng, np});
+            ct.paper_ops += nops;
+            applied.push_back(Seg{pr.first, pr.second, a, ng, np, nops});
             if (ckpt && b < cp.len) {  // a later leaf branches here
                 plan.steps.push_back(Step{ST_SAVE, saved.size()});
                 saved.push_back(b);
@@ -728,11 +752,149 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     uint64_t per_amp = 0;
     for (const Step &sp : plan.steps) {
         if (sp.kind != ST_FWD && sp.kind != ST_INV) continue;
-        const Pass &p = plan.passes[sp.id];
-        for (uint32_t i = p.op_begin; i < p.op_end; ++i) per_amp += plan.ops[i].b == 0xFF ? 16 : 32;
+        per_amp += pass_flops_per_amp(plan, plan.passes[sp.id]);
     }
     ct.sweep_flops = per_amp << c.n;
     return plan;
+}
+
+uint64_t plan_pass_flops(const Plan &plan, uint32_t pass) {
+    return pass_flops_per_amp(plan, plan.passes[pass]) << plan.n;
+}
+
+McmPlan build_mcm_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool programs) {
+    McmPlan mp;
+    Plan &plan = mp.plan;
+    plan.n = c.n;
+    plan.reg_qubits = (o.sweep_kernel == 3 || o.sweep_kernel == 5) ? 3 : 4;
+    plan.general_layouts = o.sweep_kernel == 0 || o.sweep_kernel == 4 || o.sweep_kernel == 5;
+    const uint32_t G = t.G;
+    uint64_t lb = o.leaf_begin, le = o.leaf_end;
+    if (lb == 0 && le == 0) le = t.leaves();
+    if (lb > le || le > t.leaves()) fail(TUSQ_EINVAL, "leaf range out of bounds");
+    for (uint64_t l = lb; l < le; ++l)
+        if (t.shots[l] != t.count[l] || t.wnum[l] != t.count[l] || t.wden[l] != t.S)
+            fail(TUSQ_EUNSUPPORTED, "measurement layers need a tree built without pruning");
+    mp.lb = lb;
+    mp.le = le;
+    for (uint32_t g = 0; g < G; ++g) {
+        const Gate &gt = c.gates[g];
+        if (!is_measure(gt.kind)) continue;
+        McmLayer ly{};
+        ly.gate = g;
+        ly.reset = gt.kind == TUSQ_MEASURE_RESET;
+        const uint64_t mk = measure_mask(gt);
+        for (uint32_t q = 0; q < c.n; ++q)
+            if ((mk >> q) & 1) ly.q[ly.m++] = q;
+        mp.layers.push_back(ly);
+    }
+    mp.M = static_cast<uint32_t>(mp.layers.size());
+    mp.K = std::min<uint32_t>(o.cache_capacity, mp.M);
+    const FusionParams fp = fusion_defaults(c.n, o.precision, o);
+    if (fp.max_qubits < 2 || fp.max_ops < 1) fail(TUSQ_EINVAL, "bad fusion parameters");
+    const uint32_t S1 = mp.M + 1;
+
+    // 1. the distinct stage token sequences (codes) and each leaf's path ids
+    std::vector<Tok> toks;
+    std::vector<std::map<std::vector<uint64_t>, uint32_t>> index(S1);
+    std::vector<std::vector<uint32_t>> by_stage(S1);
+    struct Src {
+        uint64_t leaf, a, b;  // a leaf and token range the path was first seen in
+    };
+    std::vector<Src> src;
+    mp.leaf_path.resize((le - lb) * S1);
+    for (uint64_t l = lb; l < le; ++l) {
+        const Ev *ev = t.evs(l);
+        leaf_tokens(G, ev, t.nev(l), toks);
+        uint64_t a = 0;
+        uint32_t s = 0;
+        for (uint64_t i = 0; i <= toks.size(); ++i) {
+            const bool end = i == toks.size();
+            if (!end && !(toks[i].is_gate && is_measure(c.gates[toks[i].idx].kind))) continue;
+            std::vector<uint64_t> code;
+            code.reserve(i - a);
+            for (uint64_t k = a; k < i; ++k) {
+                const Tok &tk = toks[k];
+                if (tk.is_gate) {
+                    code.push_back((1ull << 63) | tk.idx);
+                } else {
+                    const Ev &e = ev[tk.idx];
+                    code.push_back((uint64_t(e.slot) << 32) | (uint64_t(e.qubit) << 8) | e.pauli);
+                }
+            }
+            auto it = index[s].find(code);
+            uint32_t id;
+            if (it == index[s].end()) {
+                id = static_cast<uint32_t>(mp.paths.size());
+                McmPath path;
+                path.code = code;
+                mp.paths.push_back(std::move(path));
+                src.push_back(Src{l, a, i});
+                index[s].emplace(std::move(code), id);
+                by_stage[s].push_back(id);
+            } else {
+                id = it->second;
+            }
+            mp.leaf_path[(l - lb) * S1 + s] = id;
+            a = i + 1;
+            ++s;
+        }
+        if (s != S1) fail(TUSQ_EINVAL, "internal: stage count of a leaf");
+    }
+
+    // 2. cuts: every depth where another path of the same stage branches off
+    //    (in lexicographic order the depths shared with all others are the
+    //    running minima of neighbour prefixes, walking out both ways)
+    auto lcp = [&](uint32_t x, uint32_t y) {
+        const auto &u = mp.paths[x].code, &v = mp.paths[y].code;
+        uint64_t d = 0;
+        while (d < u.size() && d < v.size() && u[d] == v[d]) ++d;
+        return d;
+    };
+    for (uint32_t s = 0; s < S1; ++s) {
+        std::vector<uint32_t> ids;
+        for (const auto &kv : index[s]) ids.push_back(kv.second);  // map order = lexicographic
+        std::vector<uint64_t> nb(ids.size() > 0 ? ids.size() - 1 : 0);
+        for (size_t i = 0; i + 1 < ids.size(); ++i) nb[i] = lcp(ids[i], ids[i + 1]);
+        for (size_t i = 0; i < ids.size(); ++i) {
+            McmPath &p = mp.paths[ids[i]];
+            std::vector<uint64_t> cut{0, p.code.size()};
+            uint64_t run = UINT64_MAX;
+            for (size_t j = i; j > 0; --j) {
+                run = std::min(run, nb[j - 1]);
+                cut.push_back(run);
+                if (run == 0) break;
+            }
+            run = UINT64_MAX;
+            for (size_t j = i; j + 1 < ids.size(); ++j) {
+                run = std::min(run, nb[j]);
+                cut.push_back(run);
+                if (run == 0) break;
+            }
+            std::sort(cut.begin(), cut.end());
+            cut.erase(std::unique(cut.begin(), cut.end()), cut.end());
+            p.cut = std::move(cut);
+        }
+    }
+
+    // 3. fuse every segment of every path once
+    Fuser fu{c, fp, plan, programs};
+    std::vector<Fuser::Item> items;
+    for (uint32_t id = 0; id < mp.paths.size(); ++id) {
+        McmPath &p = mp.paths[id];
+        const Src &sr = src[id];
+        const Ev *ev = t.evs(sr.leaf);
+        leaf_tokens(G, ev, t.nev(sr.leaf), toks);
+        for (size_t i = 0; i + 1 < p.cut.size(); ++i) {
+            uint64_t ng, np, nops;
+            token_items(c, ev, toks, sr.a + p.cut[i], sr.a + p.cut[i + 1], items, ng, np, nops);
+            const auto pr = fu.fuse(items);
+            p.seg.push_back(McmSeg{pr.first, pr.second, static_cast<uint32_t>(ng),
+                                   static_cast<uint32_t>(np), nops});
+        }
+    }
+    plan.checkpoint_slots = mp.K;
+    return mp;
 }
 
 }  // namespace tusq

@@ -22,8 +22,13 @@
 //  k_sample    inverse-CDF shot sampling: one wavefront per draw, binary
 //              search over chunk prefixes, then a wave scan inside the chunk.
 //  k_reset, k_to_c64, k_fill   state initialisation and conversion.
+//  k_mcm_probs / k_mcm_sum     outcome weights of a measurement layer (FP64,
+//              fixed summation order); k_mcm_apply projects onto one outcome,
+//              renormalises and resets, one coset of the measured bits per
+//              thread (so it may run in place).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 
@@ -874,13 +879,14 @@ template <typename V>
 __global__ void __launch_bounds__(256) k_sample(const V *__restrict__ psi, uint32_t log_chunk,
                                                 const double *__restrict__ prefix, uint64_t nc,
                                                 const double *__restrict__ norm, uint64_t seed,
-                                                uint32_t leaf, uint64_t shots,
+                                                uint32_t leaf, uint64_t shots, uint64_t base,
                                                 uint64_t *__restrict__ out) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t d = static_cast<uint64_t>(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (d >= shots) return;
-    const Pair64 r = philox_pair(seed, static_cast<uint32_t>(d >> 1), leaf, 0, STREAM_SHOTS);
-    const uint64_t v = (d & 1) ? r.hi : r.lo;
+    const uint64_t dd = base + d;  // draw index within the leaf
+    const Pair64 r = philox_pair(seed, static_cast<uint32_t>(dd >> 1), leaf, 0, STREAM_SHOTS);
+    const uint64_t v = (dd & 1) ? r.hi : r.lo;
     const double x = static_cast<double>(v >> 11) * 0x1p-53 * (*norm);
     // first chunk whose inclusive prefix exceeds x
     uint64_t lo = 0, hi = nc;
@@ -1065,13 +1071,117 @@ hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc
 template <typename V>
 hipError_t launch_sample(const V *psi, uint32_t n, uint32_t log_chunk, const double *prefix,
                          const double *norm, uint64_t seed, uint32_t leaf, uint64_t shots,
-                         uint64_t *out, hipStream_t s) {
+                         uint64_t *out, hipStream_t s, uint64_t shot_base) {
     if (!shots) return hipSuccess;
     const uint64_t nc = 1ull << (n - log_chunk);
     const uint64_t blocks = (shots + 3) / 4;
     if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sample<V>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, psi,
-                       log_chunk, prefix, nc, norm, seed, leaf, shots, out);
+                       log_chunk, prefix, nc, norm, seed, leaf, shots, shot_base, out);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Measurement layers.  Basis index = base(r) | dep(o): base(r) spreads the
+// coset index r over the unmeasured bit positions (a zero inserted at every
+// measured position, ascending), dep(o) puts outcome bit b at measured
+// position q_b.
+__device__ __forceinline__ uint64_t mcm_base(uint64_t r, const MeasArgs &a) {
+    for (uint32_t b = 0; b < a.m; ++b) {
+        const uint32_t q = a.q[b];
+        r = ((r >> q) << (q + 1)) | (r & ((1ull << q) - 1));
+    }
+    return r;
+}
+__device__ __forceinline__ uint64_t mcm_dep(uint32_t o, const MeasArgs &a) {
+    uint64_t x = 0;
+    for (uint32_t b = 0; b < a.m; ++b) x |= static_cast<uint64_t>((o >> b) & 1u) << a.q[b];
+    return x;
+}
+
+// partial[o * gridDim.x + block] = sum of |psi|^2 over outcome o's amplitudes
+// that the block's threads visit (grid-stride over cosets, then a fixed tree)
+template <typename V>
+__global__ void __launch_bounds__(256) k_mcm_probs(const V *__restrict__ psi, uint64_t R,
+                                                   MeasArgs a, double *__restrict__ partial) {
+    __shared__ double red[256];
+    const uint32_t no = 1u << a.m;
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint32_t o = 0; o < no; ++o) {
+        const uint64_t dep = mcm_dep(o, a);
+        double acc = 0.0;
+        for (uint64_t r = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r < R;
+             r += stride)
+            acc += prob(psi, mcm_base(r, a) | dep);
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (uint32_t h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[static_cast<uint64_t>(o) * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+// P[o] = partial[o * nblk + 0] + ... + partial[o * nblk + nblk - 1], in order
+__global__ void __launch_bounds__(256) k_mcm_sum(const double *__restrict__ partial, uint32_t nblk,
+                                                 uint32_t no, double *__restrict__ P) {
+    const uint32_t o = threadIdx.x;
+    if (o >= no) return;
+    double s = 0.0;
+    for (uint32_t i = 0; i < nblk; ++i) s += partial[static_cast<uint64_t>(o) * nblk + i];
+    P[o] = s;
+}
+
+// dst[base | dep(p)] = (p == want) ? scale * src[base | dep(o)] : 0 for every
+// outcome pattern p of the thread's coset (src == dst allowed)
+template <typename V>
+__global__ void __launch_bounds__(256) k_mcm_apply(const V *src, V *dst, uint64_t R, MeasArgs a,
+                                                   uint32_t o, uint32_t want, double scale) {
+    using T = typename RealOf<V>::T;
+    const uint32_t no = 1u << a.m;
+    const uint64_t dep_o = mcm_dep(o, a);
+    const T sc = static_cast<T>(scale);
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t r = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; r < R;
+         r += stride) {
+        const uint64_t base = mcm_base(r, a);
+        V v = src[base | dep_o];
+        v.x *= sc;
+        v.y *= sc;
+        V z;
+        z.x = 0;
+        z.y = 0;
+        for (uint32_t p = 0; p < no; ++p) dst[base | mcm_dep(p, a)] = p == want ? v : z;
+    }
+}
+
+constexpr uint32_t MCM_BLOCKS = 512;
+
+template <typename V>
+hipError_t launch_mcm_probs(const V *psi, uint32_t n, const MeasArgs &a, double *partial,
+                            double *P, hipStream_t s) {
+    if (a.m < 1 || a.m > 8 || a.m > n) return hipErrorInvalidValue;
+    const uint64_t R = 1ull << (n - a.m);
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((R + 255) / 256, MCM_BLOCKS));
+    hipLaunchKernelGGL(k_mcm_probs<V>, dim3(blocks), dim3(256), 0, s, psi, R, a, partial);
+    TUSQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_mcm_sum, dim3(1), dim3(256), 0, s, partial, blocks, 1u << a.m, P);
+    TUSQ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+
+template <typename V>
+hipError_t launch_mcm_apply(const V *src, V *dst, uint32_t n, const MeasArgs &a, uint32_t o,
+                            uint32_t want, double scale, hipStream_t s) {
+    if (a.m < 1 || a.m > 8 || a.m > n || o >= (1u << a.m) || want >= (1u << a.m))
+        return hipErrorInvalidValue;
+    const uint64_t R = 1ull << (n - a.m);
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((R + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_mcm_apply<V>, dim3(blocks), dim3(256), 0, s, src, dst, R, a, o, want,
+                       scale);
     TUSQ_CHECK_LAUNCH();
     return hipSuccess;
 }
@@ -1139,10 +1249,18 @@ template hipError_t launch_leaf<float2>(const float2 *, uint32_t, uint32_t, doub
                                         double *, double *, double *, hipStream_t);
 template hipError_t launch_sample<double2>(const double2 *, uint32_t, uint32_t, const double *,
                                            const double *, uint64_t, uint32_t, uint64_t,
-                                           uint64_t *, hipStream_t);
+                                           uint64_t *, hipStream_t, uint64_t);
 template hipError_t launch_sample<float2>(const float2 *, uint32_t, uint32_t, const double *,
                                           const double *, uint64_t, uint32_t, uint64_t,
-                                          uint64_t *, hipStream_t);
+                                          uint64_t *, hipStream_t, uint64_t);
+template hipError_t launch_mcm_probs<double2>(const double2 *, uint32_t, const MeasArgs &, double *,
+                                              double *, hipStream_t);
+template hipError_t launch_mcm_probs<float2>(const float2 *, uint32_t, const MeasArgs &, double *,
+                                             double *, hipStream_t);
+template hipError_t launch_mcm_apply<double2>(const double2 *, double2 *, uint32_t, const MeasArgs &,
+                                              uint32_t, uint32_t, double, hipStream_t);
+template hipError_t launch_mcm_apply<float2>(const float2 *, float2 *, uint32_t, const MeasArgs &,
+                                             uint32_t, uint32_t, double, hipStream_t);
 template hipError_t launch_reset<double2>(double2 *, uint32_t, hipStream_t);
 template hipError_t launch_reset<float2>(float2 *, uint32_t, hipStream_t);
 

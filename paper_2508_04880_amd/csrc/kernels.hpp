@@ -58,10 +58,27 @@ hipError_t launch_sweep_pipe(V *psi, uint32_t n, const SweepArgs &a, const Instr
 template <typename V>
 hipError_t launch_leaf(const V *psi, uint32_t n, uint32_t log_chunk, double *acc, double w,
                        double *chunk_sum, double *prefix, double *norm_out, hipStream_t s);
+// draws shot_base .. shot_base + shots - 1 of leaf `leaf` into out[0 .. shots)
 template <typename V>
 hipError_t launch_sample(const V *psi, uint32_t n, uint32_t log_chunk, const double *prefix,
                          const double *norm, uint64_t seed, uint32_t leaf, uint64_t shots,
-                         uint64_t *out, hipStream_t s);
+                         uint64_t *out, hipStream_t s, uint64_t shot_base = 0);
+
+// A measurement layer: m (1..8) measured qubits, ascending.
+struct MeasArgs {
+    uint32_t m;
+    uint8_t q[8];
+};
+// P[o] (2^m doubles) = FP64 weight of every outcome o of the layer; partial
+// holds 512 * 2^m doubles of scratch.  Deterministic summation order.
+template <typename V>
+hipError_t launch_mcm_probs(const V *psi, uint32_t n, const MeasArgs &a, double *partial,
+                            double *P, hipStream_t s);
+// dst = the outcome-o part of src times scale, moved to pattern `want` (o
+// itself, or 0 for a reset); every other pattern zero.  src == dst allowed.
+template <typename V>
+hipError_t launch_mcm_apply(const V *src, V *dst, uint32_t n, const MeasArgs &a, uint32_t o,
+                            uint32_t want, double scale, hipStream_t s);
 template <typename V>
 hipError_t launch_reset(V *psi, uint32_t n, hipStream_t s);
 hipError_t launch_to_c64(const double2 *src, float2 *dst, uint32_t n, hipStream_t s);

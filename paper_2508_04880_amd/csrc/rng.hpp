@@ -42,7 +42,8 @@ TUSQ_HD U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
 
 // The two 64-bit values of one Philox block.  Counter layout used by the
 // whole engine: (sub-index, primary index, aux, stream); the key is the job
-// seed.  Streams: 0 error sampling, 1 pruning selection, 2 shot sampling.
+// seed.  Streams: 0 error sampling, 1 pruning selection, 2 shot sampling,
+// 3 measurement outcomes.
 struct Pair64 {
     uint64_t lo, hi;
 };
@@ -54,6 +55,6 @@ TUSQ_HD Pair64 philox_pair(uint64_t seed, uint32_t sub, uint32_t primary, uint32
     return Pair64{(static_cast<uint64_t>(r.y) << 32) | r.x, (static_cast<uint64_t>(r.w) << 32) | r.z};
 }
 
-enum : uint32_t { STREAM_ERRORS = 0, STREAM_PRUNE = 1, STREAM_SHOTS = 2 };
+enum : uint32_t { STREAM_ERRORS = 0, STREAM_PRUNE = 1, STREAM_SHOTS = 2, STREAM_OUTCOMES = 3 };
 
 }  // namespace tusq

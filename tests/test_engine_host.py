@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 4
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 5
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -93,7 +93,7 @@ def test_schedule_counts_match_oracle(trav, name, make, S):
     pc = tq.tusq_plan_counters(ec, et, o)
     _, _, oc, _ = oracle.run(c, ot, 5, traversal=trav, want_dist=False, want_samples=False)
     for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
-              "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores"):
+              "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores", "paper_ops"):
         assert pc[k] == oc[k], k
     # a leaf range starts from the root
     nl = et.info()["n_leaves"]
@@ -369,3 +369,48 @@ def test_thermal_noise_attached_by_the_library_gives_the_oracle_tree():
     assert tq.Tree(ec, o).serialize() == ot.serialize()
     with pytest.raises(tq.TusqError):
         ec.thermal_noise(0, 0.1, 1.0, 1.0)       # the gate already has a channel
+
+
+# --------------------------------------------------------------------------
+# Measurement layers (Sec. III-B.2): host side
+
+def test_measurement_tree_bit_exact_against_oracle():
+    from workloads import syndrome_rounds
+    for theta, commute in ((0.0, True), (0.7, True), (0.7, False)):
+        c = syndrome_rounds(3, 3, 0.02, 0.05, theta=theta)
+        ot = oracle.ecm(c, 3000, 9, do_commute=commute, prune=False)
+        o = tq.tusq_opts_default(shots=3000, seed=9, prune=0, commute=int(commute))
+        et = tq.Tree(tq.Circuit(c), o)
+        assert et.serialize() == ot.serialize()
+
+
+def test_measurement_layer_arguments_are_checked():
+    import ctypes as C
+    h = C.c_void_p()
+    assert tq.lib.tusq_circuit_create(C.c_uint32(4), C.byref(h)) == 0
+    try:
+        q = (C.c_uint32 * 9)(0, 1, 2, 3, 0, 1, 2, 3, 0)
+        assert tq.lib.tusq_circuit_measure(h, q, C.c_uint32(9), 1, None) == tq._lib.TUSQ_EINVAL
+        assert tq.lib.tusq_circuit_measure(h, q, C.c_uint32(0), 1, None) == tq._lib.TUSQ_EINVAL
+        rep = (C.c_uint32 * 2)(1, 1)
+        assert tq.lib.tusq_circuit_measure(h, rep, C.c_uint32(2), 0, None) == tq._lib.TUSQ_EINVAL
+        bad = (C.c_uint32 * 1)(4)
+        assert tq.lib.tusq_circuit_measure(h, bad, C.c_uint32(1), 0, None) == tq._lib.TUSQ_EINVAL
+        gi = C.c_uint32()
+        ok = (C.c_uint32 * 2)(3, 1)
+        assert tq.lib.tusq_circuit_measure(h, ok, C.c_uint32(2), 1, C.byref(gi)) == 0
+        probs = (C.c_double * 3)(0.1, 0.1, 0.1)
+        assert tq.lib.tusq_circuit_pauli_noise(h, gi, probs, C.c_uint32(3)) == tq._lib.TUSQ_EINVAL
+    finally:
+        tq.lib.tusq_circuit_destroy(h)
+
+
+def test_measurement_circuits_refuse_other_traversals_and_pruning():
+    from workloads import syndrome_rounds
+    c = syndrome_rounds(2, 2, 0.01, 0.01)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=100, seed=1, prune=0)
+    t = tq.Tree(ec, o)
+    with pytest.raises(tq.TusqError) as e:
+        tq.tusq_plan_counters(ec, t, o)
+    assert e.value.code == tq._lib.TUSQ_EUNSUPPORTED
