@@ -49,7 +49,7 @@ def _args():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="brick26",
-                   choices=["brick26", "ising30", "batch", "serve"])
+                   choices=["brick26", "ising30", "batch", "serve", "mcm"])
     p.add_argument("--leaves-per-step", type=int, default=8)
     p.add_argument("--shots", type=int, default=1_000_000)
     p.add_argument("--qubits", type=int, default=26)
@@ -74,6 +74,8 @@ def _args():
     p.add_argument("--serve-count", type=int, default=60)
     p.add_argument("--serve-nmax", type=int, default=28)
     p.add_argument("--serve-load", type=float, default=0.7)
+    p.add_argument("--mcm-qubits", type=int, default=22)
+    p.add_argument("--mcm-shots", type=int, default=2000)
     return p.parse_args()
 
 
@@ -476,6 +478,70 @@ def bench_serve(a, tq):
                                    f"c64/c128 50/50, load {a.serve_load}"}}
 
 
+def mcm_circuit(n, layers, every, width, seed):
+    """Brickwork (p1 = 1e-3, p2 = 1e-2) with a measure-and-reset layer of
+    `width` middle qubits after every `every` brickwork layers."""
+    from workloads import Circuit
+    from workloads.circuits import depol1, depol2
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    c = Circuit(n, name=f"brickwork_mcm_n{n}")
+    mid = list(range(n // 2 - width // 2, n // 2 - width // 2 + width))
+    for layer in range(layers):
+        for q in range(n):
+            c.add("U3", (q,), rng.random(3) * 2 * np.pi, depol1(1e-3))
+        for i in range(layer % 2, n - 1, 2):
+            c.add("CX", (i, i + 1), (), depol2(1e-2))
+        if (layer + 1) % every == 0:
+            c.add_measure(mid, reset=True)
+    return c
+
+
+def bench_mcm(a, tq):
+    """DFTT+Caching (Sec. III-B.2) on brickwork with mid-circuit
+    measure-and-reset layers: the whole tree for every cache capacity K,
+    with the operation counts of Eq. (3) and alpha(K)."""
+    n, S = a.mcm_qubits, a.mcm_shots
+    circ = mcm_circuit(n, 20, 5, 4, 11)
+    M = circ.n_measure_layers
+    ec = tq.Circuit(circ)
+    base = dict(shots=S, seed=3, prune=0, traversal="caching", want=3, profile=1, **{
+        k: v for k, v in _fusion(a).items() if k != "traversal"})
+    t0 = time.perf_counter()
+    tree = tq.Tree(ec, tq.tusq_opts_default(**base))
+    ecm_s = time.perf_counter() - t0
+    info = tree.info()
+    _log(f"[bench] mcm n={n} S={S} M={M}: {info['n_leaves']} tree leaves, ECM {ecm_s:.2f}s")
+    ctx = tq.Context(0)
+    rows = []
+    for K in [M] + list(range(M)):
+        o = tq.tusq_opts_default(**base, cache_capacity=K)
+        t1 = time.perf_counter()
+        r = tq.tusq_run_tree(ctx, ec, tree, o)
+        wall = time.perf_counter() - t1
+        ct = r.counters()
+        rows.append({"K": K, "wall_s": round(wall, 3), "shots_per_s": round(S / wall, 1),
+                     "ops": ct["paper_ops"], "sweeps": ct["passes_fwd"] + ct["passes_inv"],
+                     "measurement_edges": ct["mcm_edges"], "cache_pushes": ct["checkpoint_saves"],
+                     "cache_fetches": ct["checkpoint_restores"], "resets": ct["resets"],
+                     "final_leaves": ct["leaves"],
+                     "sweep_GBps": round(ct["sweep_bytes"] / max(ct["pass_seconds"], 1e-12) / 1e9, 1)})
+        _log(f"[bench] mcm K={K}: {rows[-1]}")
+    rows.sort(key=lambda x: x["K"])
+    n1, n2 = rows[0]["ops"], rows[M]["ops"]
+    for x in rows:
+        x["alpha"] = round((n1 - x["ops"]) / (n1 - n2), 4) if n1 != n2 else 1.0
+    ctx.close()
+    return {"metric": "noisy shots/sec with mid-circuit measurement layers (DFTT+Caching)",
+            "value": rows[M]["shots_per_s"], "unit": "shots/s", "n_gpus": 1, "dtype": "c128",
+            "data": "synthetic",
+            "config": {"workload": f"brickwork n={n} L=20 p1=1e-3 p2=1e-2 with a measure-and-reset "
+                                   f"layer of 4 middle qubits every 5 layers (M={M}), S={S}, "
+                                   f"whole tree, cache capacity K=0..{M}",
+                       "tree_leaves": info["n_leaves"], "host_ecm_seconds": round(ecm_s, 3)},
+            "by_cache_capacity": rows}
+
+
 def main():
     a = _args()
     if a.gpus != 1:
@@ -484,7 +550,7 @@ def main():
         sys.exit(2)
     import paper_2508_04880_amd as tq
     fn = {"brick26": bench_brick26, "ising30": bench_ising30, "batch": bench_batch,
-          "serve": bench_serve}[a.workload]
+          "serve": bench_serve, "mcm": bench_mcm}[a.workload]
     print(json.dumps(fn(a, tq)), flush=True)
 
 
