@@ -170,23 +170,31 @@ def cpu_baseline(circ, tokens_applied, shots, budget_s):
     the per-gate time is scaled to the gate and error applications the plain
     DFTT walk of the timed slices makes, and to their shots."""
     import oracle
+
+    def per_token_seconds(threads, budget):
+        oracle.set_threads(threads)
+        k = 2
+        while True:
+            t0 = time.perf_counter()
+            oracle.trajectory(circ, [], max_tokens=k)
+            elapsed = time.perf_counter() - t0
+            if elapsed > budget / 3 or k >= circ.n_gates:
+                break
+            k = min(circ.n_gates, k * 3)
+        return elapsed / k, k, elapsed
+
     threads = min(os.cpu_count() or 1, 16)
+    per_token, k, elapsed = per_token_seconds(threads, budget_s)
+    # the same on one core, on a smaller budget
+    one, k1, e1 = per_token_seconds(1, budget_s / 3)
     oracle.set_threads(threads)
-    k = 2
-    while True:
-        t0 = time.perf_counter()
-        oracle.trajectory(circ, [], max_tokens=k)
-        elapsed = time.perf_counter() - t0
-        if elapsed > budget_s / 3 or k >= circ.n_gates:
-            break
-        k = min(circ.n_gates, k * 3)
-    per_token = elapsed / k
     return {"value": round(shots / (per_token * tokens_applied), 6), "unit": "shots/s",
             "cores": threads, "kind": "oracle",
+            "single_core_value": round(shots / (one * tokens_applied), 6),
             "sample": f"first {k} gates of the circuit applied by the oracle in "
-                      f"{elapsed:.1f} s (complex128, {threads} OpenMP threads), scaled to the "
-                      f"{tokens_applied} gate/error applications and {shots} shots of the "
-                      f"timed slices"}
+                      f"{elapsed:.1f} s (complex128, {threads} OpenMP threads; one core: "
+                      f"{k1} gates in {e1:.1f} s), scaled to the {tokens_applied} gate/error "
+                      f"applications and {shots} shots of the timed slices"}
 
 
 def measured_traffic(kernel):
@@ -304,6 +312,10 @@ def bench_brick26(a, tq):
                      "copy_GBps": round(copy_gbs, 1),
                      "frac_of_copy": round(gbs / copy_gbs, 4)},
         "sweeps_per_leaf": round(r128["passes"] / max(r128["leaves"], 1), 2),
+        # the whole job projected from the slices: every tree leaf at the
+        # slices' sweeps per leaf and per-sweep time (host ECM excluded)
+        "projected_full_job_hours": round(info["n_leaves"] * r128["passes"] / max(r128["leaves"], 1)
+                                          * avg_us * 1e-6 / 3600, 1),
         "gate_applications_per_leaf": round(r128["tokens"] / max(r128["leaves"], 1), 1),
     }
     if r64:

@@ -314,6 +314,12 @@ int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_o
 
 /* ---- results --------------------------------------------------------------- */
 int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len);
+/* The same 2^n FP64 values written into caller device memory (e.g. a
+ * framework tensor's data pointer) on the caller's HIP stream (NULL = the
+ * null stream); dptr must hold 2^n doubles on the device the result came
+ * from.  Returns once the copy has completed.  EINVAL without a
+ * distribution or with a NULL pointer; EDEVICE if the copy fails.        */
+int tusq_result_distribution_device(const tusq_result *r, void *dptr, void *hip_stream);
 int tusq_result_samples(const tusq_result *r, uint64_t *out, uint64_t len);
 int tusq_result_norms(const tusq_result *r, double *out, uint64_t len);
 int tusq_result_counters(const tusq_result *r, tusq_counters *out);

@@ -104,6 +104,7 @@ _SIGS = {
     "tusq_job_times": (C.c_int, [P, C.c_uint64, P, P, P]),
     "tusq_run_batch": (C.c_int, [P, P, P, C.c_size_t, P]),
     "tusq_result_distribution": (C.c_int, [P, P, C.c_uint64]),
+    "tusq_result_distribution_device": (C.c_int, [P, P, P]),
     "tusq_result_samples": (C.c_int, [P, P, C.c_uint64]),
     "tusq_result_norms": (C.c_int, [P, P, C.c_uint64]),
     "tusq_result_counters": (C.c_int, [P, P]),
@@ -285,6 +286,12 @@ class Result:
         out = np.zeros(1 << self.n, np.float64)
         check(lib.tusq_result_distribution(self.h, _ptr(out), C.c_uint64(out.size)))
         return out
+
+    def distribution_to_device(self, dptr: int, stream: int = 0) -> None:
+        """Write the distribution into 2^n doubles of device memory at dptr
+        (e.g. a tensor's data_ptr()) on the given HIP stream handle."""
+        check(lib.tusq_result_distribution_device(self.h, C.c_void_p(dptr),
+                                                  C.c_void_p(stream or None)))
 
     def samples(self) -> np.ndarray:
         k = C.c_uint64()

@@ -581,6 +581,17 @@ int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len) {
     });
 }
 
+int tusq_result_distribution_device(const tusq_result *r, void *dptr, void *hip_stream) {
+    return guarded([&] {
+        need(r && dptr, "NULL argument");
+        need(!r->r.dist.empty(), "result holds no distribution");
+        const auto s = static_cast<hipStream_t>(hip_stream);
+        hip_check(hipMemcpyAsync(dptr, r->r.dist.data(), r->r.dist.size() * 8, hipMemcpyHostToDevice, s),
+                  "distribution to device");
+        hip_check(hipStreamSynchronize(s), "sync");
+    });
+}
+
 int tusq_result_samples(const tusq_result *r, uint64_t *out, uint64_t len) {
     return guarded([&] {
         need(r && out, "NULL argument");

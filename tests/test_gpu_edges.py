@@ -196,3 +196,17 @@ def test_checkpoint_budget_is_enforced(ctx):
         assert e.value.code == -2 and "checkpoint" in str(e.value)
     finally:
         small.close()
+
+
+def test_distribution_written_to_device_memory(ctx):
+    """tusq_result_distribution_device fills a torch tensor on the GPU with
+    the same values the host copy returns, on a caller stream."""
+    import torch
+    _say("[gpu] distribution to device memory")
+    c = brickwork(10, 6, 2e-3, 2e-2, 5)
+    t, r = _run(ctx, c, 2000, 3)
+    host = r.distribution()
+    dev = torch.full((1 << 10,), -1.0, dtype=torch.float64, device="cuda:0")
+    st = torch.cuda.Stream(device="cuda:0")
+    r.distribution_to_device(dev.data_ptr(), st.cuda_stream)
+    assert np.array_equal(dev.cpu().numpy(), host)
