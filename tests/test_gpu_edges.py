@@ -199,14 +199,25 @@ def test_checkpoint_budget_is_enforced(ctx):
 
 
 def test_distribution_written_to_device_memory(ctx):
-    """tusq_result_distribution_device fills a torch tensor on the GPU with
-    the same values the host copy returns, on a caller stream."""
-    import torch
+    """tusq_result_distribution_device fills device memory (allocated here
+    through the HIP runtime) with the values the host copy returns, on a
+    caller stream."""
+    import ctypes as C
     _say("[gpu] distribution to device memory")
     c = brickwork(10, 6, 2e-3, 2e-2, 5)
     t, r = _run(ctx, c, 2000, 3)
     host = r.distribution()
-    dev = torch.full((1 << 10,), -1.0, dtype=torch.float64, device="cuda:0")
-    st = torch.cuda.Stream(device="cuda:0")
-    r.distribution_to_device(dev.data_ptr(), st.cuda_stream)
-    assert np.array_equal(dev.cpu().numpy(), host)
+    hip = C.CDLL("libamdhip64.so")
+    nbytes = host.nbytes
+    dptr, stream = C.c_void_p(), C.c_void_p()
+    assert hip.hipMalloc(C.byref(dptr), C.c_size_t(nbytes)) == 0
+    try:
+        assert hip.hipStreamCreate(C.byref(stream)) == 0
+        r.distribution_to_device(dptr.value, stream.value)
+        back = np.full_like(host, -1.0)
+        assert hip.hipMemcpy(back.ctypes.data_as(C.c_void_p), dptr, C.c_size_t(nbytes), 2) == 0
+        assert np.array_equal(back, host)
+    finally:
+        if stream.value:
+            hip.hipStreamDestroy(stream)
+        hip.hipFree(dptr)

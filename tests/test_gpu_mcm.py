@@ -139,3 +139,25 @@ def test_refusals(ctx):
         assert e3.value.code == -2
     finally:
         small.close()
+
+
+def test_leaf_range_and_no_outputs(ctx):
+    """A depth-first slice of the tree starts from the root and draws its
+    samples with the slice's own counters, as the oracle's walk over the same
+    slice does; want = 0 runs the walk and returns only counters."""
+    _say("[gpu] mcm leaf range")
+    c = _mixed(9)
+    S, seed = 2000, 5
+    ot = oracle.ecm(c, S, seed, prune=False)
+    lb, le = 3, max(4, ot.n_leaves - 5)
+    dist, samples, oc, _ = oracle.run_mcm(c, ot, seed, 2, leaf_begin=lb, leaf_end=le)
+    t, r = _run(ctx, c, S, seed, 2, leaf_begin=lb, leaf_end=le)
+    np.testing.assert_allclose(r.distribution(), dist, atol=1e-10, rtol=0)
+    assert np.count_nonzero(r.samples() != samples) <= 2
+    ct = r.counters()
+    for k in COUNTERS:
+        assert ct[k] == oc[k], k
+    t2, r2 = _run(ctx, c, S, seed, 2, want=0)
+    _, _, oc2, _ = oracle.run_mcm(c, ot, seed, 2, want_dist=False, want_samples=False)
+    assert r2.counters()["paper_ops"] == oc2["paper_ops"]
+    assert len(r2.samples()) == 0
