@@ -74,6 +74,8 @@ def _args():
     p.add_argument("--serve-count", type=int, default=60)
     p.add_argument("--serve-nmax", type=int, default=28)
     p.add_argument("--serve-load", type=float, default=0.7)
+    p.add_argument("--checkpoint-slots", type=int, default=0,
+                   help="checkpoint traversal: most branch states kept (0 = no bound)")
     p.add_argument("--mcm-qubits", type=int, default=22)
     p.add_argument("--mcm-shots", type=int, default=2000)
     return p.parse_args()
@@ -86,7 +88,8 @@ def _log(*a):
 def _fusion(a):
     return dict(fusion_max_ops=a.fusion_max_ops, fusion_max_qubits=a.fusion_max_qubits,
                 fusion_low_qubits=a.fusion_low_qubits, sweep_kernel=a.sweep_kernel,
-                drift_bound=a.drift_bound, traversal=a.traversal)
+                drift_bound=a.drift_bound, traversal=a.traversal,
+                checkpoint_slots=a.checkpoint_slots)
 
 
 def copy_bandwidth(nbytes, reps=10):
@@ -289,7 +292,9 @@ def bench_brick26(a, tq):
         "data": "synthetic",
         "config": {"workload": f"random brickwork n={a.qubits} L={a.layers} p1=1e-3 "
                                f"p2=1e-2 S={a.shots}, depth-first slices of {L} leaves, "
-                               f"{a.traversal}",
+                               f"{a.traversal}" + (f" ({a.checkpoint_slots} slots)"
+                                                   if a.traversal == "checkpoint" and
+                                                   a.checkpoint_slots else ""),
                    "qubits": a.qubits, "layers": a.layers, "shots": a.shots,
                    "leaves_per_step": L, "first_timed_leaf": first,
                    "tree_leaves": info["n_leaves"], "host_ecm_seconds": round(ecm_s, 3),

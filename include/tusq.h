@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 5u
+#define TUSQ_ABI_VERSION 6u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -137,6 +137,13 @@ typedef struct {
     uint32_t cache_capacity;   /* TUSQ_CACHING: pre-measurement states kept
                                   (K of Sec. III-B.2; device slots of one
                                   state each)                                 */
+    uint32_t checkpoint_slots; /* TUSQ_CHECKPOINT: most branch states kept
+                                  (0 = as many as the walk needs).  When a save
+                                  finds them all in use, the state farthest
+                                  from the leaves is dropped, and a leaf
+                                  branching at a dropped depth undoes the
+                                  previous leaf back to it instead (a hybrid
+                                  of checkpointing and uncomputation)        */
 } tusq_opts;
 
 typedef struct {

@@ -67,6 +67,7 @@ def lib():
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oc_run_mcm.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64,
                                  C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oc_set_checkpoint_slots.argtypes = [C.c_uint64]
         L.oc_uniform53.restype = C.c_double
         L.oc_uniform53.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                    C.c_int]
@@ -278,10 +279,13 @@ TRAVERSAL = {"dftt": 0, "naive": 1, "hybrid": 2, "checkpoint": 3}
 
 
 def run(circ, tree: OracleTree, seed: int, traversal: str = "dftt", leaf_begin: int = 0,
-        leaf_end: int = 0, want_dist: bool = True, want_samples: bool = True):
+        leaf_end: int = 0, want_dist: bool = True, want_samples: bool = True,
+        checkpoint_slots: int = 0):
     """Walk the tree: returns (dist or None, samples or None, counters dict,
-    per-leaf norms)."""
+    per-leaf norms).  checkpoint_slots bounds the states the checkpoint
+    traversal keeps (0 = no bound)."""
     h = _CircuitHandle(circ)
+    lib().oc_set_checkpoint_slots(C.c_uint64(checkpoint_slots))
     le = leaf_end or tree.n_leaves
     dist = np.zeros(1 << circ.n, np.float64) if want_dist else None
     nshots = int(tree.shots[leaf_begin:le].sum())

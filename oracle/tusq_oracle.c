@@ -1061,6 +1061,14 @@ static uint64_t draw_index(const double *cdf, uint64_t N, double x)
  * (d >> 1, l, 0), half d & 1; u = (v >> 11) * 2^-53; target u * norm.
  * counters: fwd gates, inv gates, fwd paulis, inv paulis, resets, leaves,
  * draws, then the gates and paulis a final return to the root would undo. */
+/* Checkpoint traversal with at most `slots` kept states (0 = no limit):
+ * when a save finds the stack full, the state farthest from the leaves (the
+ * bottom of the stack) is dropped; a leaf whose branch depth is no longer
+ * kept undoes the previous leaf back to it instead (the hybrid of
+ * checkpointing and uncomputation). */
+static uint64_t ckpt_slots_limit = 0;
+void oc_set_checkpoint_slots(uint64_t slots) { ckpt_slots_limit = slots; }
+
 int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, uint64_t lb,
            uint64_t le, double *dist, uint64_t *samples, uint64_t *counters, double *norms)
 {
@@ -1107,9 +1115,14 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
             uint64_t d = bd[l - lb];
             while (nk > 0 && kdepth[nk - 1] > d) free(kstate[--nk]);
             if (d > 0) {
-                if (nk == 0 || kdepth[nk - 1] != d) return -2;  /* unreachable by construction */
-                memcpy(psi, kstate[nk - 1], sizeof(cplx) * N);
-                ct.restores++;
+                if (nk > 0 && kdepth[nk - 1] == d) {
+                    memcpy(psi, kstate[nk - 1], sizeof(cplx) * N);
+                    ct.restores++;
+                } else {
+                    /* its state was dropped (slot limit): undo back to it */
+                    if (!ckpt_slots_limit) return -2;  /* unreachable without a limit */
+                    for (uint64_t i = na; i > d; --i) apply_token(c, ka, ta[i - 1], psi, 1, &ct);
+                }
                 from = d;
                 reset = 0;
             } else {
@@ -1136,6 +1149,13 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
                     if (dm == i) { keep = 1; break; }
                 }
                 if (keep) {
+                    if (ckpt_slots_limit && nk == ckpt_slots_limit) {
+                        /* full: drop the state farthest from the leaves */
+                        free(kstate[0]);
+                        memmove(kdepth, kdepth + 1, sizeof(uint64_t) * (nk - 1));
+                        memmove(kstate, kstate + 1, sizeof(cplx *) * (nk - 1));
+                        --nk;
+                    }
                     kdepth[nk] = i;
                     kstate[nk] = malloc(sizeof(cplx) * N);
                     memcpy(kstate[nk], psi, sizeof(cplx) * N);

@@ -668,31 +668,55 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
     std::vector<Tok> toks;
     std::vector<Fuser::Item> items;
     auto &ct = plan.counters;
-    // checkpoint traversal: the states at the cut depths of the current path,
-    // innermost last (slot = position in this stack)
+    // checkpoint traversal: the states kept at cut depths of the current
+    // path, innermost last, each in a device slot; with a slot limit a full
+    // stack drops its bottom (the state farthest from the leaves)
     const bool ckpt = o.traversal == TUSQ_CHECKPOINT;
-    std::vector<uint64_t> saved;
+    const uint64_t slot_limit = o.checkpoint_slots;
+    struct Kept {
+        uint64_t depth;
+        uint64_t slot;
+    };
+    std::vector<Kept> saved;
+    std::vector<uint64_t> free_slots;
+    uint64_t next_slot = 0;
+    auto release = [&](const Kept &k) { free_slots.push_back(k.slot); };
     if (keep_paths) plan.path_off.push_back(0);
     for (const Comp &cp : comps) {
         if (cp.reset) {
             plan.steps.push_back(Step{ST_RESET, 0});
             ct.resets++;
             applied.clear();
+            for (const Kept &k : saved) release(k);
             saved.clear();
         } else if (ckpt) {
-            // branch depth is a cut: its state was saved on the way down
-            while (!applied.empty() && applied.back().start >= cp.from) applied.pop_back();
-            while (!saved.empty() && saved.back() > cp.from) saved.pop_back();
+            while (!saved.empty() && saved.back().depth > cp.from) {
+                release(saved.back());
+                saved.pop_back();
+            }
             if (cp.from == 0) {
                 plan.steps.push_back(Step{ST_RESET, 0});
                 ct.resets++;
                 applied.clear();
+                for (const Kept &k : saved) release(k);
                 saved.clear();
-            } else {
-                if (saved.empty() || saved.back() != cp.from)
-                    fail(TUSQ_EINVAL, "internal: no checkpoint at a branch depth");
-                plan.steps.push_back(Step{ST_RESTORE, saved.size() - 1});
+            } else if (!saved.empty() && saved.back().depth == cp.from) {
+                // the branch depth's state was kept on the way down
+                while (!applied.empty() && applied.back().start >= cp.from) applied.pop_back();
+                plan.steps.push_back(Step{ST_RESTORE, saved.back().slot});
                 ct.checkpoint_restores++;
+            } else {
+                // dropped for the slot limit: undo as plain DFTT does
+                if (!slot_limit) fail(TUSQ_EINVAL, "internal: no checkpoint at a branch depth");
+                while (!applied.empty() && applied.back().start >= cp.from) {
+                    const Seg &s = applied.back();
+                    for (uint32_t p = s.p1; p > s.p0; --p) plan.steps.push_back(Step{ST_INV, p - 1});
+                    ct.passes_inv += s.p1 - s.p0;
+                    ct.inv_gates += s.gates;
+                    ct.inv_paulis += s.paulis;
+                    ct.paper_ops += s.ops;
+                    applied.pop_back();
+                }
             }
         } else {
             while (!applied.empty() && applied.back().start >= cp.from) {
@@ -724,10 +748,21 @@ Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_p
             ct.paper_ops += nops;
             applied.push_back(Seg{pr.first, pr.second, a, ng, np, nops});
             if (ckpt && b < cp.len) {  // a later leaf branches here
-                plan.steps.push_back(Step{ST_SAVE, saved.size()});
-                saved.push_back(b);
+                if (slot_limit && saved.size() == slot_limit) {
+                    release(saved.front());
+                    saved.erase(saved.begin());
+                }
+                uint64_t slot;
+                if (!free_slots.empty()) {
+                    slot = free_slots.back();
+                    free_slots.pop_back();
+                } else {
+                    slot = next_slot++;
+                }
+                plan.steps.push_back(Step{ST_SAVE, slot});
+                saved.push_back(Kept{b, slot});
                 ct.checkpoint_saves++;
-                plan.checkpoint_slots = std::max<uint64_t>(plan.checkpoint_slots, saved.size());
+                plan.checkpoint_slots = next_slot;
             }
             a = b;
         }

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 5
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 6
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -95,6 +95,16 @@ def test_schedule_counts_match_oracle(trav, name, make, S):
     for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets", "leaves",
               "ret_gates", "ret_paulis", "checkpoint_saves", "checkpoint_restores", "paper_ops"):
         assert pc[k] == oc[k], k
+    if trav == "checkpoint":
+        for slots in (1, 2, 3):
+            o3 = tq.tusq_opts_default(shots=S, seed=5, prune=0, traversal=trav,
+                                      checkpoint_slots=slots)
+            pc3 = tq.tusq_plan_counters(ec, et, o3)
+            _, _, oc3, _ = oracle.run(c, ot, 5, traversal=trav, want_dist=False,
+                                      want_samples=False, checkpoint_slots=slots)
+            for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "resets",
+                      "checkpoint_saves", "checkpoint_restores", "paper_ops"):
+                assert pc3[k] == oc3[k], (slots, k)
     # a leaf range starts from the root
     nl = et.info()["n_leaves"]
     if nl > 6:

@@ -151,27 +151,31 @@ def test_thermal_relaxation_noise_matches_oracle(ctx, precision):
     np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
 
 
+@pytest.mark.parametrize("slots", [0, 2])
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 @pytest.mark.parametrize("n,kmax", [(10, 6), (18, 12)])
-def test_checkpoint_traversal_matches_oracle(ctx, precision, n, kmax):
+def test_checkpoint_traversal_matches_oracle(ctx, precision, n, kmax, slots):
     """Branch checkpoints kept in device memory: the distribution equals the
     oracle's, no gate or Pauli is ever undone, and the save and restore
     counts equal the oracle's walk of the same tree."""
-    _say(f"[gpu] checkpoint n={n} kmax={kmax} {precision}")
+    _say(f"[gpu] checkpoint n={n} kmax={kmax} {precision} slots={slots}")
     c = brickwork(n, 8, 3e-3, 2e-2, 31)
     S, seed = 4000, 13
     ot = oracle.ecm(c, S, seed)
-    dist, _, oc, _ = oracle.run(c, ot, seed, traversal="checkpoint", want_samples=False)
+    dist, _, oc, _ = oracle.run(c, ot, seed, traversal="checkpoint", want_samples=False,
+                                checkpoint_slots=slots)
     t, r = _run(ctx, c, S, seed, traversal="checkpoint", precision=precision,
-                fusion_max_qubits=kmax, drift_bound=1.0)
+                fusion_max_qubits=kmax, drift_bound=1.0, checkpoint_slots=slots)
     assert t.serialize() == ot.serialize()
     tol = 1e-10 if precision == "c128" else 1e-4
     np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
     ct = r.counters()
-    assert ct["inv_gates"] == 0 and ct["inv_paulis"] == 0
-    for k in ("checkpoint_saves", "checkpoint_restores", "resets", "leaves"):
+    for k in ("checkpoint_saves", "checkpoint_restores", "resets", "leaves", "inv_gates",
+              "inv_paulis", "paper_ops"):
         assert ct[k] == oc[k], k
-    assert ct["checkpoint_restores"] == ot.n_leaves - 1
+    if not slots:
+        assert ct["inv_gates"] == 0 and ct["inv_paulis"] == 0
+        assert ct["checkpoint_restores"] == ot.n_leaves - 1
 
 
 def test_checkpoint_budget_is_enforced(ctx):

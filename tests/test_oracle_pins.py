@@ -359,6 +359,10 @@ def test_lossless_pipeline_equals_definition(fam):
         for trav in ("dftt", "naive", "hybrid", "checkpoint"):
             dist, _, _, _ = oracle.run(c, t, seed, traversal=trav, want_samples=False)
             np.testing.assert_allclose(dist, want, atol=1e-12)
+        for slots in (1, 2):
+            dist, _, _, _ = oracle.run(c, t, seed, traversal="checkpoint", want_samples=False,
+                                       checkpoint_slots=slots)
+            np.testing.assert_allclose(dist, want, atol=1e-12)
 
 
 def test_commutation_only_merges():
@@ -579,3 +583,23 @@ def test_thermal_twirl_on_cx_is_the_product_channel():
     for bad in ((-1.0, 1.0, 1.0), (1.0, 0.0, 1.0), (1.0, 1.0, 0.0), (1.0, 1.0, 2.5)):
         with pytest.raises(ValueError):
             oracle.thermal_probs(*bad)
+
+
+def test_bounded_checkpoints_trade_undo_for_memory():
+    """With at most K kept states the checkpoint walk saves at the same
+    depths, restores where the state is still kept and undoes (as plain
+    DFTT) where it was dropped: every transition is one or the other, undo
+    work falls as K grows and vanishes without a bound."""
+    c = brickwork(6, 8, 0.02, 0.05, seed=3)
+    t = oracle.ecm(c, 3000, 4, prune=False)
+    _, _, dftt, _ = oracle.run(c, t, 4, traversal="dftt", want_dist=False, want_samples=False)
+    undo = lambda x: x["inv_gates"] + x["inv_paulis"]
+    runs = [oracle.run(c, t, 4, traversal="checkpoint", want_dist=False, want_samples=False,
+                       checkpoint_slots=k)[2] for k in (1, 2, 3, 0)]
+    for r in runs:
+        assert r["checkpoint_saves"] == runs[-1]["checkpoint_saves"]
+        assert r["fwd_gates"] + r["fwd_paulis"] == dftt["fwd_gates"] + dftt["fwd_paulis"]
+        assert undo(r) <= undo(dftt)
+    assert undo(runs[-1]) == 0 and runs[-1]["checkpoint_restores"] == t.n_leaves - 1
+    assert all(undo(a) >= undo(b) for a, b in zip(runs, runs[1:]))
+    assert all(a["checkpoint_restores"] <= b["checkpoint_restores"] for a, b in zip(runs, runs[1:]))
