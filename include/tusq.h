@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 6u
+#define TUSQ_ABI_VERSION 7u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -144,6 +144,11 @@ typedef struct {
                                   branching at a dropped depth undoes the
                                   previous leaf back to it instead (a hybrid
                                   of checkpointing and uncomputation)        */
+    uint32_t fusion_search;    /* how a sweep picks its tile qubits: 0 auto
+                                  (= 2), 1 the qubits the tokens claim in
+                                  circuit order, 2 also every window of
+                                  consecutive qubits above the low ones (the
+                                  candidate taking the most tokens wins)    */
 } tusq_opts;
 
 typedef struct {

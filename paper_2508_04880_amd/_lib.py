@@ -47,7 +47,8 @@ class tusq_opts(C.Structure):
                 ("fusion_max_ops", C.c_uint32), ("fusion_low_qubits", C.c_uint32),
                 ("profile", C.c_uint32), ("debug_fail_at_step", C.c_int32),
                 ("host_threads", C.c_uint32), ("sweep_kernel", C.c_uint32),
-                ("cache_capacity", C.c_uint32), ("checkpoint_slots", C.c_uint32)]
+                ("cache_capacity", C.c_uint32), ("checkpoint_slots", C.c_uint32),
+                ("fusion_search", C.c_uint32)]
 
 
 class tusq_counters(C.Structure):
@@ -117,7 +118,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 6
+ABI_VERSION = 7
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")

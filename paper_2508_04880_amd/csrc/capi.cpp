@@ -461,8 +461,8 @@ int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, cons
         // (tile qubits, low qubits, ops per sweep, kernel): kernel 1 = one tile
         // per workgroup, 4 = persistent with register prefetch (16 amplitudes
         // per thread), 5 = persistent with 8 per thread
-        static const uint32_t cand[][4] = {{12, 4, 24, 1}, {12, 4, 16, 4}, {12, 4, 24, 4},
-                                           {12, 4, 32, 4}, {11, 4, 24, 4}, {11, 4, 16, 5}};
+        static const uint32_t cand[][4] = {{12, 4, 32, 4}, {12, 4, 24, 4}, {13, 4, 32, 4},
+                                           {13, 5, 32, 4}, {12, 4, 32, 1}, {11, 4, 24, 5}};
         const uint64_t L = t->t.leaves();
         const uint64_t lb = std::min<uint64_t>(o->leaf_begin, L ? L - 1 : 0);
         const uint64_t le = std::min<uint64_t>(L, lb + std::max<uint32_t>(1, probe_leaves));

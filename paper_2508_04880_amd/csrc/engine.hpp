@@ -148,6 +148,8 @@ struct FusionParams {
     uint32_t max_qubits;  // tile qubits
     uint32_t max_ops;     // dense ops per sweep
     uint32_t low_qubits;  // lowest qubits every tile contains (coalescing)
+    bool window_search;   // also try the low qubits plus a window of
+                          // consecutive qubits as a sweep's tile
 };
 
 struct Plan {

@@ -429,6 +429,61 @@ struct Fuser {
         M2 m2;            // 1-qubit matrix (gate or Pauli)
     };
 
+    // Tokens one sweep would take from `rest` if its tile started as the
+    // qubits of `init` (nq of them): the sweep's admission rule (a token is
+    // taken unless one of its qubits is blocked, it would grow the tile past
+    // max_qubits or the sweep holds max_ops dense ops; a token not taken
+    // blocks its qubits), without building matrices.  Stops early once
+    // nothing more can be taken.
+    uint32_t dry_run(const std::vector<Item> &items, const std::vector<uint32_t> &rest,
+                     const std::vector<uint8_t> &init, uint32_t nq0) {
+        const uint32_t n = c.n;
+        std::vector<uint8_t> inq(init), blocked(n, 0);
+        std::vector<int> last(n, -1);
+        std::vector<uint8_t> one;  // per live-or-dead op: 1-qubit?
+        uint32_t nq = nq0, live = 0, taken = 0, nblk_in = 0;
+        for (uint32_t idx : rest) {
+            const Item &it = items[idx];
+            const bool blk = blocked[it.qa] || (it.two && blocked[it.qb]);
+            const uint32_t need = nq + (inq[it.qa] ? 0 : 1) + (it.two && !inq[it.qb] ? 1 : 0);
+            if (blk || need > fp.max_qubits) {
+                for (uint32_t q : {it.qa, it.two ? it.qb : it.qa})
+                    if (!blocked[q]) {
+                        blocked[q] = 1;
+                        if (inq[q]) ++nblk_in;
+                    }
+                // a full tile whose qubits are all blocked takes nothing more
+                if (nq == fp.max_qubits && nblk_in == nq) break;
+                continue;
+            }
+            for (uint32_t q : {it.qa, it.two ? it.qb : it.qa})
+                if (!inq[q]) {
+                    inq[q] = 1;
+                    ++nq;
+                    if (blocked[q]) ++nblk_in;
+                }
+            ++taken;
+            if (!it.two) {
+                if (last[it.qa] < 0) {
+                    one.push_back(1);
+                    last[it.qa] = static_cast<int>(one.size()) - 1;
+                    ++live;
+                }
+            } else {
+                const int la = last[it.qa], lb = last[it.qb];
+                if (!(la >= 0 && la == lb)) {
+                    if (la >= 0 && one[la]) --live;
+                    if (lb >= 0 && one[lb]) --live;
+                    one.push_back(0);
+                    last[it.qa] = last[it.qb] = static_cast<int>(one.size()) - 1;
+                    ++live;
+                }
+            }
+            if (live >= fp.max_ops) break;
+        }
+        return taken;
+    }
+
     // Fuse one segment; appends passes to the plan, returns their range.
     std::pair<uint32_t, uint32_t> fuse(const std::vector<Item> &items) {
         const uint32_t first = static_cast<uint32_t>(plan.passes.size());
@@ -436,8 +491,9 @@ struct Fuser {
         std::vector<uint32_t> rest(items.size());
         for (uint32_t i = 0; i < items.size(); ++i) rest[i] = i;
         const bool whole = n <= fp.max_qubits;
+        const uint32_t low = std::min(fp.low_qubits, n);
         std::vector<int> last(n, -1);
-        std::vector<uint8_t> inq(n, 0), blocked(n, 0);
+        std::vector<uint8_t> inq(n, 0), blocked(n, 0), cand(n, 0), best(n, 0);
         while (!rest.empty()) {
             std::vector<BuildOp> ops;
             std::fill(last.begin(), last.end(), -1);
@@ -448,7 +504,26 @@ struct Fuser {
             if (whole) {
                 for (uint32_t q = 0; q < n; ++q) addq(q);
             } else {
-                for (uint32_t q = 0; q < std::min(fp.low_qubits, n); ++q) addq(q);
+                for (uint32_t q = 0; q < low; ++q) addq(q);
+                if (fp.window_search && fp.max_qubits > low) {
+                    // the tile the tokens claim in order (the start above), or
+                    // the low qubits plus a window of consecutive qubits:
+                    // whichever takes the most tokens this sweep
+                    const uint32_t w = fp.max_qubits - low;
+                    uint32_t best_take = dry_run(items, rest, inq, nq), best_a = 0;
+                    for (uint32_t a = low; a + w <= n; ++a) {
+                        std::fill(cand.begin(), cand.end(), 0);
+                        for (uint32_t q = 0; q < low; ++q) cand[q] = 1;
+                        for (uint32_t q = a; q < a + w; ++q) cand[q] = 1;
+                        const uint32_t tk = dry_run(items, rest, cand, low + w);
+                        if (tk > best_take) {
+                            best_take = tk;
+                            best_a = a;
+                        }
+                    }
+                    if (best_a)
+                        for (uint32_t q = best_a; q < best_a + w; ++q) addq(q);
+                }
             }
             uint32_t live = 0, gates = 0, paulis = 0;
             std::vector<uint32_t> keep;
@@ -589,12 +664,13 @@ uint64_t pass_flops_per_amp(const Plan &plan, const Pass &p) {
 FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o) {
     FusionParams fp;
     // tiles of 2^12 amplitudes (64 KiB complex128, 32 KiB complex64) with the
-    // 4 lowest qubits always in the tile (256-byte / 128-byte runs) and up to
-    // 24 dense ops per sweep: the fastest shape measured on the 26-qubit
-    // brickwork slice in both precisions
+    // 4 lowest qubits always in the tile (256-byte / 128-byte runs), up to 32
+    // dense ops per sweep and the window search for the tile qubits: the
+    // fastest shape measured on the 26-qubit brickwork slice
     fp.max_qubits = o.fusion_max_qubits ? o.fusion_max_qubits : 12;
-    fp.max_ops = o.fusion_max_ops ? o.fusion_max_ops : 24;
+    fp.max_ops = o.fusion_max_ops ? o.fusion_max_ops : 32;
     fp.low_qubits = o.fusion_low_qubits ? o.fusion_low_qubits : 4;
+    fp.window_search = o.fusion_search != 1;
     if (fp.max_qubits > KMAX) fp.max_qubits = KMAX;
     if (fp.low_qubits > fp.max_qubits - 2) fp.low_qubits = fp.max_qubits - 2;
     (void)n;

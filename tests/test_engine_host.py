@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 6
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 7
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -172,9 +172,10 @@ def _run_plan_numpy(c, dump, weights, lb):
     return acc
 
 
+@pytest.mark.parametrize("search", [1, 2])
 @pytest.mark.parametrize("trav", ["dftt", "naive", "hybrid", "checkpoint"])
 @pytest.mark.parametrize("kmax,low,maxops", [(3, 1, 2), (4, 2, 5), (5, 3, 12), (16, 5, 12)])
-def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops):
+def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops, search):
     c = brickwork(7, 8, 0.02, 0.05, 11)
     S = 3000
     ot = oracle.ecm(c, S, 3, prune=True, alpha=(1, 50), beta=20)
@@ -182,7 +183,7 @@ def test_fused_plan_reproduces_oracle_distribution(trav, kmax, low, maxops):
     ec = tq.Circuit(c)
     o = tq.tusq_opts_default(shots=S, seed=3, alpha=(1, 50), beta=20, traversal=trav,
                              fusion_max_qubits=kmax, fusion_low_qubits=low,
-                             fusion_max_ops=maxops)
+                             fusion_max_ops=maxops, fusion_search=search)
     et = tq.Tree(ec, o)
     dump = tq.tusq_plan_dump(ec, et, o)
     if kmax < c.n:
@@ -424,3 +425,20 @@ def test_measurement_circuits_refuse_other_traversals_and_pruning():
     with pytest.raises(tq.TusqError) as e:
         tq.tusq_plan_counters(ec, t, o)
     assert e.value.code == tq._lib.TUSQ_EUNSUPPORTED
+
+
+def test_window_search_fuses_brickwork_into_fewer_sweeps():
+    """Tiles chosen as the low qubits plus the best window of consecutive
+    qubits take more tokens per sweep than the tokens-in-order tile on a
+    nearest-neighbour brickwork, at the same dense-op work."""
+    c = brickwork(16, 30, 1e-3, 1e-2, 2)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=2000, seed=1, leaf_begin=0, leaf_end=4)
+    t = tq.Tree(ec, o)
+    got = {}
+    for search in (1, 2):
+        o = tq.tusq_opts_default(shots=2000, seed=1, leaf_begin=0, leaf_end=4,
+                                 fusion_max_qubits=8, fusion_max_ops=32, fusion_search=search)
+        got[search] = tq.tusq_plan_counters(ec, t, o)
+    assert got[2]["passes_fwd"] < 0.8 * got[1]["passes_fwd"]
+    assert got[2]["fwd_gates"] == got[1]["fwd_gates"]
