@@ -249,8 +249,8 @@ def test_autotuned_shape_is_valid_and_correct(ctx):
     tuned = tq.tusq_autotune(ctx, ec, t, o, 2)
     shape = (tuned.fusion_max_qubits, tuned.fusion_low_qubits, tuned.fusion_max_ops,
              tuned.sweep_kernel)
-    assert shape in {(12, 4, 24, 1), (12, 4, 16, 4), (12, 4, 24, 4), (12, 4, 32, 4),
-                     (11, 4, 24, 4), (11, 4, 16, 5)}
+    assert shape in {(12, 4, 32, 4), (12, 4, 24, 4), (13, 4, 32, 4), (13, 5, 32, 4),
+                     (12, 4, 32, 1), (11, 4, 24, 5)}
     again = tq.tusq_autotune(ctx, ec, t, o, 2)   # cached
     assert again.fusion_max_ops == tuned.fusion_max_ops
     r = tq.tusq_run_tree(ctx, ec, t, tuned)
