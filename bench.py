@@ -70,7 +70,7 @@ def _args():
                         "(default: the library's default shape, as profiled)")
     p.add_argument("--drift-bound", type=float, default=1e-5,
                    help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
-    p.add_argument("--batch-jobs", type=int, default=4096)
+    p.add_argument("--batch-jobs", type=int, default=1024)
     p.add_argument("--batch-chunk", type=int, default=256)
     p.add_argument("--batch-precisions", default="c128,c64")
     p.add_argument("--serve-count", type=int, default=60)
