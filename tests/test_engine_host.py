@@ -248,8 +248,21 @@ def _run_programs_numpy(c, dump, progs, weights):
         for lay_thr in (thr, end_thr):
             assert lay_thr[:lowc] == list(range(lowc))
         assert (e - b) % 2 == 0      # instructions run in pairs
-        for w0, mat in progs["instr"][b:e]:
+        # the kernel reads slot s from register array s % 2; an instruction
+        # writes the other array, except an in-place lane exchange (lane bits
+        # 4 / 5 named as 6 / 7), which must be followed by a no-op slot
+        loc, prev_inplace = 0, False
+        for s_, (w0, mat) in enumerate(progs["instr"][b:e]):
             typ, arg = int(w0) & 3, int(w0) >> 2
+            if typ == 1 and (arg & 7) == 7:
+                assert prev_inplace
+                prev_inplace = False
+                continue
+            assert not prev_inplace and loc == s_ % 2
+            inplace = typ == 3 and ((arg >> 3) & 7) >= 6
+            if not inplace:
+                loc ^= 1
+            prev_inplace = inplace
             if typ == 0:
                 reg, thr = _layout(k, r, arg, int(mat))
             elif typ == 1:
@@ -264,8 +277,12 @@ def _run_programs_numpy(c, dump, progs, weights):
                 # lane exchange: thread bits 0 .. 5 are the lane bits of full wavefronts
                 assert k - r >= 6
                 ri, h = arg & 7, (arg >> 3) & 7
+                if h >= 6:
+                    h -= 2
+                    assert h in (4, 5)
                 assert ri < r and h < 6
                 reg[ri], thr[h] = thr[h], reg[ri]
+        assert not prev_inplace and loc == 0
         assert (reg, thr) == (end_reg, end_thr)
     return acc
 
