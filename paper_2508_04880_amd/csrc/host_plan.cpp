@@ -493,7 +493,7 @@ struct Fuser {
         const bool whole = n <= fp.max_qubits;
         const uint32_t low = std::min(fp.low_qubits, n);
         std::vector<int> last(n, -1);
-        std::vector<uint8_t> inq(n, 0), blocked(n, 0), cand(n, 0), best(n, 0);
+        std::vector<uint8_t> inq(n, 0), blocked(n, 0), cand(n, 0);
         while (!rest.empty()) {
             std::vector<BuildOp> ops;
             std::fill(last.begin(), last.end(), -1);
@@ -511,6 +511,7 @@ struct Fuser {
                     // whichever takes the most tokens this sweep
                     const uint32_t w = fp.max_qubits - low;
                     uint32_t best_take = dry_run(items, rest, inq, nq), best_a = 0;
+                    bool window = false;
                     for (uint32_t a = low; a + w <= n; ++a) {
                         std::fill(cand.begin(), cand.end(), 0);
                         for (uint32_t q = 0; q < low; ++q) cand[q] = 1;
@@ -519,9 +520,10 @@ struct Fuser {
                         if (tk > best_take) {
                             best_take = tk;
                             best_a = a;
+                            window = true;
                         }
                     }
-                    if (best_a)
+                    if (window)
                         for (uint32_t q = best_a; q < best_a + w; ++q) addq(q);
                 }
             }
