@@ -272,6 +272,12 @@ def bench_brick26(a, tq):
         b64 = tuned_opts(a, tq, ctx, ec, tree, base, "c64", default_tune=False)
         run_slices(tq, ctx, ec, tree, b64, 1, 1, L, "c64")
         r64 = run_slices(tq, ctx, ec, tree, b64, first, a.steps, L, "c64")
+    # the same slices with branch states kept in device memory (checkpoint
+    # traversal, no slot bound): context for the plain-DFTT headline
+    rck = None
+    if a.traversal == "dftt":
+        bck = dict(b128, traversal="checkpoint", checkpoint_slots=0)
+        rck = run_slices(tq, ctx, ec, tree, bck, first, a.steps, L, "c128")
     value = r128["shots"] / r128["wall"]
     gbs = r128["sweep_bytes"] / r128["pass_seconds"] / 1e9
     per_launch = 2 * (1 << a.qubits) * 16
@@ -343,6 +349,12 @@ def bench_brick26(a, tq):
                       "recomputes": r64["recomputes"], "max_norm_drift": r64["drift"],
                       "drift_bound": a.drift_bound,
                       "speedup_vs_c128": round(r128["wall"] / r64["wall"], 3)}
+    if rck:
+        out["checkpoint_traversal"] = {
+            "shots_per_s": round(rck["shots"] / rck["wall"], 4),
+            "speedup_vs_plain_dftt": round(r128["wall"] / rck["wall"], 3),
+            "sweeps_per_leaf": round(rck["passes"] / max(rck["leaves"], 1), 2),
+            "slots": "unbounded"}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, r128["tokens"], r128["shots"], a.cpu_seconds)
     return out
