@@ -48,6 +48,7 @@ void check_opts(const tusq_opts *o) {
     need(o->traversal <= TUSQ_CACHING, "unknown traversal");
     need(!(o->leaf_begin > o->leaf_end && o->leaf_end != 0), "leaf_begin > leaf_end");
     need(o->drift_bound >= 0.0, "drift_bound must be >= 0");
+    need(o->fusion_search <= 2, "unknown fusion_search");
 }
 }  // namespace
 

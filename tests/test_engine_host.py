@@ -354,6 +354,9 @@ def test_invalid_inputs_are_rejected():
     o = tq.tusq_opts_default(shots=0)
     t = ctypes.c_void_p()
     assert lib.tusq_ecm_build(h, ctypes.byref(o), ctypes.byref(t)) == -1
+    for bad_opt in (dict(traversal=5), dict(fusion_search=3), dict(precision=2)):
+        o = tq.tusq_opts_default(shots=10, **bad_opt)
+        assert lib.tusq_ecm_build(h, ctypes.byref(o), ctypes.byref(t)) == -1, bad_opt
     assert lib.tusq_circuit_destroy(h) == 0
     assert lib.tusq_circuit_destroy(None) == 0
     assert lib.tusq_result_destroy(None) == 0
