@@ -318,3 +318,35 @@ def test_persistent_sweep_several_tiles_per_workgroup(ctx, precision):
     assert np.mean(rp.samples() == rr.samples()) > (0.99 if precision == "c128" else 0.9)
     tol = 1e-12 if precision == "c128" else 1e-5
     assert abs(rp.distribution().sum() - 1.0) < tol
+
+
+@pytest.mark.parametrize("trav", ["dftt", "checkpoint"])
+def test_leaf_range_shards_sum_to_the_whole_job(ctx, trav):
+    """The sharding design on one GPU: the depth-first leaf list cut into 4
+    contiguous ranges, each run from the root as its own job; the FP64
+    distributions summed on the host equal the whole job's, and the samples
+    concatenate to the whole job's (a draw's counter depends only on its
+    leaf and its index within the leaf)."""
+    _say(f"[gpu] shards {trav}")
+    c = brickwork(14, 10, 2e-3, 2e-2, 17)
+    S, seed = 6000, 9
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=seed, traversal=trav, fusion_max_qubits=10)
+    t = tq.Tree(ec, o)
+    whole = tq.tusq_run_tree(ctx, ec, t, o)
+    L = t.info()["n_leaves"]
+    cuts = [0, L // 5, L // 2, (4 * L) // 5, L]
+    acc = np.zeros(1 << c.n)
+    samples = []
+    for lb, le in zip(cuts, cuts[1:]):
+        if le <= lb:
+            continue
+        os_ = tq.tusq_opts_default(shots=S, seed=seed, traversal=trav, fusion_max_qubits=10,
+                                   leaf_begin=lb, leaf_end=le)
+        r = tq.tusq_run_tree(ctx, ec, t, os_)
+        acc += r.distribution()
+        samples.append(r.samples())
+    np.testing.assert_allclose(acc, whole.distribution(), atol=1e-12, rtol=0)
+    cat = np.concatenate(samples)
+    assert len(cat) == S
+    assert np.count_nonzero(cat != whole.samples()) <= 2
