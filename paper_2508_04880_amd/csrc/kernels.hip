@@ -1125,14 +1125,15 @@ __global__ void __launch_bounds__(256) k_mcm_probs(const V *__restrict__ psi, ui
     }
 }
 
-// P[o] = partial[o * nblk + 0] + ... + partial[o * nblk + nblk - 1], in order
-__global__ void __launch_bounds__(256) k_mcm_sum(const double *__restrict__ partial, uint32_t nblk,
-                                                 uint32_t no, double *__restrict__ P) {
-    const uint32_t o = threadIdx.x;
-    if (o >= no) return;
+// P[o] = sum of partial[o * nblk + i] over i, one wavefront per outcome:
+// lane l adds i = l, l + 64, ... in order, then a fixed shuffle tree
+__global__ void __launch_bounds__(64) k_mcm_sum(const double *__restrict__ partial, uint32_t nblk,
+                                                double *__restrict__ P) {
+    const uint32_t o = blockIdx.x, lane = threadIdx.x;
     double s = 0.0;
-    for (uint32_t i = 0; i < nblk; ++i) s += partial[static_cast<uint64_t>(o) * nblk + i];
-    P[o] = s;
+    for (uint32_t i = lane; i < nblk; i += 64) s += partial[static_cast<uint64_t>(o) * nblk + i];
+    for (uint32_t off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) P[o] = s;
 }
 
 // dst[base | dep(p)] = (p == want) ? scale * src[base | dep(o)] : 0 for every
@@ -1168,7 +1169,7 @@ hipError_t launch_mcm_probs(const V *psi, uint32_t n, const MeasArgs &a, double 
     const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((R + 255) / 256, MCM_BLOCKS));
     hipLaunchKernelGGL(k_mcm_probs<V>, dim3(blocks), dim3(256), 0, s, psi, R, a, partial);
     TUSQ_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_mcm_sum, dim3(1), dim3(256), 0, s, partial, blocks, 1u << a.m, P);
+    hipLaunchKernelGGL(k_mcm_sum, dim3(1u << a.m), dim3(64), 0, s, partial, blocks, P);
     TUSQ_CHECK_LAUNCH();
     return hipSuccess;
 }
