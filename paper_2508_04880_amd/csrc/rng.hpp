@@ -11,8 +11,10 @@
 
 #if defined(__HIPCC__)
 #define TUSQ_HD __host__ __device__ inline
+#define TUSQ_UNROLL _Pragma("unroll")
 #else
 #define TUSQ_HD inline
+#define TUSQ_UNROLL
 #endif
 
 namespace tusq {
@@ -24,7 +26,7 @@ struct U4 {
 TUSQ_HD U4 philox10(U4 c, uint32_t k0, uint32_t k1) {
     constexpr uint32_t MA = 0xD2511F53u, MB = 0xCD9E8D57u;
     constexpr uint32_t WA = 0x9E3779B9u, WB = 0xBB67AE85u;
-#pragma unroll
+    TUSQ_UNROLL
     for (int round = 0; round < 10; ++round) {
         const uint64_t pa = static_cast<uint64_t>(MA) * c.x;
         const uint64_t pb = static_cast<uint64_t>(MB) * c.z;
