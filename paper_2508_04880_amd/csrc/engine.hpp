@@ -97,7 +97,6 @@ constexpr int KMAX = 16;  // most qubits a tile may span
 struct Op {
     uint8_t a;      // local index of the (first) qubit
     uint8_t b;      // local index of the second qubit, or 0xFF for a 1-qubit op
-    uint8_t diag;   // 1: the matrix is diagonal (one complex multiply per amplitude)
     uint32_t mat;   // offset (complex numbers) into the matrix pool
     uint32_t adj;   // offset of its adjoint
 };
@@ -124,8 +123,6 @@ struct Pass {
 //   IN_OP1:      2x2 matrix on register bit (arg & 7);
 //   IN_OP2:      4x4 matrix on register bits a = arg & 7 (high bit of the
 //                4x4 index) and b = (arg >> 3) & 7, with a > b;
-//   (IN_OP1 / IN_OP2 with arg bit 6 set: the matrix is diagonal, and only
-//   its diagonal is applied);
 //   IN_EXCH:     swap register bit r = arg & 7 with thread-index bit
 //                h = (arg >> 3) & 7 < 6 (a lane exchange inside the wavefront).
 // mat is an offset (complex numbers) into the matrix pool for ops; undo

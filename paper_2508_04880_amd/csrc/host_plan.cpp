@@ -317,14 +317,13 @@ void build_programs(Plan &plan, Pass &p) {
                 rem.done[i] = 1;
                 uint32_t mat = inverse ? op.adj : op.mat;
                 const uint32_t A = static_cast<uint32_t>(cur.reg_index(op.a));
-                const uint32_t dg = op.diag ? 64u : 0u;
                 if (op.b == 0xFF) {
-                    plan.prog.push_back(Instr{IN_OP1 | ((A | dg) << 2), mat});
+                    plan.prog.push_back(Instr{IN_OP1 | (A << 2), mat});
                 } else {
                     uint32_t B = static_cast<uint32_t>(cur.reg_index(op.b));
                     uint32_t hi = A, lo = B;
                     if (A < B) { hi = B; lo = A; mat = swapped(mat); }
-                    plan.prog.push_back(Instr{IN_OP2 | ((hi | (lo << 3) | dg) << 2), mat});
+                    plan.prog.push_back(Instr{IN_OP2 | ((hi | (lo << 3)) << 2), mat});
                 }
             }
             rem.advance();
@@ -395,16 +394,7 @@ struct BuildOp {
     bool live;
     M2 m2;
     M4 m4;
-    bool diag;        // the matrix is diagonal
 };
-
-bool diag2(const M2 &m) { return m[1] == cd(0.0) && m[2] == cd(0.0); }
-bool diag4(const M4 &m) {
-    for (int r = 0; r < 4; ++r)
-        for (int c = 0; c < 4; ++c)
-            if (r != c && m[4 * r + c] != cd(0.0)) return false;
-    return true;
-}
 constexpr uint32_t NONE = 0xFFFFFFFFu;
 
 struct Fuser {
@@ -437,42 +427,7 @@ struct Fuser {
         bool two;
         bool is_gate;
         M2 m2;            // 1-qubit matrix (gate or Pauli)
-        // a 2-qubit item is a CX unless `zz`: then m4 (index 2 bit(qa) +
-        // bit(qb)) is the diagonal product of CX, a diagonal 1-qubit gate and
-        // the same CX (three gates)
-        bool zz = false;
-        M4 m4{};
     };
-
-    // CX(a, b), a diagonal 1-qubit gate on a or b, CX(a, b) is diagonal (a
-    // ZZ-type rotation): such runs become one item, so that the fusion can
-    // keep it diagonal instead of folding neighbouring dense gates into it
-    static std::vector<Item> with_zz(const std::vector<Item> &items) {
-        std::vector<Item> out;
-        out.reserve(items.size());
-        const M4 g = cx_matrix();
-        for (size_t i = 0; i < items.size(); ++i) {
-            const Item &x = items[i];
-            if (x.two && !x.zz && x.is_gate && i + 2 < items.size()) {
-                const Item &y = items[i + 1], &z = items[i + 2];
-                if (!y.two && y.is_gate && (y.qa == x.qa || y.qa == x.qb) && diag2(y.m2) && z.two &&
-                    !z.zz && z.is_gate && z.qa == x.qa && z.qb == x.qb) {
-                    const M4 mid = y.qa == x.qa ? kron(y.m2, I2m) : kron(I2m, y.m2);
-                    const M4 m = mul4(g, mul4(mid, g));
-                    if (diag4(m)) {
-                        Item w = x;
-                        w.zz = true;
-                        w.m4 = m;
-                        out.push_back(w);
-                        i += 2;
-                        continue;
-                    }
-                }
-            }
-            out.push_back(x);
-        }
-        return out;
-    }
 
     // Tokens one sweep would take from `rest` if its tile started as the
     // qubits of `init` (nq of them): the sweep's admission rule (a token is
@@ -530,8 +485,7 @@ struct Fuser {
     }
 
     // Fuse one segment; appends passes to the plan, returns their range.
-    std::pair<uint32_t, uint32_t> fuse(const std::vector<Item> &items_in) {
-        const std::vector<Item> items = with_zz(items_in);
+    std::pair<uint32_t, uint32_t> fuse(const std::vector<Item> &items) {
         const uint32_t first = static_cast<uint32_t>(plan.passes.size());
         const uint32_t n = c.n;
         std::vector<uint32_t> rest(items.size());
@@ -592,47 +546,30 @@ struct Fuser {
                 }
                 addq(it.qa);
                 if (it.two) addq(it.qb);
-                if (it.is_gate) gates += it.zz ? 3 : 1; else ++paulis;
-                // a diagonal op stays diagonal: a dense 1-qubit matrix is not
-                // folded into it (one complex multiply per amplitude plus a
-                // 2x2 op is cheaper than a dense 4x4)
+                if (it.is_gate) ++gates; else ++paulis;
                 if (!it.two) {
                     const int l = last[it.qa];
-                    const bool d = diag2(it.m2);
-                    if (l >= 0 && (d || !ops[l].diag || ops[l].qb == NONE)) {
+                    if (l >= 0) {
                         BuildOp &o = ops[l];
                         if (o.qb == NONE) o.m2 = mul2(it.m2, o.m2);
                         else if (o.qa == it.qa) o.m4 = mul4(kron(it.m2, I2m), o.m4);
                         else o.m4 = mul4(kron(I2m, it.m2), o.m4);
-                        o.diag = o.diag && d;
                     } else {
-                        ops.push_back(BuildOp{it.qa, NONE, true, it.m2, {}, d});
+                        ops.push_back(BuildOp{it.qa, NONE, true, it.m2, {}});
                         last[it.qa] = static_cast<int>(ops.size()) - 1;
                         ++live;
                     }
                 } else {
                     const int la = last[it.qa], lb = last[it.qb];
-                    const M4 g = it.zz ? it.m4 : cx_matrix();
+                    const M4 g = cx_matrix();
                     if (la >= 0 && la == lb) {
                         BuildOp &o = ops[la];
                         o.m4 = mul4(o.qa == it.qa ? g : swap_halves(g), o.m4);
-                        o.diag = o.diag && it.zz;
                     } else {
-                        // fold the pending 1-qubit ops of both qubits in,
-                        // except dense ones into a diagonal item
                         M2 a = I2m, b = I2m;
-                        bool d = it.zz;
-                        auto take1 = [&](int l, M2 &m) {
-                            if (l < 0 || ops[l].qb != NONE) return;
-                            if (it.zz && !ops[l].diag) return;
-                            m = ops[l].m2;
-                            d = d && ops[l].diag;
-                            ops[l].live = false;
-                            --live;
-                        };
-                        take1(la, a);
-                        take1(lb, b);
-                        ops.push_back(BuildOp{it.qa, it.qb, true, {}, mul4(g, kron(a, b)), d});
+                        if (la >= 0 && ops[la].qb == NONE) { a = ops[la].m2; ops[la].live = false; --live; }
+                        if (lb >= 0 && ops[lb].qb == NONE) { b = ops[lb].m2; ops[lb].live = false; --live; }
+                        ops.push_back(BuildOp{it.qa, it.qb, true, {}, mul4(g, kron(a, b))});
                         last[it.qa] = last[it.qb] = static_cast<int>(ops.size()) - 1;
                         ++live;
                     }
@@ -655,7 +592,6 @@ struct Fuser {
                 Op op;
                 op.a = static_cast<uint8_t>(loc[o.qa]);
                 op.b = o.qb == NONE ? 0xFF : static_cast<uint8_t>(loc[o.qb]);
-                op.diag = o.diag ? 1 : 0;
                 // 2-qubit ops keep the higher local qubit as the high bit of
                 // the 4x4 index (the kernels' canonical order)
                 M4 m4 = o.m4;
@@ -721,8 +657,7 @@ void token_items(const Circuit &c, const Ev *ev, const std::vector<Tok> &toks, u
 
 uint64_t pass_flops_per_amp(const Plan &plan, const Pass &p) {
     uint64_t f = 0;
-    for (uint32_t i = p.op_begin; i < p.op_end; ++i)
-        f += plan.ops[i].diag ? 8 : plan.ops[i].b == 0xFF ? 16 : 32;
+    for (uint32_t i = p.op_begin; i < p.op_end; ++i) f += plan.ops[i].b == 0xFF ? 16 : 32;
     return f;
 }
 

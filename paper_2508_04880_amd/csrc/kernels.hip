@@ -523,25 +523,6 @@ __device__ __forceinline__ void pp_op2(const V (&x)[1 << R], V (&y)[1 << R],
     }
 }
 
-// Diagonal 2x2 (entries m[0], m[3]) on register bit B, and diagonal 4x4
-// (entries m[5 i], i = 2 bit(A) + bit(B)) on register bits A > B: one
-// complex multiply per amplitude
-template <typename V, int R, int B>
-__device__ __forceinline__ void pp_diag1(const V (&x)[1 << R], V (&y)[1 << R],
-                                         const V *__restrict__ m) {
-    const V d0 = m[0], d1 = m[3];
-#pragma unroll
-    for (int j = 0; j < (1 << R); ++j) y[j] = cmul((j >> B) & 1 ? d1 : d0, x[j]);
-}
-
-template <typename V, int R, int A, int B>
-__device__ __forceinline__ void pp_diag2(const V (&x)[1 << R], V (&y)[1 << R],
-                                         const V *__restrict__ m) {
-    const V d[4] = {m[0], m[5], m[10], m[15]};
-#pragma unroll
-    for (int j = 0; j < (1 << R); ++j) y[j] = cmul(d[2 * ((j >> A) & 1) + ((j >> B) & 1)], x[j]);
-}
-
 // Swap register bit B with lane bit H: for each pair a = x[j], b = x[j | 1 << B]
 // the lanes with bit H set take a's place in b and the others b's place in
 // a, i.e. element (lane L, bit B = c) moves to (lane L with bit H = c, bit
@@ -627,26 +608,11 @@ __device__ __forceinline__ void pp_step(const V (&x)[1 << R], V (&y)[1 << R], In
         thr = ins.mat;
     } else if (type == 1u) {
         const V *m = mats + ins.mat;
-        switch (arg & 71u) {  // register bit, and bit 6: diagonal
+        switch (arg & 7u) {
         case 0: pp_op1<V, R, 0>(x, y, m); break;
         case 1: pp_op1<V, R, 1>(x, y, m); break;
         case 2: pp_op1<V, R, 2>(x, y, m); break;
         case 3: if constexpr (R > 3) { pp_op1<V, R, 3>(x, y, m); break; } [[fallthrough]];
-        case 64: pp_diag1<V, R, 0>(x, y, m); break;
-        case 65: pp_diag1<V, R, 1>(x, y, m); break;
-        case 66: pp_diag1<V, R, 2>(x, y, m); break;
-        case 67: if constexpr (R > 3) { pp_diag1<V, R, 3>(x, y, m); break; } [[fallthrough]];
-        default: __builtin_unreachable();
-        }
-    } else if (type == 2u && (arg & 64u)) {
-        const V *m = mats + ins.mat;
-        switch (arg & 63u) {
-        case 1 | (0 << 3): pp_diag2<V, R, 1, 0>(x, y, m); break;
-        case 2 | (0 << 3): pp_diag2<V, R, 2, 0>(x, y, m); break;
-        case 2 | (1 << 3): pp_diag2<V, R, 2, 1>(x, y, m); break;
-        case 3 | (0 << 3): if constexpr (R > 3) { pp_diag2<V, R, 3, 0>(x, y, m); break; } [[fallthrough]];
-        case 3 | (1 << 3): if constexpr (R > 3) { pp_diag2<V, R, 3, 1>(x, y, m); break; } [[fallthrough]];
-        case 3 | (2 << 3): if constexpr (R > 3) { pp_diag2<V, R, 3, 2>(x, y, m); break; } [[fallthrough]];
         default: __builtin_unreachable();
         }
     } else if (type == 2u) {

@@ -462,39 +462,3 @@ def test_window_search_fuses_brickwork_into_fewer_sweeps():
         got[search] = tq.tusq_plan_counters(ec, t, o)
     assert got[2]["passes_fwd"] < 0.8 * got[1]["passes_fwd"]
     assert got[2]["fwd_gates"] == got[1]["fwd_gates"]
-
-
-def test_zz_rotations_stay_diagonal():
-    """CX, a diagonal 1-qubit gate, CX on the same pair fuse into one
-    diagonal op (a ZZ-type rotation) that dense gates are not folded into:
-    on the Trotterised Ising chain every such op's matrix is diagonal, the
-    dense-op work drops, and the fused sweeps still give the oracle's
-    distribution."""
-    c = ising(8, 4, 1e-2, 3e-2)
-    S = 3000
-    ot = oracle.ecm(c, S, 6, prune=False)
-    dist, _, _, _ = oracle.run(c, ot, 6, want_samples=False)
-    ec = tq.Circuit(c)
-    o = tq.tusq_opts_default(shots=S, seed=6, prune=0, fusion_max_qubits=6, fusion_low_qubits=2)
-    et = tq.Tree(ec, o)
-    dump = tq.tusq_plan_dump(ec, et, o)
-    progs = tq.tusq_plan_dump_programs(ec, et, o)
-    flagged = [(int(w) >> 2, int(m)) for w, m in progs["instr"] if int(w) & 3 in (1, 2) and (int(w) >> 2) & 64]
-    assert flagged
-    for w, m in progs["instr"]:
-        w, m = int(w), int(m)
-        if w & 3 in (1, 2) and (w >> 2) & 64:
-            d = 2 if w & 3 == 1 else 4
-            M = dump["mats"][m: m + d * d].reshape(d, d)
-            assert np.count_nonzero(M - np.diag(np.diag(M))) == 0
-    acc = _run_programs_numpy(c, dump, progs, ot.weights())
-    np.testing.assert_allclose(acc, dist, atol=1e-12)
-    # counted as one complex multiply per amplitude, the diagonal ops make
-    # the Ising chain's dense-op work smaller than with every op dense
-    pc = tq.tusq_plan_counters(ec, et, o)
-    all_dense = 0
-    for kind, ident in dump["steps"]:
-        if kind in (1, 2):
-            b, e = dump["op_range"][ident]
-            all_dense += sum(32 if int(op[1]) != 0xFF else 16 for op in dump["ops"][b:b + e])
-    assert pc["sweep_flops"] < 0.9 * (all_dense << c.n)
