@@ -248,25 +248,15 @@ def _run_programs_numpy(c, dump, progs, weights):
         for lay_thr in (thr, end_thr):
             assert lay_thr[:lowc] == list(range(lowc))
         assert (e - b) % 2 == 0      # instructions run in pairs
-        # the kernel reads slot s from register array s % 2; an instruction
-        # writes the other array, except an in-place lane exchange (lane bits
-        # 4 / 5 named as 6 / 7), which must be followed by a no-op slot
-        loc, prev_inplace = 0, False
-        for s_, (w0, mat) in enumerate(progs["instr"][b:e]):
+        # the kernel reads slot s from register array s % 2 and writes the
+        # other; every instruction is one of the four forms below
+        for w0, mat in progs["instr"][b:e]:
             typ, arg = int(w0) & 3, int(w0) >> 2
-            if typ == 1 and (arg & 7) == 7:
-                assert prev_inplace
-                prev_inplace = False
-                continue
-            assert not prev_inplace and loc == s_ % 2
-            inplace = typ == 3 and ((arg >> 3) & 7) >= 6
-            if not inplace:
-                loc ^= 1
-            prev_inplace = inplace
+            swaps = []
             if typ == 0:
                 reg, thr = _layout(k, r, arg, int(mat))
             elif typ == 1:
-                assert (arg & 7) < r
+                assert (arg & 7) < r and ((arg >> 3) & 7) == 0
                 M = dump["mats"][mat: mat + 4]
                 psi = _apply_local(psi, n, q, (reg[arg & 7], 0xFF), M, False)
             elif typ == 2:
@@ -274,15 +264,16 @@ def _run_programs_numpy(c, dump, progs, weights):
                 M = dump["mats"][mat: mat + 16]
                 psi = _apply_local(psi, n, q, (reg[arg & 7], reg[(arg >> 3) & 7]), M, False)
             else:
+                assert arg >> 6 == 0
+                swaps = [arg & 63]
+            if typ in (1, 2):
+                assert arg >> 6 == 0
+            for xa in swaps:
                 # lane exchange: thread bits 0 .. 5 are the lane bits of full wavefronts
                 assert k - r >= 6
-                ri, h = arg & 7, (arg >> 3) & 7
-                if h >= 6:
-                    h -= 2
-                    assert h in (4, 5)
+                ri, h = xa & 7, xa >> 3
                 assert ri < r and h < 6
                 reg[ri], thr[h] = thr[h], reg[ri]
-        assert not prev_inplace and loc == 0
         assert (reg, thr) == (end_reg, end_thr)
     return acc
 
