@@ -218,6 +218,16 @@ int tusq_thermal_pauli_probs(double t, double t1, double t2, double *probs);
  * tusq_circuit_pauli_noise otherwise.                                      */
 int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, double t1,
                                double t2);
+/* Read-out (measurement) error (Sec. IV-D lists it among the noise models;
+ * Sec. VI-A: a Pauli channel as it stands): the final read-out of `qubit`
+ * reports the flipped bit with probability p.  That is an X error just
+ * before the read-out, so the call appends RZ(0) -- the identity -- on the
+ * qubit with the channel (pX, pY, pZ) = (p, 0, 0).  Call it after the
+ * qubit's last gate: a gate appended later acts after the flip.  EINVAL
+ * unless 0 <= p <= 1; nothing is appended then.  gate_index_out (may be
+ * NULL) receives the appended gate's index.                                */
+int tusq_circuit_readout_noise(tusq_circuit *c, uint32_t qubit, double p,
+                               uint32_t *gate_index_out);
 /* Append a layer of concurrent Z-basis measurements of `count` distinct
  * qubits (1 .. TUSQ_MAX_MEASURED), one non-invertible edge of the circuit
  * tree (Sec. III-B.2); reset != 0 returns the measured qubits to |0>

@@ -84,6 +84,7 @@ _SIGS = {
     "tusq_thermal_pauli_probs": (C.c_int, [C.c_double, C.c_double, C.c_double, P]),
     "tusq_circuit_thermal_noise": (C.c_int, [P, C.c_uint32, C.c_double, C.c_double, C.c_double]),
     "tusq_circuit_measure": (C.c_int, [P, P, C.c_uint32, C.c_int, P]),
+    "tusq_circuit_readout_noise": (C.c_int, [P, C.c_uint32, C.c_double, P]),
     "tusq_circuit_destroy": (C.c_int, [P]),
     "tusq_ecm_build": (C.c_int, [P, P, P]),
     "tusq_tree_get_info": (C.c_int, [P, P]),
@@ -186,6 +187,14 @@ class Circuit:
         no channel yet (tusq_circuit_thermal_noise)."""
         check(lib.tusq_circuit_thermal_noise(self.h, C.c_uint32(gate_index), C.c_double(t),
                                              C.c_double(t1), C.c_double(t2)))
+
+    def readout_noise(self, qubit: int, p: float) -> int:
+        """Read-out flip of probability p on qubit: appends RZ(0) with an X
+        channel (tusq_circuit_readout_noise); returns the gate's index."""
+        g = C.c_uint32()
+        check(lib.tusq_circuit_readout_noise(self.h, C.c_uint32(qubit), C.c_double(p),
+                                             C.byref(g)))
+        return g.value
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -172,6 +172,24 @@ int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, d
     return tusq_circuit_pauli_noise(c, gate_index, p, m);
 }
 
+int tusq_circuit_readout_noise(tusq_circuit *c, uint32_t qubit, double p,
+                               uint32_t *gate_index_out) {
+    const int rc = guarded([&] {
+        need(c != nullptr, "circuit is NULL");
+        need(qubit < c->c.n, "qubit out of range");
+        need(std::isfinite(p) && p >= 0.0 && p <= 1.0, "read-out flip probability outside [0, 1]");
+    });
+    if (rc != TUSQ_OK) return rc;
+    uint32_t g = 0;
+    const double angle[3] = {0.0, 0.0, 0.0};
+    int r = tusq_circuit_gate(c, TUSQ_RZ, &qubit, angle, &g);
+    if (r != TUSQ_OK) return r;
+    const double probs[3] = {p, 0.0, 0.0};
+    r = tusq_circuit_pauli_noise(c, g, probs, 3);
+    if (r == TUSQ_OK && gate_index_out) *gate_index_out = g;
+    return r;
+}
+
 int tusq_circuit_measure(tusq_circuit *c, const uint32_t *qubits, uint32_t count, int reset,
                          uint32_t *gate_index_out) {
     return guarded([&] {

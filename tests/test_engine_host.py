@@ -393,6 +393,31 @@ def test_thermal_noise_attached_by_the_library_gives_the_oracle_tree():
         ec.thermal_noise(0, 0.1, 1.0, 1.0)       # the gate already has a channel
 
 
+def test_readout_noise_through_the_library_gives_the_oracle_tree():
+    """Read-out flips (Sec. IV-D) appended through tusq_circuit_readout_noise
+    give the same tree, byte for byte, as the oracle's circuit with the same
+    flips written as RZ(0) gates carrying an X channel; bad arguments are
+    refused and append nothing."""
+    base = brickwork(6, 6, 1e-3, 1e-2, 21)
+    flips = [0.01, 0.02, 0.0, 0.05, 0.3, 1.0]
+    c = Circuit(6, kinds=list(base.kinds), qubits=list(base.qubits),
+                params=list(base.params), noise=list(base.noise))
+    ec = tq.Circuit(Circuit(6, kinds=list(base.kinds), qubits=list(base.qubits),
+                            params=list(base.params), noise=list(base.noise)))
+    for q, p in enumerate(flips):
+        assert ec.readout_noise(q, p) == c.add_readout_noise(q, p)
+    S, seed = 4000, 3
+    ot = oracle.ecm(c, S, seed)
+    o = tq.tusq_opts_default(shots=S, seed=seed)
+    assert tq.Tree(ec, o).serialize() == ot.serialize()
+    for q, p in ((0, -0.1), (0, 1.5), (0, float("nan")), (6, 0.1)):
+        with pytest.raises(tq.TusqError) as e:
+            ec.readout_noise(q, p)
+        assert e.value.code == -1
+    # nothing was appended by the refused calls
+    assert ec.readout_noise(0, 0.1) == base.n_gates + len(flips)
+
+
 # --------------------------------------------------------------------------
 # Measurement layers (Sec. III-B.2): host side
 

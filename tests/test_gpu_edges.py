@@ -151,6 +151,32 @@ def test_thermal_relaxation_noise_matches_oracle(ctx, precision):
     np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_readout_noise_matches_oracle(ctx, precision):
+    """Brickwork with the paper's depolarising noise plus a read-out flip on
+    every qubit (tusq_circuit_readout_noise), against the oracle run on the
+    same circuit built through the workload helper."""
+    _say(f"[gpu] read-out noise {precision}")
+    base = brickwork(9, 10, 1e-3, 1e-2, 23)
+    c = Circuit(9, kinds=list(base.kinds), qubits=list(base.qubits),
+                params=list(base.params), noise=list(base.noise))
+    ec = tq.Circuit(Circuit(9, kinds=list(base.kinds), qubits=list(base.qubits),
+                            params=list(base.params), noise=list(base.noise)))
+    for q in range(9):
+        p = 0.01 * (q + 1)
+        c.add_readout_noise(q, p)
+        ec.readout_noise(q, p)
+    S, seed = 20_000, 6
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    o = tq.tusq_opts_default(shots=S, seed=seed, precision=precision, drift_bound=1.0)
+    t = tq.Tree(ec, o)
+    assert t.serialize() == ot.serialize()
+    r = tq.tusq_run_tree(ctx, ec, t, o)
+    tol = 1e-10 if precision == "c128" else 1e-4
+    np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
+
+
 @pytest.mark.parametrize("slots", [0, 2])
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 @pytest.mark.parametrize("n,kmax", [(10, 6), (18, 12)])

@@ -573,6 +573,33 @@ def test_thermal_twirl_decay_rates(t, t1, t2):
     assert abs(np.trace(_PAULI["Z"] @ apply(one)).real + math.exp(-t / t1)) < 1e-14
 
 
+@pytest.mark.parametrize("p", [(0.1, 0.25, 0.05), (1.0, 0.0, 1.0), (0.0, 0.4, 0.0)])
+def test_readout_flips_closed_form(p):
+    """Read-out flips (Sec. IV-D) on the product state X|0>, H|0>, |0>: each
+    qubit reads its bit flipped with its own probability, so the output is a
+    product of Bernoulli marginals -- qubit 0 reads 1 with probability 1 - p0,
+    qubit 1 with 1/2 whatever p1, qubit 2 with p2.  Exact over every error
+    pattern and by the density matrix; through the sampled lossless pipeline
+    within the binomial spread."""
+    c = Circuit(3)
+    c.add("X", (0,), ())
+    c.add("H", (1,), ())
+    for q in range(3):
+        c.add_readout_noise(q, p[q])
+    one = [1 - p[0], 0.5, p[2]]
+    want = np.array([np.prod([one[q] if b >> q & 1 else 1 - one[q] for q in range(3)])
+                     for b in range(8)])
+    mix = np.zeros(8)
+    for pr, ev in dms.enumerate_ers(c):
+        mix += pr * np.abs(oracle.trajectory(c, ev)) ** 2
+    np.testing.assert_allclose(mix, want, atol=1e-15)
+    np.testing.assert_allclose(np.real(np.diag(dms.density_matrix(c))), want, atol=1e-14)
+    S = 200_000
+    t = oracle.ecm(c, S, seed=4, prune=False)
+    dist, _, _, _ = oracle.run(c, t, seed=4, want_samples=False)
+    assert np.max(np.abs(dist - want)) < 5 * np.sqrt(0.25 / S) + 1e-15
+
+
 def test_thermal_twirl_on_cx_is_the_product_channel():
     p1 = oracle.thermal_probs(0.2, 1.3, 0.9)
     p2 = oracle.thermal_probs(0.2, 1.3, 0.9, two_qubit=True)

@@ -58,6 +58,14 @@ class Circuit:
         self.noise.append(noise)
         return len(self.kinds) - 1
 
+    def add_readout_noise(self, qubit: int, p: float) -> int:
+        """Read-out flip of probability p on `qubit`: an X error just before
+        the final read-out, written as RZ(0) (the identity) carrying the
+        channel (p, 0, 0).  Append it after the qubit's last gate."""
+        if not 0.0 <= p <= 1.0:
+            raise ValueError("read-out flip probability outside [0, 1]")
+        return self.add("RZ", (qubit,), (0.0,), (float(p), 0.0, 0.0))
+
     def add_measure(self, qubits: Sequence[int], reset: bool = True) -> int:
         """A layer of concurrent Z-basis measurements of `qubits` (at most
         8, distinct), one non-invertible edge of the circuit tree; with
