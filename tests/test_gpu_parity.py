@@ -131,6 +131,40 @@ def test_c64_error_is_stated_and_bounded(ctx):
     assert err2 < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_brickwork_26_qubit_slice_matches_oracle(ctx, precision):
+    """Full size, in the sweep shape the benchmark times (12-qubit tiles, 4
+    low qubits, at most 32 ops per sweep, persistent kernel, window-searched
+    tiles): the 26-qubit brickwork with the paper's depolarising noise
+    (16 layers), depth-first leaves [1, 3) -- a leaf forward, the undo back
+    to the branch node and the next leaf -- against the oracle on all 2^26
+    probabilities, and the gate and Pauli counts of the walk."""
+    import os
+    _say(f"[gpu] brickwork n=26 leaves [1,3) {precision}")
+    c = brickwork(26, 16, 1e-3, 1e-2, 1)
+    S, seed = 10_000, 2
+    oracle.set_threads(min(os.cpu_count() or 1, 16))
+    try:
+        ot = oracle.ecm(c, S, seed)
+        want, _, oc, _ = oracle.run(c, ot, seed, leaf_begin=1, leaf_end=3, want_samples=False)
+    finally:
+        oracle.set_threads(1)
+    ec, t, o, r = _engine(ctx, c, S, seed, precision=precision, fusion_max_qubits=12,
+                          fusion_low_qubits=4, fusion_max_ops=32, sweep_kernel=4,
+                          leaf_begin=1, leaf_end=3, drift_bound=1.0)
+    assert t.serialize() == ot.serialize()
+    got = r.distribution()
+    # complex128: rounding-order differences only; complex64: each sweep
+    # rounds every amplitude at ~6e-8 relative
+    rel = 1e-10 if precision == "c128" else 1e-4
+    scale = float(want.max())
+    assert np.max(np.abs(got - want)) <= rel * scale, (np.max(np.abs(got - want)), scale)
+    assert abs(got.sum() - want.sum()) <= rel * want.sum()
+    ct = r.counters()
+    for k in ("leaves", "resets", "fwd_gates", "fwd_paulis", "inv_gates", "inv_paulis"):
+        assert ct[k] == oc[k], (k, ct[k], oc[k])
+
+
 def test_product_state_at_26_qubits(ctx):
     """Full-size addressing check with an exactly known answer: 1-qubit gates
     only, so the output is a product of 26 one-qubit distributions."""
