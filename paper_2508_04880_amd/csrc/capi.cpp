@@ -186,7 +186,12 @@ int tusq_circuit_readout_noise(tusq_circuit *c, uint32_t qubit, double p,
     if (r != TUSQ_OK) return r;
     const double probs[3] = {p, 0.0, 0.0};
     r = tusq_circuit_pauli_noise(c, g, probs, 3);
-    if (r == TUSQ_OK && gate_index_out) *gate_index_out = g;
+    if (r != TUSQ_OK) {  // take the gate back: the call appends both or nothing
+        c->c.gates.pop_back();
+        c->c.dirty = true;
+        return r;
+    }
+    if (gate_index_out) *gate_index_out = g;
     return r;
 }
 
