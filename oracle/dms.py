@@ -75,9 +75,32 @@ def cx_full(n: int, c: int, t: int) -> np.ndarray:
     return a + b
 
 
+def _matrix_of(params: Sequence[float], d: int) -> np.ndarray:
+    v = np.asarray(params, dtype=np.float64)
+    return (v[0::2] + 1j * v[1::2]).reshape(d, d)
+
+
+def embed_2q(n: int, qa: int, qb: int, m: np.ndarray) -> np.ndarray:
+    """A 4x4 acting on qubits (qa, qb), index 2 * bit(qa) + bit(qb), as a
+    2^n x 2^n matrix, entry by entry."""
+    N = 1 << n
+    U = np.zeros((N, N), dtype=np.complex128)
+    for i in range(N):
+        col = 2 * ((i >> qa) & 1) + ((i >> qb) & 1)
+        base = i & ~((1 << qa) | (1 << qb))
+        for row in range(4):
+            j = base | ((row >> 1) << qa) | ((row & 1) << qb)
+            U[j, i] = m[row, col]
+    return U
+
+
 def gate_full(n: int, kind: str, qubits: Sequence[int], params: Sequence[float]) -> np.ndarray:
     if kind == "CX":
         return cx_full(n, qubits[0], qubits[1])
+    if kind == "UNITARY2":
+        return embed_2q(n, qubits[0], qubits[1], _matrix_of(params, 4))
+    if kind == "UNITARY1":
+        return embed_1q(n, qubits[0], _matrix_of(params, 2))
     return embed_1q(n, qubits[0], gate_2x2(kind, params))
 
 

@@ -16,7 +16,8 @@ _SRC = os.path.join(_HERE, "tusq_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 KIND_CODES = {name: i for i, name in enumerate(
-    ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX", "M", "MR"))}
+    ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX", "M", "MR",
+     "UNITARY1", "UNITARY2"))}
 
 
 def build_library(force: bool = False) -> str:
@@ -33,7 +34,8 @@ def build_library(force: bool = False) -> str:
 class _Circuit(C.Structure):
     _fields_ = [("n", C.c_uint32), ("G", C.c_uint32),
                 ("kind", C.c_void_p), ("q0", C.c_void_p), ("q1", C.c_void_p),
-                ("params", C.c_void_p), ("nprob", C.c_void_p), ("probs", C.c_void_p)]
+                ("params", C.c_void_p), ("nprob", C.c_void_p), ("probs", C.c_void_p),
+                ("mats", C.c_void_p), ("mat_off", C.c_void_p)]
 
 
 _lib = None
@@ -92,12 +94,16 @@ class _CircuitHandle:
         self.params = np.ascontiguousarray(params, dtype=np.float64)
         self.nprob = np.ascontiguousarray(nprob)
         self.probs = np.ascontiguousarray(probs if probs.size else np.zeros(1))
+        mats, mat_off = circ.unitary_arrays()
+        self.mats = np.ascontiguousarray(mats if mats.size else np.zeros(1))
+        self.mat_off = np.ascontiguousarray(mat_off if mat_off.size else np.zeros(1, np.uint64))
         self.n = circ.n
         self.G = len(kinds)
         self.s = _Circuit(circ.n, self.G, _ptr(self.kind) if self.G else None,
                           _ptr(self.q0) if self.G else None, _ptr(self.q1) if self.G else None,
                           _ptr(self.params) if self.G else None,
-                          _ptr(self.nprob) if self.G else None, _ptr(self.probs))
+                          _ptr(self.nprob) if self.G else None, _ptr(self.probs),
+                          _ptr(self.mats), _ptr(self.mat_off))
 
     @property
     def ref(self):

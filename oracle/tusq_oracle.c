@@ -46,7 +46,10 @@
 /* ------------------------------------------------------------------------ */
 /* Gate kinds (the oracle's own numbering; the Python wrapper maps names).   */
 enum { OK_U3 = 0, OK_RX, OK_RY, OK_RZ, OK_H, OK_S, OK_SDG, OK_T, OK_TDG,
-       OK_X, OK_Y, OK_Z, OK_CX, OK_M, OK_MR, OK_NKINDS };
+       OK_X, OK_Y, OK_Z, OK_CX, OK_M, OK_MR, OK_U1M, OK_U2M, OK_NKINDS };
+/* OK_U1M / OK_U2M: a caller's 2x2 / 4x4 unitary, read from mats at
+ * mat_off[g] as row-major (re, im) pairs; the 4x4's basis index is
+ * 2 * bit(q0) + bit(q1).  No Pauli moves through either. */
 /* OK_M / OK_MR: a layer of concurrent Z-basis measurements (MR: the measured
  * qubits are reset to |0> afterwards).  Its qubit set is a 64-bit mask held
  * as q0 (low word) and q1 (high word); at most 8 qubits, no noise channel. */
@@ -61,6 +64,8 @@ typedef struct {
     const double *params;   /* 3 per gate */
     const uint8_t *nprob;   /* 0, 3 or 15 per gate */
     const double *probs;    /* concatenated channel probabilities */
+    const double *mats;     /* matrices of OK_U1M / OK_U2M gates */
+    const uint64_t *mat_off;/* per gate: offset into mats (doubles) */
 } oc_circuit;
 
 static int oracle_threads = 1;
@@ -164,7 +169,7 @@ typedef struct {
     uint64_t *chan_thr;    /* 15 per channel */
 } prep_t;
 
-static int is_two_qubit(uint8_t k) { return k == OK_CX; }
+static int is_two_qubit(uint8_t k) { return k == OK_CX || k == OK_U2M; }
 static int is_measure(uint8_t k) { return k == OK_M || k == OK_MR; }
 static uint64_t meas_mask(const oc_circuit *c, uint32_t g)
 {
@@ -190,6 +195,7 @@ static int validate(const oc_circuit *c)
         }
         if (c->q0[g] >= c->n) return -1;
         if (is_two_qubit(c->kind[g]) && (c->q1[g] >= c->n || c->q1[g] == c->q0[g])) return -1;
+        if ((c->kind[g] == OK_U1M || c->kind[g] == OK_U2M) && !(c->mats && c->mat_off)) return -1;
         int m = c->nprob[g];
         if (m != 0 && m != (is_two_qubit(c->kind[g]) ? 15 : 3)) return -1;
         double s = 0.0;
@@ -397,7 +403,11 @@ static int commute_one(const prep_t *P, stacks_t *S, int nraw, const uint32_t *c
                 if ((meas_mask(c, g) >> q) & 1) push(&S->st[q], (int32_t)g);
             continue;
         }
-        if (is_two_qubit(k)) {
+        if (k == OK_U2M) {
+            /* a general 2-qubit unitary stops the Paulis on both qubits */
+            push(&S->st[c->q0[g]], (int32_t)g);
+            push(&S->st[c->q1[g]], (int32_t)g);
+        } else if (is_two_qubit(k)) {
             stack_t_ *sc = &S->st[c->q0[g]], *stt = &S->st[c->q1[g]];
             int pc = 0, pt = 0;
             if (sc->size && top(sc) < 0) { pc = -top(sc); sc->size--; }
@@ -924,11 +934,47 @@ static void apply_pauli(cplx *psi, uint32_t n, uint32_t q, int p)
     }
 }
 
+/* A 4x4 on qubits (qa, qb): amplitude index 2 * bit(qa) + bit(qb). */
+static void apply_2q(cplx *psi, uint32_t n, uint32_t qa, uint32_t qb, const cplx m[16])
+{
+    uint64_t N = 1ull << n, ba = 1ull << qa, bb = 1ull << qb;
+#pragma omp parallel for num_threads(oracle_threads) schedule(static) if (N >= (1ull << 16))
+    for (uint64_t i = 0; i < N; ++i) {
+        if (i & (ba | bb)) continue;
+        uint64_t idx[4] = {i, i | bb, i | ba, i | ba | bb};
+        cplx a[4], r[4];
+        for (int k = 0; k < 4; ++k) a[k] = psi[idx[k]];
+        for (int r_ = 0; r_ < 4; ++r_) {
+            r[r_] = 0;
+            for (int k = 0; k < 4; ++k) r[r_] += m[4 * r_ + k] * a[k];
+        }
+        for (int k = 0; k < 4; ++k) psi[idx[k]] = r[k];
+    }
+}
+
 static void apply_gate(const oc_circuit *c, uint32_t g, cplx *psi, int inverse)
 {
     if (c->kind[g] == OK_CX) { apply_cx(psi, c->n, c->q0[g], c->q1[g]); return; }
+    if (c->kind[g] == OK_U2M) {
+        const double *d = c->mats + c->mat_off[g];
+        cplx m[16];
+        for (int r = 0; r < 4; ++r)
+            for (int k = 0; k < 4; ++k) {
+                /* the inverse is the conjugate transpose */
+                int s = inverse ? 4 * k + r : 4 * r + k;
+                cplx v = d[2 * s] + I * d[2 * s + 1];
+                m[4 * r + k] = inverse ? conj(v) : v;
+            }
+        apply_2q(psi, c->n, c->q0[g], c->q1[g], m);
+        return;
+    }
     cplx m[4];
-    gate_matrix(c->kind[g], c->params + 3 * (size_t)g, m);
+    if (c->kind[g] == OK_U1M) {
+        const double *d = c->mats + c->mat_off[g];
+        for (int k = 0; k < 4; ++k) m[k] = d[2 * k] + I * d[2 * k + 1];
+    } else {
+        gate_matrix(c->kind[g], c->params + 3 * (size_t)g, m);
+    }
     if (inverse) {
         cplx d[4] = {conj(m[0]), conj(m[2]), conj(m[1]), conj(m[3])};
         apply_1q(psi, c->n, c->q0[g], d);

@@ -600,6 +600,120 @@ def test_readout_flips_closed_form(p):
     assert np.max(np.abs(dist - want)) < 5 * np.sqrt(0.25 / S) + 1e-15
 
 
+# --------------------------------------------------------------------------
+# A caller's unitaries (UNITARY1 / UNITARY2)
+
+def _haar(d, rng):
+    z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _prep(n, rng):
+    c = Circuit(n)
+    for q in range(n):
+        c.add("U3", (q,), rng.random(3) * 6.28)
+    return c
+
+
+def test_unitary1_with_a_named_gates_matrix_is_that_gate():
+    rng = np.random.default_rng(3)
+    for kind, npar in (("U3", 3), ("RX", 1), ("H", 0), ("T", 0)):
+        pr = tuple(rng.random(npar) * 6.28)
+        a, b = _prep(3, rng), None
+        b = Circuit(3, kinds=list(a.kinds), qubits=list(a.qubits), params=list(a.params),
+                    noise=list(a.noise))
+        a.add(kind, (1,), pr)
+        b.add_unitary((1,), dms.gate_2x2(kind, pr))
+        np.testing.assert_allclose(oracle.trajectory(b), oracle.trajectory(a), atol=1e-14)
+
+
+def test_unitary2_orientation_and_products():
+    """The 4x4's basis index is 2 * bit(first qubit) + bit(second): the CX
+    matrix on (c, t) is CX(c, t) in both qubit orders, and kron(A, B) on
+    (qa, qb) is A on qa then B on qb."""
+    rng = np.random.default_rng(4)
+    cxm = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], complex)
+    for ctl, tgt in ((0, 2), (2, 0), (1, 2)):
+        a = _prep(3, rng)
+        b = Circuit(3, kinds=list(a.kinds), qubits=list(a.qubits), params=list(a.params),
+                    noise=list(a.noise))
+        a.add("CX", (ctl, tgt))
+        b.add_unitary((ctl, tgt), cxm)
+        np.testing.assert_allclose(oracle.trajectory(b), oracle.trajectory(a), atol=1e-14)
+    A, B = _haar(2, rng), _haar(2, rng)
+    a = _prep(3, rng)
+    b = Circuit(3, kinds=list(a.kinds), qubits=list(a.qubits), params=list(a.params),
+                noise=list(a.noise))
+    a.add_unitary((2, 0), np.kron(A, B))
+    b.add_unitary((2,), A)
+    b.add_unitary((0,), B)
+    np.testing.assert_allclose(oracle.trajectory(a), oracle.trajectory(b), atol=1e-14)
+    # and against the plain matrix product on the whole space
+    np.testing.assert_allclose(oracle.trajectory(a), dms.circuit_unitary(a)[:, 0], atol=1e-13)
+
+
+def test_user_unitaries_undo_to_the_start():
+    """The undo of a UNITARY1 / UNITARY2 (its conjugate transpose) returns
+    the state: forward to every depth and back gives |0...0>."""
+    rng = np.random.default_rng(5)
+    c = Circuit(3)
+    for _ in range(3):
+        c.add_unitary((int(rng.integers(3)),), _haar(2, rng), depol1(0.3))
+        a, b = rng.choice(3, 2, replace=False)
+        c.add_unitary((int(a), int(b)), _haar(4, rng), depol2(0.3))
+    ev = [(2, 0, 1), (4, 1, 3), (5, 2, 2)]
+    for depth in range(1, c.n_gates + len(ev) + 1):
+        assert oracle.roundtrip(c, ev, depth) < 1e-13
+
+
+def test_no_pauli_moves_through_a_user_unitary():
+    """RX lets an X error through and CX maps X_c to X_c X_t; the same
+    matrices given as UNITARY1 / UNITARY2 stop the error at their slot."""
+    rx = dms.gate_2x2("RX", (0.7,))
+    cxm = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], complex)
+    for named in (True, False):
+        c = Circuit(2)
+        c.add("X", (0,), (), (1.0, 0.0, 0.0))        # always an X error on qubit 0
+        if named:
+            c.add("RX", (0,), (0.7,))
+            c.add("CX", (0, 1))
+        else:
+            c.add_unitary((0,), rx)
+            c.add_unitary((0, 1), cxm)
+        chan, outc = oracle.sample_shot(c, 1, 0)
+        ev = oracle.commute(c, chan, outc)
+        assert ev == ([(3, 0, 1), (3, 1, 1)] if named else [(1, 0, 1)])
+        assert dms.equal_up_to_phase(dms.circuit_unitary(c, ev),
+                                     dms.circuit_unitary(c, oracle.commute(
+                                         c, chan, outc, do_commute=False)))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_noisy_user_unitaries_equal_density_matrix(seed):
+    rng = np.random.default_rng(40 + seed)
+    c = Circuit(3)
+    c.add_unitary((0,), _haar(2, rng), depol1(0.2))
+    c.add_unitary((1, 2), _haar(4, rng), depol2(0.2))
+    c.add("H", (2,), (), depol1(0.1))
+    c.add_unitary((2, 0), _haar(4, rng), (0.01,) * 15)
+    mix = np.zeros(8)
+    for p, ev in dms.enumerate_ers(c):
+        mix += p * np.abs(oracle.trajectory(c, ev)) ** 2
+    np.testing.assert_allclose(mix, np.real(np.diag(dms.density_matrix(c))), atol=1e-12)
+
+
+def test_add_unitary_refuses_bad_input():
+    c = Circuit(3)
+    for qs, m in (((0,), np.eye(4)), ((0, 1), np.eye(2)), ((0, 0), np.eye(4)),
+                  ((0,), [[1, 1], [0, 1]]), ((3,), np.eye(2)), ((0,), [[np.nan, 0], [0, 1]])):
+        with pytest.raises(ValueError):
+            c.add_unitary(qs, m)
+    with pytest.raises(ValueError):
+        c.add_unitary((0,), np.eye(2), depol2(0.1))
+    assert c.n_gates == 0
+
+
 def test_thermal_twirl_on_cx_is_the_product_channel():
     p1 = oracle.thermal_probs(0.2, 1.3, 0.9)
     p2 = oracle.thermal_probs(0.2, 1.3, 0.9, two_qubit=True)

@@ -25,6 +25,10 @@ import numpy as np
 GATE_NAMES = ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX")
 TWO_QUBIT = frozenset({"CX"})
 N_PARAMS = {"U3": 3, "RX": 1, "RY": 1, "RZ": 1}
+# a caller's unitary (add_unitary): the gate's params are the matrix,
+# row-major, as (re, im) pairs; UNITARY2's basis index is
+# 2 * bit(first qubit) + bit(second qubit)
+UNITARY_KINDS = ("UNITARY1", "UNITARY2")
 # mid-circuit Z-basis measurement layers: "M" keeps the measured qubits in
 # their outcome, "MR" resets them to |0> afterwards
 MEASURE_KINDS = ("M", "MR")
@@ -55,6 +59,31 @@ class Circuit:
             noise = tuple(float(x) for x in noise)
             if len(noise) != (3 if arity == 1 else 15):
                 raise ValueError("noise must have 3 (1q) or 15 (2q) probabilities")
+        self.noise.append(noise)
+        return len(self.kinds) - 1
+
+    def add_unitary(self, qubits: Sequence[int], matrix,
+                    noise: Optional[Sequence[float]] = None) -> int:
+        """A caller's 2x2 (one qubit) or 4x4 (two qubits, basis index
+        2 * bit(qubits[0]) + bit(qubits[1])) unitary, optionally followed by
+        a Pauli channel of 3 or 15 probabilities."""
+        qs = tuple(int(q) for q in qubits)
+        d = 2 if len(qs) == 1 else 4
+        m = np.asarray(matrix, dtype=np.complex128)
+        if len(qs) not in (1, 2) or m.shape != (d, d):
+            raise ValueError("add_unitary takes 1 qubit and a 2x2, or 2 qubits and a 4x4")
+        if len(set(qs)) != len(qs) or min(qs) < 0 or max(qs) >= self.n:
+            raise ValueError("qubits out of range or repeated")
+        if not np.all(np.isfinite(m)) or \
+                np.max(np.abs(m.conj().T @ m - np.eye(d))) > 1e-10:
+            raise ValueError("matrix is not unitary")
+        if noise is not None:
+            noise = tuple(float(x) for x in noise)
+            if len(noise) != (3 if d == 2 else 15):
+                raise ValueError("noise must have 3 (1q) or 15 (2q) probabilities")
+        self.kinds.append("UNITARY1" if d == 2 else "UNITARY2")
+        self.qubits.append(qs)
+        self.params.append(tuple(float(v) for z in m.ravel() for v in (z.real, z.imag)))
         self.noise.append(noise)
         return len(self.kinds) - 1
 
@@ -113,10 +142,23 @@ class Circuit:
                 continue
             q0[g] = qs[0]
             q1[g] = qs[1] if len(qs) > 1 else 0
-        params = np.array(self.params, dtype=np.float64).reshape(G, 3)
+        params = np.array([(0.0, 0.0, 0.0) if k in UNITARY_KINDS else p
+                           for k, p in zip(self.kinds, self.params)],
+                          dtype=np.float64).reshape(G, 3)
         nprob = np.array([0 if x is None else len(x) for x in self.noise], dtype=np.uint8)
         probs = np.array([v for x in self.noise if x is not None for v in x], dtype=np.float64)
         return list(self.kinds), q0, q1, params, nprob, probs
+
+    def unitary_arrays(self):
+        """The matrices of UNITARY1 / UNITARY2 gates concatenated as (re, im)
+        doubles, and per gate its offset there (0 for other gates)."""
+        off = np.zeros(self.n_gates, dtype=np.uint64)
+        vals = []
+        for g, (k, p) in enumerate(zip(self.kinds, self.params)):
+            if k in UNITARY_KINDS:
+                off[g] = len(vals)
+                vals.extend(p)
+        return np.array(vals, dtype=np.float64), off
 
 
 def depol1(p: float) -> tuple:
