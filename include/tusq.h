@@ -63,6 +63,10 @@ enum {
 /* kinds of the mid-circuit measurement layers tusq_circuit_measure appends
  * (not accepted by tusq_circuit_gate) */
 enum { TUSQ_MEASURE = 13, TUSQ_MEASURE_RESET = 14 };
+/* a caller's unitary (beyond the paper's named gates; its matrix is the
+ * gate's params, see tusq_circuit_gate).  No error commutes through one:
+ * a Pauli that reaches it stays just before it. */
+enum { TUSQ_UNITARY1 = 15, TUSQ_UNITARY2 = 16 };
 #define TUSQ_MAX_MEASURED 8u
 
 /* amplitude precision of the sweeps; reductions are always FP64 */
@@ -197,12 +201,18 @@ void tusq_opts_default(tusq_opts *opts);
 int tusq_circuit_create(uint32_t n_qubits, tusq_circuit **out);
 /* Append a gate.  qubits: 1 entry (2 for CX: control, target); params: 3
  * doubles (U3: theta, phi, lambda; RX/RY/RZ: angle first), may be NULL for
- * parameterless kinds.  gate_index_out (may be NULL) receives its index.   */
+ * parameterless kinds.  TUSQ_UNITARY1: params holds the 2x2 matrix, row-
+ * major, as 8 doubles (re, im pairs); TUSQ_UNITARY2: two distinct qubits
+ * and the 4x4 as 32 doubles, basis index 2 * bit(qubits[0]) + bit(qubits[1]);
+ * EINVAL unless the matrix is finite and unitary to 1e-10 (max entry of
+ * U^H U - I).  The matrix is copied.  gate_index_out (may be NULL)
+ * receives its index.                                                      */
 int tusq_circuit_gate(tusq_circuit *c, uint32_t kind, const uint32_t *qubits,
                       const double *params, uint32_t *gate_index_out);
 /* Attach a Pauli channel right after gate gate_index (Sec. II, Eq. (4) form):
- * 1-qubit gate: n_probs = 3, (pX, pY, pZ);  CX: n_probs = 15, entry k - 1 for
- * the Pauli k = 4a + b (a on the control, b on the target, I=0 X=1 Y=2 Z=3).
+ * 1-qubit gate: n_probs = 3, (pX, pY, pZ);  CX or UNITARY2: n_probs = 15,
+ * entry k - 1 for the Pauli k = 4a + b (a on the first qubit -- a CX's
+ * control --, b on the second; I=0 X=1 Y=2 Z=3).
  * The identity takes the remaining probability.  One channel per gate.      */
 int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double *probs,
                              uint32_t n_probs);

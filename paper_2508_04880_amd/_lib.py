@@ -28,6 +28,8 @@ TUSQ_EINVAL, TUSQ_ENOMEM, TUSQ_EUNSUPPORTED, TUSQ_EDEVICE, TUSQ_EBUSY, TUSQ_ECAN
     -1, -2, -3, -4, -5, -6)
 KINDS = {name: i for i, name in enumerate(
     ("U3", "RX", "RY", "RZ", "H", "S", "SDG", "T", "TDG", "X", "Y", "Z", "CX"))}
+# a caller's unitaries: the matrix travels as the gate's params
+KINDS.update({"UNITARY1": 15, "UNITARY2": 16})
 C128, C64 = 0, 1
 DFTT, NAIVE, HYBRID, CHECKPOINT, CACHING = 0, 1, 2, 3, 4
 WANT_DIST, WANT_SAMPLES, WANT_NORMS = 1, 2, 4
@@ -174,10 +176,16 @@ class Circuit:
                 continue
             q[0] = qs[0]
             q[1] = qs[1] if len(qs) > 1 else 0
-            for i in range(3):
-                pr[i] = params[i]
             gi = C.c_uint32()
-            check(lib.tusq_circuit_gate(self.h, C.c_uint32(KINDS[kind]), q, pr, C.byref(gi)))
+            if kind in ("UNITARY1", "UNITARY2"):
+                mat = (C.c_double * len(params))(*params)
+                check(lib.tusq_circuit_gate(self.h, C.c_uint32(KINDS[kind]), q, mat,
+                                            C.byref(gi)))
+            else:
+                for i in range(3):
+                    pr[i] = params[i]
+                check(lib.tusq_circuit_gate(self.h, C.c_uint32(KINDS[kind]), q, pr,
+                                            C.byref(gi)))
             if noise is not None:
                 arr = (C.c_double * len(noise))(*noise)
                 check(lib.tusq_circuit_pauli_noise(self.h, gi, arr, C.c_uint32(len(noise))))
@@ -187,6 +195,18 @@ class Circuit:
         no channel yet (tusq_circuit_thermal_noise)."""
         check(lib.tusq_circuit_thermal_noise(self.h, C.c_uint32(gate_index), C.c_double(t),
                                              C.c_double(t1), C.c_double(t2)))
+
+    def unitary(self, qubits, matrix) -> int:
+        """Append a caller's 2x2 (one qubit) or 4x4 (two qubits, basis index
+        2 * bit(qubits[0]) + bit(qubits[1])) unitary (tusq_circuit_gate with
+        TUSQ_UNITARY1 / TUSQ_UNITARY2); returns the gate's index."""
+        m = np.asarray(matrix, dtype=np.complex128).ravel()
+        kind = 15 if len(qubits) == 1 else 16
+        q = (C.c_uint32 * 2)(qubits[0], qubits[1] if len(qubits) > 1 else 0)
+        vals = (C.c_double * (2 * m.size))(*[v for z in m for v in (z.real, z.imag)])
+        g = C.c_uint32()
+        check(lib.tusq_circuit_gate(self.h, C.c_uint32(kind), q, vals, C.byref(g)))
+        return g.value
 
     def readout_noise(self, qubit: int, p: float) -> int:
         """Read-out flip of probability p on qubit: appends RZ(0) with an X

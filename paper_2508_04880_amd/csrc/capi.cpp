@@ -90,19 +90,46 @@ int tusq_circuit_gate(tusq_circuit *c, uint32_t kind, const uint32_t *qubits, co
                       uint32_t *gate_index_out) {
     return guarded([&] {
         need(c && qubits, "circuit or qubits is NULL");
-        need(kind < TUSQ_NUM_KINDS, "unknown gate kind");
+        const bool user = kind == TUSQ_UNITARY1 || kind == TUSQ_UNITARY2;
+        need(kind < TUSQ_NUM_KINDS || user, "unknown gate kind");
         Gate g{};
         g.kind = static_cast<uint8_t>(kind);
         g.q[0] = qubits[0];
-        g.q[1] = is_cx(g.kind) ? qubits[1] : 0;
+        g.q[1] = is_two_qubit(g.kind) ? qubits[1] : 0;
         need(g.q[0] < c->c.n, "qubit out of range");
-        if (is_cx(g.kind)) need(g.q[1] < c->c.n && g.q[1] != g.q[0], "CX qubits out of range or equal");
-        for (int i = 0; i < 3; ++i) {
-            g.p[i] = params ? params[i] : 0.0;
-            need(std::isfinite(g.p[i]), "non-finite gate parameter");
+        if (is_two_qubit(g.kind))
+            need(g.q[1] < c->c.n && g.q[1] != g.q[0], "2-qubit gate qubits out of range or equal");
+        std::vector<cd> u;
+        if (user) {
+            // the matrix, checked finite and unitary: max |(U^H U - I)_ij| <= 1e-10
+            const int d = kind == TUSQ_UNITARY1 ? 2 : 4;
+            need(params != nullptr, "a unitary gate needs its matrix in params");
+            u.resize(d * d);
+            for (int i = 0; i < d * d; ++i) {
+                u[i] = cd(params[2 * i], params[2 * i + 1]);
+                need(std::isfinite(params[2 * i]) && std::isfinite(params[2 * i + 1]),
+                     "non-finite matrix entry");
+            }
+            double dev = 0.0;
+            for (int r = 0; r < d; ++r)
+                for (int k = 0; k < d; ++k) {
+                    cd s = 0.0;
+                    for (int j = 0; j < d; ++j) s += std::conj(u[j * d + r]) * u[j * d + k];
+                    dev = std::max(dev, std::abs(s - (r == k ? 1.0 : 0.0)));
+                }
+            need(dev <= 1e-10, "matrix is not unitary");
+        } else {
+            for (int i = 0; i < 3; ++i) {
+                g.p[i] = params ? params[i] : 0.0;
+                need(std::isfinite(g.p[i]), "non-finite gate parameter");
+            }
         }
         g.chan = -1;
         need(c->c.gates.size() < 0xFFFFFFF0u, "too many gates");
+        if (user) {
+            g.umat = static_cast<uint32_t>(c->c.umats.size());
+            c->c.umats.insert(c->c.umats.end(), u.begin(), u.end());
+        }
         c->c.gates.push_back(g);
         c->c.dirty = true;
         if (gate_index_out) *gate_index_out = static_cast<uint32_t>(c->c.gates.size() - 1);
@@ -117,7 +144,7 @@ int tusq_circuit_pauli_noise(tusq_circuit *c, uint32_t gate_index, const double 
         Gate &g = c->c.gates[gate_index];
         need(!is_measure(g.kind), "a measurement layer takes no noise channel");
         need(g.chan < 0, "gate already has a channel");
-        need(n_probs == (is_cx(g.kind) ? 15u : 3u), "wrong number of probabilities for the gate");
+        need(n_probs == (is_two_qubit(g.kind) ? 15u : 3u), "wrong number of probabilities for the gate");
         double s = 0.0;
         Channel ch{};
         ch.m = static_cast<uint8_t>(n_probs);
@@ -159,8 +186,8 @@ int tusq_circuit_thermal_noise(tusq_circuit *c, uint32_t gate_index, double t, d
         need(c != nullptr, "circuit is NULL");
         need(gate_index < c->c.gates.size(), "gate index out of range");
         thermal_probs(t, t1, t2, p1);
-        if (is_cx(c->c.gates[gate_index].kind)) {
-            // independent channels on control (a) and target (b): outcome 4a + b
+        if (is_two_qubit(c->c.gates[gate_index].kind)) {
+            // independent channels on the first (a) and second (b) qubit: outcome 4a + b
             const double q[4] = {1.0 - p1[0] - p1[1] - p1[2], p1[0], p1[1], p1[2]};
             m = 15;
             for (int k = 1; k < 16; ++k) p[k - 1] = q[k >> 2] * q[k & 3];

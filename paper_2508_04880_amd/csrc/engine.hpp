@@ -27,7 +27,8 @@ struct Gate {
     uint8_t kind;
     uint32_t q[2];  // measurement layers: the measured-qubit mask, low word in q[0]
     double p[3];
-    int32_t chan;  // channel index or -1
+    int32_t chan;   // channel index or -1
+    uint32_t umat;  // UNITARY1 / UNITARY2: offset of the matrix in Circuit::umats
 };
 
 struct Channel {
@@ -41,15 +42,17 @@ struct Circuit {
     uint32_t n = 0;
     std::vector<Gate> gates;
     std::vector<Channel> chans;  // rebuilt in gate order by finalize()
+    std::vector<cd> umats;       // matrices of the caller's unitaries, row-major
     bool dirty = true;
     void finalize();
 };
 
 bool is_cx(uint8_t kind);
+bool is_two_qubit(uint8_t kind);  // CX or UNITARY2
 bool is_measure(uint8_t kind);
 inline uint64_t measure_mask(const Gate &g) { return uint64_t(g.q[0]) | (uint64_t(g.q[1]) << 32); }
 bool has_measure(const Circuit &c);
-void gate_matrix(const Gate &g, cd m[4]);  // 2x2 of a 1-qubit gate
+void gate_matrix(const Circuit &c, const Gate &g, cd m[4]);  // 2x2 of a 1-qubit gate
 
 // ---------------------------------------------------------------------------
 // Error events and the tree of circuits to simulate

@@ -29,6 +29,7 @@ unsigned host_threads(const tusq_opts &o) {
 }
 
 bool is_cx(uint8_t kind) { return kind == TUSQ_CX; }
+bool is_two_qubit(uint8_t kind) { return kind == TUSQ_CX || kind == TUSQ_UNITARY2; }
 bool is_measure(uint8_t kind) { return kind == TUSQ_MEASURE || kind == TUSQ_MEASURE_RESET; }
 bool has_measure(const Circuit &c) {
     for (const Gate &g : c.gates)
@@ -36,10 +37,11 @@ bool has_measure(const Circuit &c) {
     return false;
 }
 
-void gate_matrix(const Gate &g, cd m[4]) {
+void gate_matrix(const Circuit &circ, const Gate &g, cd m[4]) {
     const cd i(0.0, 1.0);
     const double h = g.p[0] * 0.5;
     switch (g.kind) {
+    case TUSQ_UNITARY1: std::copy(circ.umats.begin() + g.umat, circ.umats.begin() + g.umat + 4, m); return;
     case TUSQ_U3: {
         const double c = std::cos(g.p[0] * 0.5), s = std::sin(g.p[0] * 0.5);
         m[0] = c;
@@ -177,7 +179,14 @@ struct Commuter {
                     }
                 continue;
             }
-            if (is_cx(gt.kind)) {
+            if (gt.kind == TUSQ_UNITARY2) {
+                // a general 2-qubit unitary stops the Paulis on both qubits
+                for (int j = 0; j < 2; ++j)
+                    if (pend[gt.q[j]]) {
+                        out.push_back(Ev{g, gt.q[j], sym_to_code(pend[gt.q[j]])});
+                        pend[gt.q[j]] = 0;
+                    }
+            } else if (is_cx(gt.kind)) {
                 const uint32_t qc = gt.q[0], qt = gt.q[1];
                 uint8_t sc = pend[qc], st = pend[qt];
                 if (sc | st) {
@@ -197,14 +206,14 @@ struct Commuter {
             if (g_ev == g) {
                 const uint8_t o = static_cast<uint8_t>(codes[pos] & 15);
                 ++pos;
-                if (is_cx(gt.kind)) {
+                if (is_two_qubit(gt.kind)) {
                     set(gt.q[0], pend[gt.q[0]] ^ code_to_sym(o >> 2));
                     set(gt.q[1], pend[gt.q[1]] ^ code_to_sym(o & 3));
                 } else {
                     set(gt.q[0], pend[gt.q[0]] ^ code_to_sym(o));
                 }
             }
-            for (int j = 0; j < (is_cx(gt.kind) ? 2 : 1); ++j)
+            for (int j = 0; j < (is_two_qubit(gt.kind) ? 2 : 1); ++j)
                 if (pend[gt.q[j]]) schedule(gt.q[j], g);
         }
         for (uint32_t q : touched)
@@ -224,7 +233,7 @@ void place_uncommuted(const Circuit &c, const uint32_t *codes, size_t n, std::ve
         const Channel &ch = c.chans[codes[i] >> 4];
         const Gate &gt = c.gates[ch.gate];
         const uint8_t o = static_cast<uint8_t>(codes[i] & 15);
-        if (is_cx(gt.kind)) {
+        if (is_two_qubit(gt.kind)) {
             if (o >> 2) out.push_back(Ev{ch.gate + 1, gt.q[0], static_cast<uint8_t>(o >> 2)});
             if (o & 3) out.push_back(Ev{ch.gate + 1, gt.q[1], static_cast<uint8_t>(o & 3)});
         } else {
@@ -382,7 +391,7 @@ Tree build_tree(const Circuit &cin, const tusq_opts &o) {
             continue;
         }
         qg[c.gates[g].q[0]].push_back(g);
-        if (is_cx(c.gates[g].kind)) qg[c.gates[g].q[1]].push_back(g);
+        if (is_two_qubit(c.gates[g].kind)) qg[c.gates[g].q[1]].push_back(g);
     }
     std::vector<std::vector<Ev>> can(U);
     parallel_for(nt, U, [&](unsigned, uint64_t lo, uint64_t hi) {

@@ -427,6 +427,7 @@ struct Fuser {
         bool two;
         bool is_gate;
         M2 m2;            // 1-qubit matrix (gate or Pauli)
+        M4 m4;            // 2-qubit gate, basis index 2 * bit(qa) + bit(qb)
     };
 
     // Tokens one sweep would take from `rest` if its tile started as the
@@ -561,7 +562,7 @@ struct Fuser {
                     }
                 } else {
                     const int la = last[it.qa], lb = last[it.qb];
-                    const M4 g = cx_matrix();
+                    const M4 &g = it.m4;
                     if (la >= 0 && la == lb) {
                         BuildOp &o = ops[la];
                         o.m4 = mul4(o.qa == it.qa ? g : swap_halves(g), o.m4);
@@ -615,7 +616,7 @@ struct Fuser {
 };
 
 // Fuser items of tokens [a, b) of a leaf (toks from leaf_tokens); counts
-// gates, Paulis and the operation count (1 per 1-qubit token, 4 per CX).
+// gates, Paulis and the operation count (1 per 1-qubit token, 4 per 2-qubit gate).
 void token_items(const Circuit &c, const Ev *ev, const std::vector<Tok> &toks, uint64_t a,
                  uint64_t b, std::vector<Fuser::Item> &items, uint64_t &ng, uint64_t &np,
                  uint64_t &ops) {
@@ -628,15 +629,19 @@ void token_items(const Circuit &c, const Ev *ev, const std::vector<Tok> &toks, u
             const Gate &g = c.gates[tk.idx];
             it.is_gate = true;
             it.qa = g.q[0];
-            if (is_cx(g.kind)) {
+            if (is_two_qubit(g.kind)) {
                 it.two = true;
                 it.qb = g.q[1];
+                if (g.kind == TUSQ_UNITARY2)
+                    std::copy(c.umats.begin() + g.umat, c.umats.begin() + g.umat + 16, it.m4.begin());
+                else
+                    it.m4 = cx_matrix();
                 ops += 4;
             } else {
                 it.two = false;
                 it.qb = NONE;
                 cd m[4];
-                gate_matrix(g, m);
+                gate_matrix(c, g, m);
                 it.m2 = M2{m[0], m[1], m[2], m[3]};
                 ops += 1;
             }

@@ -393,6 +393,65 @@ def test_thermal_noise_attached_by_the_library_gives_the_oracle_tree():
         ec.thermal_noise(0, 0.1, 1.0, 1.0)       # the gate already has a channel
 
 
+@pytest.mark.parametrize("commute,prune", [(True, True), (True, False), (False, True)])
+def test_user_unitary_trees_equal_the_oracle(commute, prune):
+    """Circuits mixing named gates with a caller's UNITARY1 / UNITARY2
+    (tusq_circuit_gate copies the matrix): the library's tree equals the
+    oracle's byte for byte."""
+    from workloads.circuits import unitary_mix
+    for seed in range(3):
+        c = unitary_mix(6, 40, seed)
+        ot = oracle.ecm(c, 3000, 5 + seed, do_commute=commute, prune=prune)
+        o = tq.tusq_opts_default(shots=3000, seed=5 + seed, commute=int(commute),
+                                 prune=int(prune))
+        assert tq.Tree(tq.Circuit(c), o).serialize() == ot.serialize()
+
+
+@pytest.mark.parametrize("kernel", [0, 4])
+def test_user_unitary_programs_reproduce_oracle(kernel):
+    """The fused register programs of a circuit with a caller's unitaries,
+    replayed on the CPU, give the oracle's distribution."""
+    from workloads.circuits import unitary_mix
+    c = unitary_mix(10, 60, 7)
+    S = 3000
+    ot = oracle.ecm(c, S, 4)
+    dist, _, _, _ = oracle.run(c, ot, 4, want_samples=False)
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=4, fusion_max_qubits=8, fusion_low_qubits=2,
+                             fusion_max_ops=12, sweep_kernel=kernel)
+    et = tq.Tree(ec, o)
+    acc = _run_programs_numpy(c, tq.tusq_plan_dump(ec, et, o),
+                              tq.tusq_plan_dump_programs(ec, et, o), ot.weights())
+    np.testing.assert_allclose(acc, dist, atol=1e-12)
+
+
+def test_unitary_gate_arguments_are_checked():
+    import ctypes as C
+    h = C.c_void_p()
+    assert tq.lib.tusq_circuit_create(C.c_uint32(3), C.byref(h)) == 0
+    try:
+        q = (C.c_uint32 * 2)(0, 1)
+        same = (C.c_uint32 * 2)(1, 1)
+        eye2 = (C.c_double * 8)(1, 0, 0, 0, 0, 0, 1, 0)
+        eye4 = (C.c_double * 32)(*[float(i % 10 == 0 and i % 2 == 0) for i in range(32)])
+        bad = (C.c_double * 8)(1, 0, 1, 0, 0, 0, 1, 0)          # [[1, 1], [0, 1]]
+        nan = (C.c_double * 8)(float("nan"), 0, 0, 0, 0, 0, 1, 0)
+        g = C.c_uint32()
+        assert tq.lib.tusq_circuit_gate(h, 15, q, eye2, C.byref(g)) == 0 and g.value == 0
+        assert tq.lib.tusq_circuit_gate(h, 16, q, eye4, C.byref(g)) == 0 and g.value == 1
+        for kind, qs, m in ((15, q, bad), (15, q, nan), (15, q, None), (16, same, eye4),
+                            (17, q, eye2)):
+            assert tq.lib.tusq_circuit_gate(h, kind, qs, m, C.byref(g)) == -1
+        p3 = (C.c_double * 3)(0.1, 0, 0)
+        p15 = (C.c_double * 15)(*([0.01] * 15))
+        assert tq.lib.tusq_circuit_pauli_noise(h, 1, p3, 3) == -1
+        assert tq.lib.tusq_circuit_pauli_noise(h, 1, p15, 15) == 0
+        assert tq.lib.tusq_circuit_pauli_noise(h, 0, p3, 3) == 0
+        assert tq.lib.tusq_circuit_gate(h, 0, q, None, C.byref(g)) == 0 and g.value == 2
+    finally:
+        tq.lib.tusq_circuit_destroy(h)
+
+
 def test_readout_noise_through_the_library_gives_the_oracle_tree():
     """Read-out flips (Sec. IV-D) appended through tusq_circuit_readout_noise
     give the same tree, byte for byte, as the oracle's circuit with the same

@@ -152,6 +152,27 @@ def test_thermal_relaxation_noise_matches_oracle(ctx, precision):
 
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("trav", ["dftt", "checkpoint"])
+def test_user_unitaries_match_oracle(ctx, precision, trav):
+    """A caller's UNITARY1 / UNITARY2 gates (Haar-random) mixed with U3 and
+    CX, all noisy, on 13 qubits with tiles of 10: against the oracle."""
+    from workloads.circuits import unitary_mix
+    _say(f"[gpu] user unitaries {precision} {trav}")
+    c = unitary_mix(13, 120, 17)
+    S, seed = 5000, 8
+    ot = oracle.ecm(c, S, seed)
+    dist, _, oc, _ = oracle.run(c, ot, seed, traversal=trav, want_samples=False)
+    t, r = _run(ctx, c, S, seed, precision=precision, traversal=trav, fusion_max_qubits=10,
+                fusion_low_qubits=4, drift_bound=1.0)
+    assert t.serialize() == ot.serialize()
+    tol = 1e-10 if precision == "c128" else 1e-4
+    np.testing.assert_allclose(r.distribution(), dist, atol=tol, rtol=0)
+    ct = r.counters()
+    for k in ("fwd_gates", "inv_gates", "fwd_paulis", "inv_paulis", "paper_ops"):
+        assert ct[k] == oc[k], k
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_readout_noise_matches_oracle(ctx, precision):
     """Brickwork with the paper's depolarising noise plus a read-out flip on
     every qubit (tusq_circuit_readout_noise), against the oracle run on the

@@ -250,6 +250,35 @@ def random_small_circuit(n: int, n_gates: int, seed: int, p1: float = 0.05,
     return c
 
 
+def haar_unitary(d: int, rng) -> np.ndarray:
+    """A d x d unitary drawn from the Haar measure (QR of a complex Gaussian
+    matrix with the phases of R's diagonal divided out)."""
+    z = rng.normal(size=(d, d)) + 1j * rng.normal(size=(d, d))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def unitary_mix(n: int, n_gates: int, seed: int, p1: float = 0.02,
+                p2: float = 0.05) -> Circuit:
+    """Named gates (U3, CX) mixed with a caller's UNITARY1 / UNITARY2 gates
+    (Haar-random), each followed by depolarising noise."""
+    rng = np.random.default_rng(seed)
+    c = Circuit(n, name=f"unitary_mix_n{n}_G{n_gates}_s{seed}")
+    for _ in range(n_gates):
+        r = rng.random()
+        if r < 0.25:
+            c.add("U3", (int(rng.integers(n)),), rng.random(3) * 2 * math.pi, depol1(p1))
+        elif r < 0.45:
+            a, b = rng.choice(n, 2, replace=False)
+            c.add("CX", (int(a), int(b)), (), depol2(p2))
+        elif r < 0.7:
+            c.add_unitary((int(rng.integers(n)),), haar_unitary(2, rng), depol1(p1))
+        else:
+            a, b = rng.choice(n, 2, replace=False)
+            c.add_unitary((int(a), int(b)), haar_unitary(4, rng), depol2(p2))
+    return c
+
+
 @dataclass
 class JobParams:
     index: int
