@@ -262,6 +262,11 @@ int tusq_tree_get_info(const tusq_tree *t, tusq_tree_info *out);
  * (u32 slot, u32 qubit, u8 pauli).  With buf == NULL only *len_out is set. */
 int tusq_tree_serialize(const tusq_tree *t, uint8_t *buf, size_t cap, size_t *len_out);
 /* Raw (pre-commutation) events sorted by (shot, channel); cap = entries. */
+/* SHA-256 (FIPS 180-4) of those raw events, in that order, each as 9 bytes:
+ * u32 shot, u32 channel (little endian), u8 outcome -- a fingerprint of the
+ * error-sampling stage (Sec. III-A.1) for comparing runs and
+ * implementations without moving the list.  Writes 32 bytes.            */
+int tusq_raw_er_hash(const tusq_tree *t, uint8_t *sha256_out);
 int tusq_tree_raw_events(const tusq_tree *t, uint32_t *shot, uint32_t *channel,
                          uint8_t *outcome, uint64_t cap, uint64_t *n_out);
 int tusq_tree_destroy(tusq_tree *t);

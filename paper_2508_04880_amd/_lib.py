@@ -93,6 +93,7 @@ _SIGS = {
     "tusq_tree_serialize": (C.c_int, [P, P, C.c_size_t, P]),
     "tusq_tree_raw_events": (C.c_int, [P, P, P, P, C.c_uint64, P]),
     "tusq_tree_destroy": (C.c_int, [P]),
+    "tusq_raw_er_hash": (C.c_int, [P, P]),
     "tusq_plan_counters": (C.c_int, [P, P, P, P]),
     "tusq_plan_dump": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P]),
     "tusq_plan_dump_programs": (C.c_int, [P, P, P, P, P, P, P, P]),
@@ -257,6 +258,12 @@ class Tree:
         check(lib.tusq_tree_raw_events(self.h, _ptr(shot), _ptr(chan), _ptr(out),
                                        C.c_uint64(max(k, 1)), C.byref(n)))
         return shot[:k], chan[:k], out[:k]
+
+    def raw_er_hash(self) -> bytes:
+        """SHA-256 of the raw events (tusq_raw_er_hash)."""
+        out = (C.c_uint8 * 32)()
+        check(lib.tusq_raw_er_hash(self.h, out))
+        return bytes(out)
 
     def __del__(self):
         if getattr(self, "h", None):

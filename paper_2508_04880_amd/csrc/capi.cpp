@@ -10,6 +10,7 @@
 #include "engine.hpp"
 #include "exec.hpp"
 #include "serve.hpp"
+#include "sha256.hpp"
 
 using namespace tusq;
 
@@ -298,6 +299,31 @@ int tusq_tree_raw_events(const tusq_tree *t, uint32_t *shot, uint32_t *channel, 
             if (channel) std::memcpy(channel, t->t.raw_chan.data(), n * 4);
             if (outcome) std::memcpy(outcome, t->t.raw_out.data(), n);
         }
+    });
+}
+
+int tusq_raw_er_hash(const tusq_tree *t, uint8_t *sha256_out) {
+    return guarded([&] {
+        need(t && sha256_out, "tree or output is NULL");
+        Sha256 h;
+        const uint64_t n = t->t.raw_shot.size();
+        uint8_t rec[9 * 512];
+        size_t fill = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            const uint32_t s = t->t.raw_shot[i], ch = t->t.raw_chan[i];
+            for (int b = 0; b < 4; ++b) {
+                rec[fill + b] = static_cast<uint8_t>(s >> (8 * b));
+                rec[fill + 4 + b] = static_cast<uint8_t>(ch >> (8 * b));
+            }
+            rec[fill + 8] = t->t.raw_out[i];
+            fill += 9;
+            if (fill == sizeof(rec)) {
+                h.update(rec, fill);
+                fill = 0;
+            }
+        }
+        h.update(rec, fill);
+        h.finish(sha256_out);
     });
 }
 

@@ -452,6 +452,37 @@ def test_unitary_gate_arguments_are_checked():
         tq.lib.tusq_circuit_destroy(h)
 
 
+def _raw_bytes(shot, chan, out):
+    rec = np.zeros(len(shot), dtype=[("s", "<u4"), ("c", "<u4"), ("o", "u1")])
+    rec["s"], rec["c"], rec["o"] = shot, chan, out
+    return rec.tobytes()
+
+
+def test_raw_er_hash_is_sha256_of_the_oracles_raw_events():
+    """tusq_raw_er_hash equals hashlib's SHA-256 of the oracle's raw events
+    (9 bytes each: u32 shot, u32 channel, u8 outcome): no events (the
+    standard's digest of the empty message), lists whose byte length falls
+    on either side of the padding boundaries (55 / 56 / 64 bytes mod 64),
+    and a large list."""
+    import hashlib
+    c0 = random_small_circuit(4, 10, 1, p1=0.0, p2=0.0)
+    et = tq.Tree(tq.Circuit(c0), tq.tusq_opts_default(shots=50, seed=1))
+    assert et.raw_er_hash() == hashlib.sha256(b"").digest()
+    assert et.raw_er_hash().hex().startswith("e3b0c442")
+    seen = set()
+    cases = [(S, 0.5) for S in range(1, 41)] + [(20000, 0.05)]
+    for S, p in cases:
+        c = random_small_circuit(5, 30, 2, p1=p, p2=p)
+        ot = oracle.ecm(c, S, 9)
+        et = tq.Tree(tq.Circuit(c), tq.tusq_opts_default(shots=S, seed=9))
+        msg = _raw_bytes(*ot.raw_events())
+        seen.add(len(msg) % 64)
+        assert et.raw_er_hash() == hashlib.sha256(msg).digest(), (S, len(msg))
+    # a residue that still fits the length in the last block, and one that
+    # pushes it into an extra block
+    assert seen & set(range(48, 56)) and seen & set(range(56, 64)), sorted(seen)
+
+
 def test_readout_noise_through_the_library_gives_the_oracle_tree():
     """Read-out flips (Sec. IV-D) appended through tusq_circuit_readout_noise
     give the same tree, byte for byte, as the oracle's circuit with the same
