@@ -12,6 +12,7 @@ import oracle
 import paper_2508_04880_amd as tq
 from conftest import same_bits
 from workloads import brickwork, ising, random_small_circuit
+from workloads.circuits import unitary_mix
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +30,12 @@ def ctx():
     c.close()
 
 
+def _with_readout(c, p):
+    for q in range(c.n):
+        c.add_readout_noise(q, p)
+    return c
+
+
 JOBS = [
     lambda: brickwork(5, 6, 2e-3, 2e-2, 11),
     lambda: brickwork(10, 12, 1e-3, 1e-2, 12),
@@ -38,6 +45,8 @@ JOBS = [
     lambda: brickwork(14, 8, 1e-3, 1e-2, 15),
     lambda: brickwork(16, 6, 1e-3, 5e-3, 16),
     lambda: ising(15, 4, 1e-3, 5e-3),
+    lambda: unitary_mix(11, 60, 21),
+    lambda: _with_readout(brickwork(7, 8, 1e-3, 1e-2, 17), 0.03),
 ]
 
 
