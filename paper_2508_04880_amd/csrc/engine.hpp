@@ -160,6 +160,7 @@ struct Plan {
     std::vector<Pass> passes;
     std::vector<Op> ops;
     std::vector<cd> mats;
+    std::vector<std::pair<uint32_t, uint32_t>> mat_blocks;  // (offset, dim) of each matrix in mats
     std::vector<Step> steps;
     std::vector<Instr> prog;
     uint32_t reg_qubits = 4;  // R of the register-blocked programs
@@ -182,6 +183,10 @@ FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o)
 // op lists only, or count)
 Plan build_plan(const Circuit &c, const Tree &t, const tusq_opts &o, bool keep_paths,
                 bool programs = true);
+// The plan's matrices for complex64 sweeps, as (re, im) floats: each matrix
+// rounded so that its squared Frobenius norm stays the FP64 one (see
+// host_plan.cpp).
+void mats_to_c64(const Plan &p, std::vector<float> &out);
 
 // ---------------------------------------------------------------------------
 // Circuits with mid-circuit measurement layers (DFTT+Caching).  The tokens

@@ -123,9 +123,10 @@ void upload_plan_into(const Plan &plan, Workspace &ws, bool c64, hipStream_t s, 
     for (size_t i = 0; i < plan.mats.size(); ++i) m128[i] = double2{plan.mats[i].real(), plan.mats[i].imag()};
     if (c64) {
         std::vector<float2> &m64 = st.m64;
+        std::vector<float> flat;
+        mats_to_c64(plan, flat);
         m64.resize(plan.mats.size());
-        for (size_t i = 0; i < plan.mats.size(); ++i)
-            m64[i] = float2{static_cast<float>(plan.mats[i].real()), static_cast<float>(plan.mats[i].imag())};
+        for (size_t i = 0; i < plan.mats.size(); ++i) m64[i] = float2{flat[2 * i], flat[2 * i + 1]};
         mats_b.ensure(std::max<size_t>(m64.size(), 1) * sizeof(float2));
         if (!m64.empty())
             hip_check(hipMemcpyAsync(mats_b.p, m64.data(), m64.size() * sizeof(float2), hipMemcpyHostToDevice, s),

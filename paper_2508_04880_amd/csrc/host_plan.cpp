@@ -197,6 +197,7 @@ void build_programs(Plan &plan, Pass &p) {
     auto identity2 = [&]() {
         if (plan.identity2 == UINT32_MAX) {
             plan.identity2 = static_cast<uint32_t>(plan.mats.size());
+            plan.mat_blocks.emplace_back(plan.identity2, 2u);
             plan.mats.insert(plan.mats.end(), {cd(1.0), cd(0.0), cd(0.0), cd(1.0)});
         }
         return plan.identity2;
@@ -209,6 +210,7 @@ void build_programs(Plan &plan, Pass &p) {
         for (int i = 0; i < 16; ++i) m[i] = plan.mats[mat + i];
         const M4 w = swap_halves(m);
         const uint32_t off = static_cast<uint32_t>(plan.mats.size());
+        plan.mat_blocks.emplace_back(off, 4u);
         plan.mats.insert(plan.mats.end(), w.begin(), w.end());
         plan.swapped.emplace(mat, off);
         return off;
@@ -415,6 +417,8 @@ struct Fuser {
             if (it->second.second == d && std::memcmp(plan.mats.data() + it->second.first, m, nb) == 0)
                 return it->second.first;
         const uint32_t off = static_cast<uint32_t>(plan.mats.size());
+        plan.mat_blocks.emplace_back(off, static_cast<uint32_t>(d));
+        plan.mat_blocks.emplace_back(off + static_cast<uint32_t>(d * d), static_cast<uint32_t>(d));
         plan.mats.insert(plan.mats.end(), m, m + d * d);
         for (int r = 0; r < d; ++r)
             for (int cc = 0; cc < d; ++cc) plan.mats.push_back(std::conj(m[cc * d + r]));
@@ -667,6 +671,57 @@ uint64_t pass_flops_per_amp(const Plan &plan, const Pass &p) {
 }
 
 }  // namespace
+
+// Complex64 copies of the matrices.  Rounding each entry to its nearest
+// float leaves U^H U = I + E with tr E of the size of the rounding (~1e-7):
+// an op scales the squared norm of a spread-out state by about
+// 1 + tr(E)/d, with the same sign on every amplitude, and the same fused
+// matrices recur many times in a walk, so this adds up to the norm drift
+// that triggers complex128 recomputes.  Each matrix is rounded instead so
+// that its squared Frobenius norm -- the trace of U^H U -- stays the FP64
+// one: entries start at the nearest float, then, one at a time, an entry
+// moves to its other float neighbour, always the move that brings sum |f|^2
+// closest to the target, while a move improves it.  Every entry stays
+// within one float spacing of its FP64 value.
+void mats_to_c64(const Plan &p, std::vector<float> &out) {
+    out.assign(2 * p.mats.size(), 0.0f);
+    for (size_t i = 0; i < p.mats.size(); ++i) {
+        out[2 * i] = static_cast<float>(p.mats[i].real());
+        out[2 * i + 1] = static_cast<float>(p.mats[i].imag());
+    }
+    for (const auto &blk : p.mat_blocks) {
+        const uint32_t off = blk.first, nc = 2 * blk.second * blk.second;  // real components
+        float *f = out.data() + 2 * static_cast<size_t>(off);
+        double target = 0.0, sum = 0.0;
+        float alt[32];
+        bool moved[32] = {};
+        for (uint32_t k = 0; k < nc; ++k) {
+            const cd &z = p.mats[off + k / 2];
+            const double x = (k & 1) ? z.imag() : z.real();
+            target += x * x;
+            alt[k] = x > f[k] ? std::nextafter(f[k], HUGE_VALF)
+                   : x < f[k] ? std::nextafter(f[k], -HUGE_VALF) : f[k];
+            sum += double(f[k]) * f[k];
+        }
+        double err = sum - target;
+        for (;;) {
+            int best = -1;
+            double best_abs = std::fabs(err);
+            for (uint32_t k = 0; k < nc; ++k) {
+                if (moved[k] || alt[k] == f[k]) continue;
+                const double e2 = err - double(f[k]) * f[k] + double(alt[k]) * alt[k];
+                if (std::fabs(e2) < best_abs) {
+                    best = static_cast<int>(k);
+                    best_abs = std::fabs(e2);
+                }
+            }
+            if (best < 0) break;
+            err += double(alt[best]) * alt[best] - double(f[best]) * f[best];
+            std::swap(f[best], alt[best]);
+            moved[best] = true;
+        }
+    }
+}
 
 FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o) {
     FusionParams fp;
