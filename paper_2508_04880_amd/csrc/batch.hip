@@ -439,12 +439,12 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         }
         for (const Op &op : p.ops)
             dops.h.push_back(DOp{static_cast<uint32_t>(op.a) | (static_cast<uint32_t>(op.b) << 8), mat0 + op.mat});
-        if constexpr (std::is_same<V, float2>::value) {
-            std::vector<float> flat;
-            mats_to_c64(p, flat);
-            for (size_t i = 0; i < p.mats.size(); ++i) mats.h.push_back(V{flat[2 * i], flat[2 * i + 1]});
-        } else {
-            for (const cd &m : p.mats) mats.h.push_back(V{m.real(), m.imag()});
+        // nearest rounding for complex64: small batched jobs have no drift
+        // check to keep below its bound, and the norm-keeping rounding of the
+        // single-job path would add a serial host pass over every matrix
+        for (const cd &m : p.mats) {
+            using R = decltype(V{}.x);
+            mats.h.push_back(V{static_cast<R>(m.real()), static_cast<R>(m.imag())});
         }
         uint64_t soff = 0;
         for (uint64_t l = 0; l < up.lb; ++l) soff += trees[up.job].shots[l];

@@ -14,6 +14,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "engine.hpp"
 
@@ -689,7 +690,13 @@ void mats_to_c64(const Plan &p, std::vector<float> &out) {
         out[2 * i] = static_cast<float>(p.mats[i].real());
         out[2 * i + 1] = static_cast<float>(p.mats[i].imag());
     }
-    for (const auto &blk : p.mat_blocks) {
+    // blocks are independent: large plans split them over host threads
+    const size_t nb = p.mat_blocks.size();
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nt = nb >= (size_t(1) << 16) ? hw : 1u;
+    auto work = [&](size_t b0, size_t b1) {
+    for (size_t bi = b0; bi < b1; ++bi) {
+        const auto &blk = p.mat_blocks[bi];
         const uint32_t off = blk.first, nc = 2 * blk.second * blk.second;  // real components
         float *f = out.data() + 2 * static_cast<size_t>(off);
         double target = 0.0, sum = 0.0;
@@ -721,6 +728,14 @@ void mats_to_c64(const Plan &p, std::vector<float> &out) {
             moved[best] = true;
         }
     }
+    };
+    if (nt == 1) {
+        work(0, nb);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nt; ++t) th.emplace_back(work, nb * t / nt, nb * (t + 1) / nt);
+    for (auto &x : th) x.join();
 }
 
 FusionParams fusion_defaults(uint32_t n, uint32_t precision, const tusq_opts &o) {
