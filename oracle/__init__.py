@@ -13,12 +13,15 @@ pin the oracle for tiny qubit counts.
 from .oracle import (  # noqa: F401
     KIND_CODES,
     OracleTree,
+    apportion,
+    bounded,
     build_library,
     commute,
     ecm,
     leaf_margins,
     lib,
     philox,
+    prune_select,
     roundtrip,
     run,
     run_mcm,

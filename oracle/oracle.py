@@ -70,6 +70,10 @@ def lib():
         L.oc_run_mcm.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_uint32, C.c_uint64,
                                  C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oc_set_checkpoint_slots.argtypes = [C.c_uint64]
+        L.oc_prune_select.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_void_p]
+        L.oc_apportion.argtypes = [C.c_uint64, C.c_void_p, C.c_uint32, C.c_void_p]
+        L.oc_bounded.restype = C.c_uint64
+        L.oc_bounded.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64]
         L.oc_uniform53.restype = C.c_double
         L.oc_uniform53.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
                                    C.c_int]
@@ -108,6 +112,28 @@ class _CircuitHandle:
     @property
     def ref(self):
         return C.byref(self.s)
+
+
+def prune_select(seed: int, nins: int, beta: int) -> List[int]:
+    """Positions (ascending) of the beta insignificant circuits the pruning
+    stage keeps out of nins (Sec. III-A.4; the oracle's selection step)."""
+    out = np.zeros(max(nins, 1), dtype=np.uint64)
+    lib().oc_prune_select(int(seed), int(nins), int(beta), _ptr(out))
+    return [int(x) for x in out[:beta]]
+
+
+def apportion(s_insig: int, counts: Sequence[int]) -> List[int]:
+    """Integer shots of the selected circuits (the oracle's largest-remainder
+    step of Eq. (2))."""
+    cnt = np.ascontiguousarray(np.array(counts, dtype=np.uint64))
+    out = np.zeros(max(len(counts), 1), dtype=np.uint64)
+    lib().oc_apportion(int(s_insig), _ptr(cnt), len(counts), _ptr(out))
+    return [int(x) for x in out[:len(counts)]]
+
+
+def bounded(seed: int, t: int, m: int) -> int:
+    """The oracle's uniform integer in [0, m) from stream 1 (draw t)."""
+    return int(lib().oc_bounded(int(seed), int(t), int(m)))
 
 
 def philox(ctr: Sequence[int], key: Sequence[int]) -> Tuple[int, int, int, int]:

@@ -30,9 +30,12 @@
  *
  * Parity status: every function here is pinned by tests against values
  * that do not come from this file (published Philox vectors, density-matrix
- * simulation, closed forms, brute-force operator identities), except the
- * pruning selection stream, which follows a reading of the paper's
- * "randomly sample" and is pinned only by its invariants.
+ * simulation, closed forms, brute-force operator identities).  The pruning
+ * selection follows a reading of the paper's "randomly sample" (uniform
+ * without replacement) and is pinned by what that reading fixes: every
+ * beta-subset equally likely (chi-square over thousands of seeds), uniform
+ * bounded draws where a modulo bias would be gross, and the largest-remainder
+ * shots against hand-worked cases and a brute-force closest apportionment.
  */
 #include <complex.h>
 #include <math.h>
@@ -569,6 +572,51 @@ static uint64_t bounded(uint64_t seed, uint32_t t, uint64_t m)
     }
 }
 
+/* Pruning selection (Sec. III-A.4 says only that beta of the insignificant
+ * circuits are sampled at random; read as uniformly without replacement):
+ * a partial Fisher-Yates shuffle of the positions 0 .. nins-1 whose step t
+ * swaps position t with t + bounded(seed, t, nins - t).  out[0 .. beta)
+ * receives the chosen positions in ascending order; out holds nins entries
+ * (scratch beyond beta).  Requires beta <= nins. */
+void oc_prune_select(uint64_t seed, uint64_t nins, uint32_t beta, uint64_t *out)
+{
+    for (uint64_t t = 0; t < nins; ++t) out[t] = t;
+    for (uint32_t t = 0; t < beta; ++t) {
+        uint64_t r = bounded(seed, t, nins - t);
+        uint64_t tmp = out[t]; out[t] = out[t + r]; out[t + r] = tmp;
+    }
+    qsort(out, beta, sizeof(uint64_t), cmp_u64);
+}
+
+/* Integer shots of the beta selected circuits (Eq. (2): the insignificant
+ * shots sI shared in proportion to the selected counts cnt, D = their sum):
+ * the quota sI * cnt[t] / D is floored, and the sI - sum(floors) units left
+ * go one each to the largest remainders (sI * cnt[t]) mod D, a tie to the
+ * earlier circuit (Hamilton's largest-remainder method). */
+void oc_apportion(uint64_t sI, const uint64_t *cnt, uint32_t beta, uint64_t *out)
+{
+    uint64_t D = 0, given = 0;
+    for (uint32_t t = 0; t < beta; ++t) D += cnt[t];
+    uint64_t *rem = malloc(sizeof(uint64_t) * (beta + 1));
+    uint8_t *got = calloc(beta + 1, 1);
+    for (uint32_t t = 0; t < beta; ++t) {
+        uint64_t num = sI * cnt[t];
+        out[t] = num / D; rem[t] = num % D; given += out[t];
+    }
+    uint64_t left = sI - given;
+    for (uint64_t u = 0; u < left; ++u) {
+        int64_t best = -1;
+        for (uint32_t t = 0; t < beta; ++t)
+            if (!got[t] && (best < 0 || rem[t] > rem[best])) best = t;
+        got[best] = 1;
+        out[best] += 1;
+    }
+    free(got); free(rem);
+}
+
+/* bounded() for tests of the rejection rule */
+uint64_t oc_bounded(uint64_t seed, uint32_t t, uint64_t m) { return bounded(seed, t, m); }
+
 void oc_tree_free(oc_tree *t)
 {
     if (!t) return;
@@ -745,35 +793,18 @@ oc_tree *oc_ecm(const oc_circuit *c, uint64_t S, uint64_t seed, int commute, int
         T->stats[4] = sI; T->stats[5] = sI;
     } else {
         uint64_t *a = malloc(sizeof(uint64_t) * nins);
-        for (uint64_t t = 0; t < nins; ++t) a[t] = t;
-        for (uint32_t t = 0; t < beta; ++t) {
-            uint64_t r = bounded(seed, t, nins - t);
-            uint64_t tmp = a[t]; a[t] = a[t + r]; a[t + r] = tmp;
-        }
-        qsort(a, beta, sizeof(uint64_t), cmp_u64);
+        oc_prune_select(seed, nins, beta, a);
         uint64_t sI = 0, D = 0;
         for (uint64_t t = 0; t < nins; ++t) sI += lcnt[ins[t]];
-        for (uint32_t t = 0; t < beta; ++t) D += lcnt[ins[a[t]]];
+        uint64_t *cnt = malloc(sizeof(uint64_t) * beta), *got = malloc(sizeof(uint64_t) * beta);
+        for (uint32_t t = 0; t < beta; ++t) { cnt[t] = lcnt[ins[a[t]]]; D += cnt[t]; }
         T->stats[4] = sI; T->stats[5] = D;
-        uint64_t *rem = malloc(sizeof(uint64_t) * beta);
-        uint64_t given = 0;
+        oc_apportion(sI, cnt, beta, got);
         for (uint32_t t = 0; t < beta; ++t) {
             uint64_t i = ins[a[t]];
-            uint64_t num = sI * lcnt[i];
-            keep[i] = 1; wnum[i] = num; wden[i] = D * S;
-            shots[i] = num / D; rem[t] = num % D; given += shots[i];
+            keep[i] = 1; wnum[i] = sI * cnt[t]; wden[i] = D * S; shots[i] = got[t];
         }
-        /* largest remainder; ties go to the earlier leaf */
-        uint64_t left = sI - given;
-        uint8_t *got = calloc(beta, 1);
-        for (uint64_t u = 0; u < left; ++u) {
-            int64_t best = -1;
-            for (uint32_t t = 0; t < beta; ++t)
-                if (!got[t] && (best < 0 || rem[t] > rem[best])) best = t;
-            got[best] = 1;
-            shots[ins[a[best]]] += 1;
-        }
-        free(got); free(rem); free(a);
+        free(cnt); free(got); free(a);
     }
     free(ins);
 

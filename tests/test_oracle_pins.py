@@ -497,6 +497,162 @@ def test_pruned_keeps_exactly_beta_insignificant():
         assert n_ins == min(5, t.stats["insignificant"])
 
 
+# The selection step: the paper asks for beta of the insignificant circuits
+# "sampled at random"; read as uniform selection without replacement, every
+# beta-subset of the |C_I| positions is equally likely.  These checks hold
+# for that reading whatever generator drives it, so a biased shuffle, an
+# off-by-one draw range, a repeated position or a modulo bias fails them.
+
+def _chi2_bound(dof, tail=1e-6):
+    from scipy.stats import chi2
+    return float(chi2.ppf(1.0 - tail, dof))
+
+
+@pytest.mark.parametrize("nins,beta", [(10, 3), (7, 6), (12, 1)])
+def test_prune_selection_uniform_over_subsets(nins, beta):
+    seeds = 6000
+    subsets = {}
+    for seed in range(seeds):
+        sel = oracle.prune_select(seed, nins, beta)
+        assert sel == sorted(sel) and len(set(sel)) == beta        # no position twice
+        assert all(0 <= x < nins for x in sel)
+        subsets[tuple(sel)] = subsets.get(tuple(sel), 0) + 1
+    k = math.comb(nins, beta)
+    assert len(subsets) == k                                        # every subset reachable
+    e = seeds / k
+    chi2 = sum((subsets.get(sub, 0) - e) ** 2 / e
+               for sub in itertools.combinations(range(nins), beta))
+    assert chi2 < _chi2_bound(k - 1), chi2
+    # each position is kept with probability beta / nins
+    p = beta / nins
+    for pos in range(nins):
+        x = sum(v for sub, v in subsets.items() if pos in sub)
+        assert abs(x - seeds * p) < 5 * math.sqrt(seeds * p * (1 - p)), (pos, x)
+
+
+@pytest.mark.parametrize("m", [3 << 62, (1 << 63) + 1, 7])
+def test_bounded_draws_are_uniform(m):
+    # m = 3 * 2^62: reducing a 64-bit draw modulo m without rejection puts the
+    # values below 2^62 twice as often (probability 1/2 instead of 1/3);
+    # m = 2^63 + 1: the lower half gets 3/4 instead of 1/2
+    n = 6000
+    r = [oracle.bounded(seed, t, m) for seed in range(n // 30) for t in range(30)]
+    assert all(0 <= x < m for x in r)
+    if m > 1 << 62:
+        for cut, p in ((1 << 62, (1 << 62) / m), (m // 2, (m // 2) / m)):
+            x = sum(1 for v in r if v < cut)
+            assert abs(x - n * p) < 5 * math.sqrt(n * p * (1 - p)), (cut, x, n * p)
+    else:
+        e = n / m
+        chi2 = sum((r.count(v) - e) ** 2 / e for v in range(m))
+        assert chi2 < _chi2_bound(m - 1), chi2
+    assert oracle.bounded(5, 0, 1) == 0
+
+
+def test_pipeline_selection_matches_uniform_inclusion():
+    # through the whole error characterisation: per seed, the insignificant
+    # leaves of the lossless tree (in leaf order) and the ones the pruned
+    # tree keeps; rank r of C_I is kept with probability beta / |C_I|
+    c = brickwork(2, 2, 0.01, 0.03, seed=2)     # |C_I| of 12 .. 18 leaves
+    beta, S = 4, 400
+    X, E, V = {}, {}, {}
+    runs = 0
+    for s in range(2400):
+        seed = 7000 + s
+        tl = oracle.ecm(c, S, seed, prune=False)
+        smax = int(tl.count.max())
+        ins = [i for i in range(tl.n_leaves) if 20 * int(tl.count[i]) < smax]
+        if len(ins) <= beta:
+            continue
+        tp = oracle.ecm(c, S, seed, prune=True, alpha=(1, 20), beta=beta)
+        lossless = {tuple(tl.events(i)): i for i in range(tl.n_leaves)}
+        kept = [lossless[tuple(tp.events(j))] for j in range(tp.n_leaves)]
+        kept_ins = [i for i in kept if i in set(ins)]
+        assert len(kept_ins) == beta == len(set(kept_ins))
+        rank = {i: r for r, i in enumerate(ins)}
+        p = beta / len(ins)
+        for r in range(len(ins)):
+            E[r] = E.get(r, 0.0) + p
+            V[r] = V.get(r, 0.0) + p * (1 - p)
+        for i in kept_ins:
+            X[rank[i]] = X.get(rank[i], 0) + 1
+        runs += 1
+    assert runs >= 2000
+    z2 = 0.0
+    for r in E:
+        if V[r] < 25:   # ranks seen too rarely for a normal bound
+            continue
+        z = (X.get(r, 0) - E[r]) / math.sqrt(V[r])
+        assert abs(z) < 5, (r, X.get(r, 0), E[r])
+        z2 += z * z
+    dof = sum(1 for r in E if V[r] >= 25)
+    assert z2 < _chi2_bound(dof), (z2, dof)
+
+
+# The shots of the selected circuits: Eq. (2) shares the insignificant shots
+# s_I in proportion to the selected counts; integers by the largest-remainder
+# (Hamilton) method, ties to the earlier circuit.
+
+# (s_I, selected counts, shots) worked by hand.  Quotas q_j = s_I s_j / D:
+#  10, (1,1,1):  D=3, q = 10/3 each -> floors 3,3,3, one unit left, three equal
+#                remainders 1/3 -> the first circuit: 4,3,3
+#   8, (1,1,1):  q = 8/3 each -> floors 2,2,2, two left, equal remainders 2/3
+#                -> the first two: 3,3,2
+#  10, (1,2,4):  D=7, q = 10/7, 20/7, 40/7 -> floors 1,2,5, remainders 3/7,
+#                6/7, 5/7, two left -> the second and third: 1,3,6
+#  11, (3,2,2):  D=7, q = 33/7, 22/7, 22/7 -> floors 4,3,3, remainders 5/7,
+#                1/7, 1/7, one left -> the first: 5,3,3
+#   9, (2,1,2,1): D=6, q = 3, 1.5, 3, 1.5 -> floors 3,1,3,1, remainders 0,
+#                1/2, 0, 1/2, one left, tie of the second and fourth -> the
+#                second: 3,2,3,1
+#   7, (2,1,3,1): D=7, quotas exact: 2,1,3,1
+#   5, (1,1,1,1,1,1): q = 5/6 each, floors 0, five left -> 1,1,1,1,1,0
+HAND_APPORTIONED = [
+    (10, (1, 1, 1), (4, 3, 3)),
+    (8, (1, 1, 1), (3, 3, 2)),
+    (10, (1, 2, 4), (1, 3, 6)),
+    (11, (3, 2, 2), (5, 3, 3)),
+    (9, (2, 1, 2, 1), (3, 2, 3, 1)),
+    (7, (2, 1, 3, 1), (2, 1, 3, 1)),
+    (5, (1, 1, 1, 1, 1, 1), (1, 1, 1, 1, 1, 0)),
+]
+
+
+@pytest.mark.parametrize("s_insig,counts,want", HAND_APPORTIONED)
+def test_apportionment_hand_worked(s_insig, counts, want):
+    got = oracle.apportion(s_insig, counts)
+    assert tuple(got) == want
+    assert sum(got) == s_insig
+
+
+def _closest_apportionment(s_insig, counts):
+    """Brute force: among allocations a_j in {floor q_j, floor q_j + 1} with
+    sum s_I, those closest to the quotas in squared distance (exact
+    fractions); of several, the one giving the extra units to the earliest
+    circuits (lexicographically largest)."""
+    D = sum(counts)
+    q = [Fraction(s_insig * c, D) for c in counts]
+    fl = [math.floor(x) for x in q]
+    left = s_insig - sum(fl)
+    best, best_d = None, None
+    for extra in itertools.combinations(range(len(counts)), left):
+        a = [f + (1 if j in extra else 0) for j, f in enumerate(fl)]
+        d = sum((Fraction(x) - y) ** 2 for x, y in zip(a, q))
+        if best_d is None or d < best_d or (d == best_d and a > best):
+            best, best_d = a, d
+    return best
+
+
+def test_apportionment_is_the_closest_to_the_quotas():
+    rng = np.random.default_rng(11)
+    for _ in range(400):
+        k = int(rng.integers(1, 8))
+        counts = [int(x) for x in rng.integers(1, 6, size=k)]
+        s_insig = int(rng.integers(0, 40))
+        assert oracle.apportion(s_insig, counts) == _closest_apportionment(s_insig, counts), \
+            (s_insig, counts)
+
+
 # --------------------------------------------------------------------------
 # Shot sampling (leaf-level inverse CDF)
 
