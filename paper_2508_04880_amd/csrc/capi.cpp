@@ -556,7 +556,10 @@ int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, cons
             tr.leaf_end = le;
             tr.want = 0;
             tr.profile = 0;
+            // the probe plan keeps no recompute paths: no recompute of
+            // either kind may come due
             tr.drift_bound = 1e300;
+            tr.max_passes_between_recompute = 0;
             Plan p = build_plan(cc->c, t->t, tr, false);
             Result r;
             execute_plan(*ctx->c, t->t, p, tr, nullptr, r);

@@ -261,6 +261,8 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
                 const bool by_count = o.max_passes_between_recompute &&
                                       passes_since_exact > o.max_passes_between_recompute;
                 if (drift > o.drift_bound || by_count) {
+                    if (plan.path_off.size() < li + 2)
+                        fail(TUSQ_EINVAL, "a complex128 recompute came due on a plan built without recompute paths");
                     double2 *s128 = static_cast<double2 *>(psi128.p);
                     hip_check(launch_reset<double2>(s128, n, s), "reset128");
                     const double2 *mat128 = static_cast<const double2 *>(mats128_b.p);

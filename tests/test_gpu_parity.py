@@ -313,6 +313,28 @@ def test_autotuned_shape_is_valid_and_correct(ctx):
     np.testing.assert_allclose(r.distribution(), dist, atol=TOL_C128, rtol=0)
 
 
+def test_autotune_complex64_with_count_recompute(ctx):
+    """The tuner's probe plans hold no recompute paths; a complex64 job that
+    asks for a recompute every few passes must still tune, and the tuned
+    job (which does keep them) recomputes and matches the oracle."""
+    _say("[gpu] autotune c64 with max_passes_between_recompute")
+    c = brickwork(16, 8, 1e-3, 1e-2, 35)
+    S, seed = 2000, 15
+    ec = tq.Circuit(c)
+    o = tq.tusq_opts_default(shots=S, seed=seed, precision="c64",
+                             max_passes_between_recompute=2)
+    t = tq.Tree(ec, o)
+    tuned = tq.tusq_autotune(ctx, ec, t, o, 2)
+    assert tuned.max_passes_between_recompute == 2
+    r = tq.tusq_run_tree(ctx, ec, t, tuned)
+    assert r.counters()["recomputes"] > 0
+    ot = oracle.ecm(c, S, seed)
+    dist, _, _, _ = oracle.run(c, ot, seed, want_samples=False)
+    err = float(np.max(np.abs(r.distribution() - dist)))
+    _say(f"[gpu]   c64 tuned, recomputes {r.counters()['recomputes']}, max |dP| {err:.2e}")
+    assert err < TOL_C64
+
+
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_eight_amplitude_sweep_matches_oracle(ctx, precision):
     _say(f"[gpu] 8-amplitude sweep {precision}")
