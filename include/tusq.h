@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 7u
+#define TUSQ_ABI_VERSION 8u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -316,6 +316,29 @@ int tusq_run(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *opts, void *
 /* Same, for a tree built earlier with tusq_ecm_build (host stages untimed). */
 int tusq_run_tree(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t,
                   const tusq_opts *opts, void *hip_stream, tusq_result **out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run as tusq_run_tree with no device allocation and no device copy back.
+ * The state, the complex128 recompute state (TUSQ_C64), the sampler's chunk
+ * sums and prefix, the leaf norms, the uploaded plan and any checkpoint
+ * slots live in a static device array of TUSQ_NOALLOC_SCRATCH_BYTES per
+ * GPU, held until the process ends; a job whose buffers do not fit fails
+ * with TUSQ_ENOMEM before any device work (about 21 qubits at most in
+ * complex128 with a small plan).  dist_dev receives the 2^n FP64
+ * probabilities (required with TUSQ_WANT_DIST, else ignored) and
+ * samples_dev the job's samples (samples_len u64, at least the slice's
+ * shots, required with TUSQ_WANT_SAMPLES); both are caller device memory
+ * on the context's device.  counters_out (host, may be NULL) receives the
+ * counters.  Runs on hip_stream (NULL = the context's stream) and returns
+ * when the work has completed.  Measurement circuits: TUSQ_EUNSUPPORTED.
+ * Every call on one GPU shares that GPU's array, whichever context makes
+ * it: calls that overlap in time on one GPU race and give wrong results. */
+#define TUSQ_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int tusq_run_tree_noalloc(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t,
+                          const tusq_opts *opts, void *hip_stream, double *dist_dev,
+                          uint64_t *samples_dev, uint64_t samples_len,
+                          tusq_counters *counters_out);
 
 /* Autotuner: time a few candidate sweep shapes (tile qubits, low qubits,
  * dense ops per sweep, amplitudes per thread) on the depth-first slice

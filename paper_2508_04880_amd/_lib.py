@@ -102,6 +102,7 @@ _SIGS = {
     "tusq_run": (C.c_int, [P, P, P, P, P]),
     "tusq_run_tree": (C.c_int, [P, P, P, P, P, P]),
     "tusq_autotune": (C.c_int, [P, P, P, P, C.c_uint32, P]),
+    "tusq_run_tree_noalloc": (C.c_int, [P, P, P, P, P, P, P, C.c_uint64, P]),
     "tusq_submit": (C.c_int, [P, P, P, P]),
     "tusq_poll": (C.c_int, [P, C.c_uint64, P]),
     "tusq_wait": (C.c_int, [P, C.c_uint64, P]),
@@ -122,7 +123,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 7
+ABI_VERSION = 8
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")
@@ -382,6 +383,18 @@ def tusq_run_tree(ctx: Context, circuit: Circuit, tree: Tree, opts: tusq_opts,
     check(lib.tusq_run_tree(ctx.h, circuit.h, tree.h, C.byref(opts), C.c_void_p(stream or 0),
                             C.byref(h)))
     return Result(h, circuit.n)
+
+
+def tusq_run_tree_noalloc(ctx: Context, circuit: Circuit, tree: Tree, opts: tusq_opts,
+                          dist_dev: int, samples_dev: int, samples_len: int,
+                          stream: Optional[int] = None) -> dict:
+    """tusq_run_tree_noalloc: results land in caller device memory at the
+    addresses dist_dev / samples_dev (0 = none); returns the counters."""
+    c = tusq_counters()
+    check(lib.tusq_run_tree_noalloc(ctx.h, circuit.h, tree.h, C.byref(opts), C.c_void_p(stream or 0),
+                                    C.c_void_p(dist_dev or None), C.c_void_p(samples_dev or None),
+                                    C.c_uint64(samples_len), C.byref(c)))
+    return c.as_dict()
 
 
 def tusq_autotune(ctx: Context, circuit: Circuit, tree: Tree, opts: tusq_opts,

@@ -509,6 +509,28 @@ int tusq_run_tree(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, cons
     });
 }
 
+int tusq_run_tree_noalloc(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t,
+                          const tusq_opts *o, void *stream, double *dist_dev, uint64_t *samples_dev,
+                          uint64_t samples_len, tusq_counters *counters_out) {
+    return guarded([&] {
+        need(ctx && c && t, "NULL argument");
+        check_opts(o);
+        auto *cc = const_cast<tusq_circuit *>(c);
+        cc->c.finalize();
+        need(t->t.n == cc->c.n && t->t.G == cc->c.gates.size(), "tree was built for another circuit");
+        if (has_measure(cc->c))
+            fail(TUSQ_EUNSUPPORTED, "the no-allocation run takes circuits without measurement layers");
+        const double t0 = now_seconds();
+        Plan p = build_plan(cc->c, t->t, *o, o->precision == TUSQ_C64);
+        const double plan_s = now_seconds() - t0;
+        Result r;
+        execute_plan_static(*ctx->c, t->t, p, *o, static_cast<hipStream_t>(stream), r, dist_dev,
+                            samples_dev, samples_len);
+        r.counters.host_plan_seconds = plan_s;
+        if (counters_out) *counters_out = r.counters;
+    });
+}
+
 int tusq_autotune(tusq_ctx *ctx, const tusq_circuit *c, const tusq_tree *t, const tusq_opts *o,
                   uint32_t probe_leaves, tusq_opts *tuned) {
     return guarded([&] {

@@ -22,9 +22,10 @@ void hip_check(hipError_t e, const char *what) {
 
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
 }
 void DevBuf::alloc(size_t b) {
     release();
@@ -34,8 +35,39 @@ void DevBuf::alloc(size_t b) {
 }
 void DevBuf::ensure(size_t b) {
     if (b <= bytes && p) return;
+    if (!owned) fail(TUSQ_ENOMEM, "internal: a borrowed device buffer is too small");
     alloc(b);
 }
+void DevBuf::borrow(void *q, size_t b) {
+    release();
+    p = q;
+    bytes = b;
+    owned = false;
+}
+
+// Work memory of the no-allocation run (execute_plan_static).  Every device
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives for the
+// current device (Ctx::scratch), never through this name.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex scratch_mu;
+std::map<int, void *> scratch_ptrs;  // device -> address of its scratch copy
+
+// The scratch address on device dev, which must be current; looked up once
+// per device.
+void *scratch_address(int dev) {
+    std::lock_guard<std::mutex> g(scratch_mu);
+    auto it = scratch_ptrs.find(dev);
+    if (it != scratch_ptrs.end()) return it->second;
+    void *ptr = nullptr;
+    hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) fail(TUSQ_EDEVICE, "static scratch has no device address");
+    scratch_ptrs[dev] = ptr;
+    return ptr;
+}
+}  // namespace
 
 uint64_t Workspace::bytes() const {
     uint64_t b = 0;
@@ -311,11 +343,11 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
         ctx.recycle(evs);
     }
     res.n = n;
-    if (want_dist) {
+    if (want_dist && !ws.device_outputs) {
         res.dist.resize(N);
         hip_check(hipMemcpy(res.dist.data(), acc.p, N * 8, hipMemcpyDeviceToHost), "dist readback");
     }
-    if (want_samples && total_shots) {
+    if (want_samples && total_shots && !ws.device_outputs) {
         res.samples.resize(total_shots);
         hip_check(hipMemcpy(res.samples.data(), samples.p, total_shots * 8, hipMemcpyDeviceToHost),
                   "samples readback");
@@ -685,6 +717,7 @@ Ctx::Ctx(int dev, uint64_t budget_) : device(dev) {
     if (dev < 0 || dev >= count) fail(TUSQ_EINVAL, "no such device");
     hip_check(hipSetDevice(dev), "hipSetDevice");
     hip_check(sweep_kernel_setup(), "kernel setup");
+    scratch = scratch_address(dev);
     hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
     size_t fr = 0, tot = 0;
     hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
@@ -740,6 +773,66 @@ void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o,
     Workspace &w = ws ? *ws : local;
     if (o.precision == TUSQ_C64) run_typed<float2>(ctx, t, plan, o, s, res, w, cancel);
     else if (o.precision == TUSQ_C128) run_typed<double2>(ctx, t, plan, o, s, res, w, cancel);
+    else fail(TUSQ_EINVAL, "unknown precision");
+}
+
+void execute_plan_static(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o,
+                         hipStream_t s, Result &res, double *dist, uint64_t *samples,
+                         uint64_t samples_len) {
+    hip_check(hipSetDevice(ctx.device), "hipSetDevice");
+    if (!s) s = ctx.stream;
+    if (!ctx.scratch) fail(TUSQ_EDEVICE, "static scratch not set up");
+    const uint32_t n = plan.n;
+    const uint64_t N = 1ull << n;
+    const bool c64 = o.precision == TUSQ_C64;
+    const uint64_t B = c64 ? sizeof(float2) : sizeof(double2);
+    uint64_t lb = o.leaf_begin, le = o.leaf_end;
+    if (lb == 0 && le == 0) le = t.leaves();
+    uint64_t total_shots = 0;
+    for (uint64_t l = lb; l < le; ++l) total_shots += t.shots[l];
+    const bool want_dist = o.want & TUSQ_WANT_DIST;
+    const bool want_samples = (o.want & TUSQ_WANT_SAMPLES) && total_shots;
+    if (want_dist && !dist) fail(TUSQ_EINVAL, "TUSQ_WANT_DIST needs a device distribution buffer");
+    if (want_samples && (!samples || samples_len < total_shots))
+        fail(TUSQ_EINVAL, "the samples buffer holds " + std::to_string(samples_len) + " values, the job draws " +
+                              std::to_string(total_shots));
+    const uint32_t lc = std::min<uint32_t>(n, 11);
+    const uint64_t nc = N >> lc;
+    // the work buffers, each on a 256-byte boundary, in the order they are
+    // carved; sizes as run_typed and upload_plan_into ask for them
+    const uint64_t sizes[] = {
+        N * B,                                                      // psi
+        c64 ? N * sizeof(double2) : 0,                              // psi128
+        nc * 8,                                                     // csum
+        nc * 8,                                                     // prefix
+        std::max<uint64_t>(le - lb, 1) * 8,                         // norms
+        std::max<uint64_t>(plan.ops.size(), 1) * sizeof(DOp),       // dops
+        std::max<uint64_t>(plan.mats.size(), 1) * B,                // mats
+        c64 ? std::max<uint64_t>(plan.mats.size(), 1) * sizeof(double2) : 0,  // mats128
+        std::max<uint64_t>(plan.prog.size(), 1) * sizeof(Instr2),   // prog
+        plan.checkpoint_slots * N * B,                              // ckpt
+    };
+    uint64_t off[10], total = 0;
+    for (int i = 0; i < 10; ++i) {
+        off[i] = total;
+        total += (sizes[i] + 255) & ~255ull;
+    }
+    if (total > STATIC_SCRATCH_BYTES)
+        fail(TUSQ_ENOMEM, "the job needs " + std::to_string(total) + " bytes of work memory; the static scratch holds " +
+                              std::to_string(STATIC_SCRATCH_BYTES));
+    unsigned char *base = static_cast<unsigned char *>(ctx.scratch);
+    Workspace ws;
+    DevBuf *bufs[] = {&ws.psi, &ws.psi128, &ws.csum, &ws.prefix, &ws.norms,
+                      &ws.dops, &ws.mats, &ws.mats128, &ws.prog, &ws.ckpt};
+    for (int i = 0; i < 10; ++i)
+        if (sizes[i]) bufs[i]->borrow(base + off[i], sizes[i]);
+    if (want_dist) ws.acc.borrow(dist, N * 8);
+    if (want_samples) ws.samples.borrow(samples, samples_len * 8);
+    ws.device_outputs = true;
+    tusq_opts oo = o;
+    oo.profile = 0;  // no event pool growth
+    if (c64) run_typed<float2>(ctx, t, plan, oo, s, res, ws, nullptr);
+    else if (o.precision == TUSQ_C128) run_typed<double2>(ctx, t, plan, oo, s, res, ws, nullptr);
     else fail(TUSQ_EINVAL, "unknown precision");
 }
 

@@ -18,12 +18,15 @@ void hip_check(hipError_t e, const char *what);
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;  // false: a view of memory owned elsewhere, never freed
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf();
     void alloc(size_t b);
-    void ensure(size_t b);  // reallocate only when larger than what is held
+    void ensure(size_t b);  // reallocate only when larger than what is held;
+                            // a borrowed view fails with TUSQ_ENOMEM instead
+    void borrow(void *q, size_t b);
     void release();
 };
 
@@ -33,6 +36,9 @@ struct Workspace {
     DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops, mats, mats128, prog;
     DevBuf ckpt;  // checkpoint traversal: saved branch states; caching: cached nodes
     DevBuf mcm;   // measurement layers: per-block partial weights and P
+    // acc and samples are the caller's device buffers: the run leaves the
+    // distribution and samples there and copies neither back to the host
+    bool device_outputs = false;
     uint64_t bytes() const;
     void release();
 };
@@ -56,12 +62,17 @@ struct Ctx {
     std::vector<hipEvent_t> pool;
     Serving *serving = nullptr;
     std::map<uint64_t, std::array<uint32_t, 4>> tuned;  // autotuner choices
+    void *scratch = nullptr;  // this device's copy of the static scratch array
 
     Ctx(int dev, uint64_t budget);
     ~Ctx();
     hipEvent_t event();
     void recycle(std::vector<hipEvent_t> &evs);
 };
+
+// Size of the file-scope device array behind execute_plan_static: the
+// no-allocation run keeps its state, sampler sums, norms and plan there.
+constexpr uint64_t STATIC_SCRATCH_BYTES = TUSQ_NOALLOC_SCRATCH_BYTES;
 
 // Device bytes a job needs (state, recompute buffer, accumulator, sampler
 // scratch, samples, plan) -- used for admission.
@@ -71,6 +82,14 @@ uint64_t checkpoint_bytes(uint32_t n, uint32_t precision, uint64_t slots);
 
 void execute_plan(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hipStream_t s,
                   Result &res, Workspace *ws = nullptr, const std::atomic<bool> *cancel = nullptr);
+// The same run with no device allocation: every work buffer is carved from
+// the context's static scratch (TUSQ_ENOMEM when the job does not fit), the
+// distribution is accumulated in dist (2^n doubles, or NULL without
+// TUSQ_WANT_DIST) and the samples written to samples (samples_len u64)
+// in caller device memory; neither is copied to the host.
+void execute_plan_static(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o,
+                         hipStream_t s, Result &res, double *dist, uint64_t *samples,
+                         uint64_t samples_len);
 // DFTT+Caching over a circuit with measurement layers (host-driven walk: the
 // outcome weights of every pre-measurement node come back to the host, which
 // splits the node's shots and chooses the next launches)
