@@ -25,6 +25,7 @@ from .oracle import (  # noqa: F401
     roundtrip,
     run,
     run_mcm,
+    run_with_margins,
     sample_shot,
     set_threads,
     thermal_probs,

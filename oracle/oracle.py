@@ -57,6 +57,9 @@ def lib():
         L.oc_tree_serialize.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.oc_run.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_uint64,
                              C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.oc_run_margins.argtypes = [C.c_void_p, C.c_void_p, C.c_uint64, C.c_int, C.c_uint64,
+                                     C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]
         L.oc_trajectory.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_uint64, C.c_void_p]
         L.oc_roundtrip.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, C.c_void_p,
@@ -333,6 +336,30 @@ def run(circ, tree: OracleTree, seed: int, traversal: str = "dftt", leaf_begin: 
     counters = {k: int(v) for k, v in zip(COUNTER_NAMES, ctr)}
     return dist, (samples[:nshots] if samples is not None else None), counters, \
         norms[: le - leaf_begin]
+
+
+def run_with_margins(circ, tree: OracleTree, seed: int, traversal: str = "dftt",
+                     leaf_begin: int = 0, leaf_end: int = 0, want_dist: bool = True):
+    """run() with samples, also returning each draw's margin to the nearer
+    CDF boundary of its index: (dist or None, samples, margins, counters,
+    norms)."""
+    h = _CircuitHandle(circ)
+    lib().oc_set_checkpoint_slots(C.c_uint64(0))
+    le = leaf_end or tree.n_leaves
+    dist = np.zeros(1 << circ.n, np.float64) if want_dist else None
+    nshots = int(tree.shots[leaf_begin:le].sum())
+    samples = np.zeros(max(nshots, 1), np.uint64)
+    margins = np.zeros(max(nshots, 1), np.float64)
+    ctr = np.zeros(len(COUNTER_NAMES), np.uint64)
+    norms = np.zeros(max(le - leaf_begin, 1), np.float64)
+    rc = lib().oc_run_margins(h.ref, C.c_void_p(tree.handle), C.c_uint64(seed),
+                              C.c_int(TRAVERSAL[traversal]), C.c_uint64(leaf_begin),
+                              C.c_uint64(le), _ptr(dist) if dist is not None else None,
+                              _ptr(samples), _ptr(margins), _ptr(ctr), _ptr(norms))
+    if rc:
+        raise ValueError("oracle run failed")
+    counters = {k: int(v) for k, v in zip(COUNTER_NAMES, ctr)}
+    return dist, samples[:nshots], margins[:nshots], counters, norms[: le - leaf_begin]
 
 
 def run_mcm(circ, tree: OracleTree, seed: int, cache_capacity: int, leaf_begin: int = 0,

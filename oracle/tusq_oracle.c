@@ -1146,8 +1146,23 @@ static uint64_t draw_index(const double *cdf, uint64_t N, double x)
 static uint64_t ckpt_slots_limit = 0;
 void oc_set_checkpoint_slots(uint64_t slots) { ckpt_slots_limit = slots; }
 
+/* oc_run_margins: oc_run that also writes, per draw, the distance of its
+ * target to the nearer CDF boundary of the drawn index (the margin
+ * oc_leaf_margins gives), so that tests can excuse draws a different
+ * summation order may move without recomputing the leaf. */
+int oc_run_margins(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal,
+                   uint64_t lb, uint64_t le, double *dist, uint64_t *samples, double *margins,
+                   uint64_t *counters, double *norms);
+
 int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, uint64_t lb,
            uint64_t le, double *dist, uint64_t *samples, uint64_t *counters, double *norms)
+{
+    return oc_run_margins(c, t, seed, traversal, lb, le, dist, samples, NULL, counters, norms);
+}
+
+int oc_run_margins(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal,
+                   uint64_t lb, uint64_t le, double *dist, uint64_t *samples, double *margins,
+                   uint64_t *counters, double *norms)
 {
     if (validate(c)) return -1;
     if (has_measure(c)) return -3;  /* non-invertible edges: oc_run_mcm */
@@ -1256,7 +1271,13 @@ int oc_run(const oc_circuit *c, const oc_tree *t, uint64_t seed, int traversal, 
             for (uint64_t d = 0; d < t->shots[l]; ++d) {
                 uint64_t v = draw64(seed, (uint32_t)(d >> 1), (uint32_t)l, 0, 2, (int)(d & 1));
                 double u = (double)(v >> 11) * 0x1p-53;
-                samples[so++] = draw_index(cdf, N, u * nrm);
+                uint64_t i = draw_index(cdf, N, u * nrm);
+                if (margins) {
+                    double x = u * nrm, lo = i ? cdf[i - 1] : 0.0;
+                    double m1 = fabs(x - lo), m2 = fabs(cdf[i] - x);
+                    margins[so] = m1 < m2 ? m1 : m2;
+                }
+                samples[so++] = i;
                 ct.draws++;
             }
         }

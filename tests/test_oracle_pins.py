@@ -900,3 +900,25 @@ def test_bounded_checkpoints_trade_undo_for_memory():
     assert undo(runs[-1]) == 0 and runs[-1]["checkpoint_restores"] == t.n_leaves - 1
     assert all(undo(a) >= undo(b) for a, b in zip(runs, runs[1:]))
     assert all(a["checkpoint_restores"] <= b["checkpoint_restores"] for a, b in zip(runs, runs[1:]))
+
+
+def test_run_margins_equal_the_per_leaf_margins():
+    # the walk's per-draw margins are those of each leaf's state recomputed
+    # from the root (up to the rounding an undo leaves, ~5e-15 here), and
+    # the samples are the plain run's
+    c = brickwork(6, 6, 5e-3, 3e-2, seed=4)
+    t = oracle.ecm(c, 3000, 9)
+    d0, s0, _, _ = oracle.run(c, t, 9)
+    d1, s1, m1, _, _ = oracle.run_with_margins(c, t, 9)
+    assert np.array_equal(d0, d1) and np.array_equal(s0, s1)
+    off = 0
+    for leaf in range(t.n_leaves):
+        k = int(t.shots[leaf])
+        if not k:
+            continue
+        psi = oracle.trajectory(c, t.events(leaf))
+        idx, mar = oracle.leaf_margins(c, psi, 9, leaf, k)
+        assert np.array_equal(idx, s1[off:off + k])
+        np.testing.assert_allclose(m1[off:off + k], mar, rtol=0, atol=1e-13)
+        off += k
+    assert off == len(s1)
