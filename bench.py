@@ -68,9 +68,12 @@ def _args():
     p.add_argument("--autotune", action="store_true",
                    help="brick26: pick sweep shapes with the library's autotuner "
                         "(default: the library's default shape, as profiled)")
-    p.add_argument("--drift-bound", type=float, default=1e-5,
-                   help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds this")
-    p.add_argument("--batch-jobs", type=int, default=1024)
+    p.add_argument("--drift-bound", type=float, default=1e-6,
+                   help="complex64: recompute a leaf in complex128 when |norm - 1| exceeds "
+                        "this (default: the library's)")
+    p.add_argument("--cpu-leaves", type=int, default=2,
+                   help="brick26: leaves of the first timed slice the CPU oracle walks")
+    p.add_argument("--batch-jobs", type=int, default=4096)
     p.add_argument("--batch-chunk", type=int, default=256)
     p.add_argument("--batch-precisions", default="c128,c64")
     p.add_argument("--serve-count", type=int, default=60)
@@ -133,7 +136,7 @@ def kernel_name(sweep_kernel, v):
             5: f"k_sweep_pp<{v},3>"}.get(int(sweep_kernel), "?")
 
 
-def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision, want=2):
+def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision, want=3):
     """Run `steps` consecutive slices of L leaves; returns totals."""
     tot = {"shots": 0, "wall": 0.0, "sweep_bytes": 0, "sweep_flops": 0, "pass_seconds": 0.0,
            "pass_events": 0,
@@ -169,37 +172,51 @@ def run_slices(tq, ctx, ec, tree, base_opts, first_leaf, steps, L, precision, wa
     return tot
 
 
-def cpu_baseline(circ, tokens_applied, shots, budget_s):
-    """The oracle, as it stands, on a bounded sample: it applies the first K
-    gates of the circuit one by one in complex128 (OpenMP over amplitudes);
-    the per-gate time is scaled to the gate and error applications the plain
-    DFTT walk of the timed slices makes, and to their shots."""
+def cpu_baseline(circ, shots, seed, first, nleaves, budget_s):
+    """The oracle, as it stands, on the first `nleaves` leaves of the first
+    timed slice: its own error characterisation builds the tree (untimed,
+    as the engine's is), then its plain DFTT walk computes those leaves in
+    complex128 (the first from |0...0>, as the slice does), timed on the
+    host's cores.  One core is timed on a bounded prefix of the first leaf's
+    gates.  Returns the baseline record and the oracle's distribution,
+    samples and margins of those leaves (for the error statements)."""
     import oracle
-
-    def per_token_seconds(threads, budget):
-        oracle.set_threads(threads)
-        k = 2
-        while True:
-            t0 = time.perf_counter()
-            oracle.trajectory(circ, [], max_tokens=k)
-            elapsed = time.perf_counter() - t0
-            if elapsed > budget / 3 or k >= circ.n_gates:
-                break
-            k = min(circ.n_gates, k * 3)
-        return elapsed / k, k, elapsed
-
-    threads = min(os.cpu_count() or 1, 16)
-    per_token, k, elapsed = per_token_seconds(threads, budget_s)
-    # the same on one core, on a smaller budget
-    one, k1, e1 = per_token_seconds(1, budget_s / 3)
+    threads = min(os.cpu_count() or 1, 16)   # the GPU box's CPU share
     oracle.set_threads(threads)
-    return {"value": round(shots / (per_token * tokens_applied), 6), "unit": "shots/s",
-            "cores": threads, "kind": "oracle",
-            "single_core_value": round(shots / (one * tokens_applied), 6),
-            "sample": f"first {k} gates of the circuit applied by the oracle in "
-                      f"{elapsed:.1f} s (complex128, {threads} OpenMP threads; one core: "
-                      f"{k1} gates in {e1:.1f} s), scaled to the {tokens_applied} gate/error "
-                      f"applications and {shots} shots of the timed slices"}
+    t0 = time.perf_counter()
+    ot = oracle.ecm(circ, shots, seed)
+    ecm_s = time.perf_counter() - t0
+    _log(f"[bench] oracle ECM {ecm_s:.1f}s ({threads} threads)")
+    t0 = time.perf_counter()
+    dist, samples, margins, oc, _ = oracle.run_with_margins(circ, ot, seed, leaf_begin=first,
+                                                            leaf_end=first + nleaves)
+    walk_s = time.perf_counter() - t0
+    apps = oc["fwd_gates"] + oc["inv_gates"] + oc["fwd_paulis"] + oc["inv_paulis"]
+    _log(f"[bench] oracle walk of leaves [{first},{first + nleaves}) {walk_s:.1f}s, "
+         f"{apps} gate/error applications")
+    # one core: the first gates of the first leaf, within a bounded budget
+    oracle.set_threads(1)
+    k, e1 = 2, 0.0
+    while True:
+        t0 = time.perf_counter()
+        oracle.trajectory(circ, ot.events(first), max_tokens=k)
+        e1 = time.perf_counter() - t0
+        if e1 > budget_s / 3 or k >= circ.n_gates:
+            break
+        k = min(circ.n_gates, k * 3)
+    oracle.set_threads(threads)
+    rec = {"value": round(oc["draws"] / walk_s, 6), "unit": "shots/s", "cores": threads,
+           "kind": "oracle", "nproc": os.cpu_count(),
+           "sample": f"oracle plain-DFTT walk of leaves [{first},{first + nleaves}) (the "
+                     f"first timed slice's first {nleaves}, the first from |0...0>): "
+                     f"{apps} gate/error applications, {oc['draws']} shots in "
+                     f"{walk_s:.1f} s, complex128, {threads} OpenMP threads "
+                     f"(host nproc {os.cpu_count()}); its own tree built in {ecm_s:.1f} s, "
+                     f"untimed",
+           "seconds": round(walk_s, 2),
+           "single_core_gate_applications_per_s": round(k / e1, 2),
+           "single_core_sample": f"first {k} gates of leaf {first} on one core in {e1:.1f} s"}
+    return rec, dist, samples, margins
 
 
 def measured_traffic(kernel):
@@ -267,7 +284,7 @@ def bench_brick26(a, tq):
     run_slices(tq, ctx, ec, tree, b128, 1, a.warmup, L, "c128")
     first = 1 + a.warmup * L
     r128 = run_slices(tq, ctx, ec, tree, b128, first, a.steps, L, "c128")
-    r64 = None
+    r64 = b64 = None
     if not a.no_c64:
         b64 = tuned_opts(a, tq, ctx, ec, tree, base, "c64", default_tune=False)
         run_slices(tq, ctx, ec, tree, b64, 1, 1, L, "c64")
@@ -315,6 +332,8 @@ def bench_brick26(a, tq):
                    "qubits": a.qubits, "layers": a.layers, "shots": a.shots,
                    "leaves_per_step": L, "first_timed_leaf": first,
                    "tree_leaves": info["n_leaves"], "host_ecm_seconds": round(ecm_s, 3),
+                   "outputs": "FP64 distribution accumulated over the slice's leaves and "
+                              "read back, and every shot's sampled bitstring",
                    "sweep_shape_c128": {**{k: b128[k] for k in TUNED},
                                         "fusion_search": a.fusion_search}},
         "gate_sweep_GBps": round(gbs, 1),
@@ -356,7 +375,34 @@ def bench_brick26(a, tq):
             "sweeps_per_leaf": round(rck["passes"] / max(rck["leaves"], 1), 2),
             "slots": "unbounded"}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(circ, r128["tokens"], r128["shots"], a.cpu_seconds)
+        import numpy as np
+        nl = max(1, min(a.cpu_leaves, L))
+        rec, odist, osamp, omarg = cpu_baseline(circ, a.shots, 2, first, nl, a.cpu_seconds)
+        out["cpu_baseline"] = rec
+        # the engine on the same leaves (untimed), stated against the oracle
+        errs = {}
+        for prec, opts in (("c128", b128), ("c64", b64 if r64 else None)):
+            if opts is None:
+                continue
+            o = tq.tusq_opts_default(**opts, precision=prec, leaf_begin=first,
+                                     leaf_end=first + nl, want=3)
+            r = tq.tusq_run_tree(ctx, ec, tree, o)
+            d, smp, ct = r.distribution(), r.samples(), r.counters()
+            diff = np.abs(d - odist)
+            errs[prec] = {"max_abs": float(diff.max()),
+                          "max_abs_rel_to_largest": float(diff.max() / odist.max()),
+                          "total_variation": float(0.5 * diff.sum()),
+                          "samples_equal": int((smp == osamp).sum()),
+                          # draws that differ although the oracle's target is
+                          # at least 1e-11 from a CDF boundary
+                          "samples_differing_beyond_margin": int(
+                              ((smp != osamp) & (omarg >= 1e-11)).sum()),
+                          "samples": int(len(osamp)),
+                          "recomputes": int(ct["recomputes"]),
+                          "max_norm_drift": float(ct["max_norm_drift"])}
+        out["error_vs_oracle"] = {"leaves": [first, first + nl], **errs}
+        if "c64" in errs and "c64" in out:
+            out["c64"]["error_vs_oracle"] = errs["c64"]
     return out
 
 
@@ -428,7 +474,20 @@ def bench_batch(a, tq):
     precs = [x for x in a.batch_precisions.split(",") if x]
     for prec in precs:
         tot = {"wall": 0.0, "device": 0.0, "ecm": 0.0, "plan": 0.0, "shots": 0, "leaves": 0,
-               "passes": 0}
+               "passes": 0, "reused": 0}
+        shapes = {}
+        if not a.no_autotune:
+            # launch shapes per qubit count, timed on 2 jobs of each (cached
+            # in the context for every call below)
+            t0 = time.perf_counter()
+            tq.tusq_batch_autotune(ctx, ecs, tq.tusq_opts_default(shots=10_000, seed=100_000,
+                                                                  precision=prec,
+                                                                  traversal=a.traversal), 2)
+            _log(f"[bench] batch autotune {prec}: {time.perf_counter() - t0:.1f}s")
+        for n in sorted({c.n for c in circs}):
+            sh, tuned = tq.tusq_batch_shape(ctx, n, prec)
+            shapes[n] = {"threads": sh[0], "tile_qubits": sh[1], "low_qubits": sh[2],
+                         "ops_per_sweep": sh[3], "tuned": tuned}
         for c0 in range(0, len(ecs), a.batch_chunk):
             chunk = ecs[c0:c0 + a.batch_chunk]
             o = tq.tusq_opts_default(shots=10_000, seed=100_000, precision=prec,
@@ -445,6 +504,7 @@ def bench_batch(a, tq):
             cts = [r.counters() for r in res]     # per job (times: the whole call)
             tot["leaves"] += sum(int(c["leaves"]) for c in cts)
             tot["passes"] += sum(int(c["passes_fwd"] + c["passes_inv"]) for c in cts)
+            tot["reused"] += int(ct["batch_graph_reused"])
             _log(f"[bench] batch {prec} jobs [{c0},{c0 + len(chunk)}): wall {wall:.2f}s "
                  f"device {ct['device_seconds']:.2f}s host ECM {ct['host_ecm_seconds']:.2f}s "
                  f"plan {ct['host_plan_seconds']:.2f}s")
@@ -452,6 +512,7 @@ def bench_batch(a, tq):
                      "host_ecm_s": round(tot["ecm"], 3), "host_plan_s": round(tot["plan"], 3),
                      "leaves": tot["leaves"], "sweeps": tot["passes"],
                      "launches": -(-len(ecs) // a.batch_chunk),
+                     "graph_replays": tot["reused"], "shapes": shapes,
                      "shots_per_s_device": round(tot["shots"] / tot["device"], 1),
                      "shots_per_s_wall": round(tot["shots"] / tot["wall"], 1)}
         _log(f"[bench] batch {prec}: {out[prec]}")

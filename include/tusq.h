@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 8u
+#define TUSQ_ABI_VERSION 9u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -181,6 +181,9 @@ typedef struct {
     double host_ecm_seconds, host_plan_seconds, device_seconds;
     double max_norm_drift;              /* max |norm - 1| over leaves (FP64);
                                            complex64: before any recompute       */
+    uint64_t batch_graph_reused;        /* tusq_run_batch: 1 when the call
+                                           replayed the graph an earlier call
+                                           captured, 0 when it captured one     */
 } tusq_counters;
 
 typedef struct {
@@ -366,11 +369,35 @@ int tusq_cancel(tusq_ctx *ctx, uint64_t job_id);
 int tusq_job_times(tusq_ctx *ctx, uint64_t job_id, double *submitted, double *admitted,
                    double *finished);
 
-/* Batching: many small independent jobs (n <= 16) in one persistent,
- * graph-captured launch; work units (job, leaf range) are taken from a
- * device queue.  outs[i] receives job i's result.                          */
+/* Batching: many small independent jobs (n <= 16) with independent
+ * sub-trees walked in parallel (Sec. III-B, Fig. 6E).  Each job's leaves are
+ * cut into work units (job, leaf range) that start from |0...0>; units of
+ * one qubit count run in one persistent launch that takes them from a
+ * device queue (largest first), with the state in LDS (up to 2^13
+ * amplitudes complex128, 2^14 complex64) or in a per-workgroup global slot
+ * swept tile by tile.  The launches of a call (queue reset, one per qubit
+ * count, combine) form one hipGraph; a later call whose launch shapes match
+ * and whose buffers fit replays it (counters.batch_graph_reused).  Job i
+ * uses seed opts->seed + i; outs[i] receives its result.  complex64 jobs
+ * have no recompute: counters.max_norm_drift reports each job's largest
+ * |norm - 1|.                                                              */
 int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *opts,
                    size_t n_jobs, tusq_result **outs);
+
+/* Batch autotuner: for every qubit count among the jobs (at opts->precision)
+ * not tuned yet in this context, time candidate launch shapes -- threads
+ * per workgroup (256 / 512 / 1024), and for states kept in global memory
+ * the tile qubits, the low qubits always in a tile and the dense ops per
+ * sweep -- on up to probe_jobs of its jobs (at most 2000 shots each) and
+ * keep the fastest; tusq_run_batch then uses it for jobs of that size.     */
+int tusq_batch_autotune(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *opts,
+                        size_t n_jobs, uint32_t probe_jobs);
+/* The launch shape tusq_run_batch uses for n-qubit jobs at a precision:
+ * shape[0] threads per workgroup, [1] tile qubits (n itself when the state
+ * stays in LDS), [2] low qubits, [3] dense ops per sweep (0 = the planner's
+ * default); returns 1 in *tuned when it came from the autotuner.          */
+int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint32_t shape[4],
+                     int *tuned);
 
 /* ---- results --------------------------------------------------------------- */
 int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len);

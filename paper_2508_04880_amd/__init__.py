@@ -12,7 +12,7 @@ _EXPORTS = (
     "Circuit", "Context", "Result", "Tree", "TusqError", "lib", "tusq_cancel",
     "tusq_ctx_create", "tusq_ecm_build", "tusq_job_times", "tusq_opts", "tusq_opts_default",
     "tusq_plan_counters", "tusq_plan_dump", "tusq_plan_dump_programs", "tusq_poll", "tusq_run", "tusq_run_batch",
-    "tusq_run_tree", "tusq_run_tree_noalloc", "tusq_submit", "tusq_autotune", "tusq_wait", "LIB_PATH", "ABI_VERSION", "tusq_thermal_pauli_probs",
+    "tusq_run_tree", "tusq_run_tree_noalloc", "tusq_batch_autotune", "tusq_batch_shape", "tusq_submit", "tusq_autotune", "tusq_wait", "LIB_PATH", "ABI_VERSION", "tusq_thermal_pauli_probs",
 )
 
 

@@ -60,7 +60,8 @@ class tusq_counters(C.Structure):
         "recompute_passes", "sweep_bytes", "checkpoint_saves", "checkpoint_restores",
         "sweep_flops", "mcm_edges", "paper_ops", "pass_events")] + \
         [(k, C.c_double) for k in ("pass_seconds", "host_ecm_seconds", "host_plan_seconds",
-                                   "device_seconds", "max_norm_drift")]
+                                   "device_seconds", "max_norm_drift")] + \
+        [("batch_graph_reused", C.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -109,6 +110,8 @@ _SIGS = {
     "tusq_cancel": (C.c_int, [P, C.c_uint64]),
     "tusq_job_times": (C.c_int, [P, C.c_uint64, P, P, P]),
     "tusq_run_batch": (C.c_int, [P, P, P, C.c_size_t, P]),
+    "tusq_batch_autotune": (C.c_int, [P, P, P, C.c_size_t, C.c_uint32]),
+    "tusq_batch_shape": (C.c_int, [P, C.c_uint32, C.c_uint32, P, P]),
     "tusq_result_distribution": (C.c_int, [P, P, C.c_uint64]),
     "tusq_result_distribution_device": (C.c_int, [P, P, P]),
     "tusq_result_samples": (C.c_int, [P, P, C.c_uint64]),
@@ -123,7 +126,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 8
+ABI_VERSION = 9
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")
@@ -438,3 +441,19 @@ def tusq_run_batch(ctx: Context, circuits, opts: tusq_opts):
     outs = (C.c_void_p * len(circuits))()
     check(lib.tusq_run_batch(ctx.h, arr, C.byref(opts), C.c_size_t(len(circuits)), outs))
     return [Result(C.c_void_p(outs[i]), circuits[i].n) for i in range(len(circuits))]
+
+
+def tusq_batch_autotune(ctx: Context, circuits, opts: tusq_opts, probe_jobs: int = 4) -> None:
+    arr = (C.c_void_p * len(circuits))(*[c.h.value for c in circuits])
+    check(lib.tusq_batch_autotune(ctx.h, arr, C.byref(opts), C.c_size_t(len(circuits)),
+                                  C.c_uint32(probe_jobs)))
+
+
+def tusq_batch_shape(ctx: Context, n: int, precision) -> tuple:
+    """(threads, tile qubits, low qubits, ops per sweep), tuned?"""
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    out = (C.c_uint32 * 4)()
+    tuned = C.c_int()
+    check(lib.tusq_batch_shape(ctx.h, C.c_uint32(n), C.c_uint32(precision), out, C.byref(tuned)))
+    return tuple(out), bool(tuned.value)

@@ -19,6 +19,8 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <map>
+#include <mutex>
 #include <thread>
 
 #include "kernels.hpp"
@@ -135,14 +137,15 @@ __device__ __forceinline__ double pr(V v) {
 constexpr uint32_t BATCH_CHUNK_LOG = 6;   // 64 amplitudes per sampling chunk
 constexpr uint32_t BATCH_MAX_CHUNKS = 1024;
 
-template <typename V>
-__global__ void __launch_bounds__(256) k_batch(const BUnit *__restrict__ units, uint32_t n_units,
-                                               uint32_t *queue, const BStep *__restrict__ steps,
-                                               const BPass *__restrict__ passes,
-                                               const DOp *__restrict__ ops, const V *__restrict__ mats,
-                                               const BLeaf *__restrict__ leaves, V *scratch,
-                                               uint64_t slot_elems, double *partial,
-                                               uint64_t *samples, uint32_t lds_elems) {
+template <typename V, int NT>
+__global__ void __launch_bounds__(NT) k_batch(const BUnit *__restrict__ units,
+                                              const uint32_t *__restrict__ range, uint32_t *queue,
+                                              const BStep *__restrict__ steps,
+                                              const BPass *__restrict__ passes,
+                                              const DOp *__restrict__ ops, const V *__restrict__ mats,
+                                              const BLeaf *__restrict__ leaves, V *scratch,
+                                              uint64_t slot_elems, double *partial,
+                                              uint64_t *samples, double *norms, uint32_t lds_elems) {
     extern __shared__ unsigned char smem_raw[];
     V *tile = reinterpret_cast<V *>(smem_raw);
     double *cpre = reinterpret_cast<double *>(smem_raw + sizeof(V) * lds_elems);
@@ -152,10 +155,10 @@ __global__ void __launch_bounds__(256) k_batch(const BUnit *__restrict__ units, 
     V *slot = scratch + static_cast<uint64_t>(blockIdx.x) * slot_elems;
     for (;;) {
         __syncthreads();
-        if (tid == 0) s_unit = atomicAdd(queue, 1u);
+        if (tid == 0) s_unit = range[0] + atomicAdd(queue, 1u);
         __syncthreads();
         const uint32_t u = s_unit;
-        if (u >= n_units) break;
+        if (u >= range[1]) break;
         const BUnit U = units[u];
         const uint32_t n = U.n;
         const uint64_t N = 1ull << n;
@@ -222,6 +225,7 @@ __global__ void __launch_bounds__(256) k_batch(const BUnit *__restrict__ units, 
                         cpre[c] = r;
                     }
                     s_norm = r;
+                    norms[S.arg] = r;
                 }
                 __syncthreads();
                 const double norm = s_norm;
@@ -255,57 +259,182 @@ __global__ void __launch_bounds__(256) k_batch(const BUnit *__restrict__ units, 
     }
 }
 
+// Sizes of one call, read by the graph's kernels from device memory so that
+// a captured graph serves later calls of other sizes.
+struct BDesc {
+    uint64_t partial_elems;
+    uint64_t n_jobs;
+};
+
+// dist of job j = the sum of its units' partials in unit order (fixed
+// order: bitwise reproducible); blocks walk jobs, threads amplitudes
 __global__ void k_batch_combine(const double *partial, const uint64_t *job_unit_off,
                                 const uint64_t *unit_partial_off, const uint64_t *job_dist_off,
-                                const uint32_t *job_n, uint32_t n_jobs, double *dist) {
-    const uint32_t j = blockIdx.y;
-    if (j >= n_jobs) return;
-    const uint64_t N = 1ull << job_n[j];
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
-         i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-        double s = 0.0;
-        for (uint64_t u = job_unit_off[j]; u < job_unit_off[j + 1]; ++u) s += partial[unit_partial_off[u] + i];
-        dist[job_dist_off[j] + i] = s;
+                                const uint32_t *job_n, const BDesc *desc, double *dist) {
+    const uint64_t J = desc->n_jobs;
+    for (uint64_t j = blockIdx.x; j < J; j += gridDim.x) {
+        const uint64_t N = 1ull << job_n[j];
+        for (uint64_t i = threadIdx.x; i < N; i += blockDim.x) {
+            double s = 0.0;
+            for (uint64_t u = job_unit_off[j]; u < job_unit_off[j + 1]; ++u)
+                s += partial[unit_partial_off[u] + i];
+            dist[job_dist_off[j] + i] = s;
+        }
     }
 }
 
-__global__ void k_fill_batch(double *p, uint64_t n) {
+__global__ void k_fill_batch(double *p, const BDesc *desc) {
+    const uint64_t n = desc->partial_elems;
     for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
         p[i] = 0.0;
 }
 
-__global__ void k_set_u32(uint32_t *p, uint32_t v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__global__ void k_zero_u32(uint32_t *p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
+// Host side: plans, launch shapes, the reusable graph.
+
+constexpr uint32_t resident_max(bool c64) { return c64 ? 14u : 13u; }  // 128 KiB of LDS
+constexpr uint32_t tile_default(bool c64) { return c64 ? 13u : 12u; }   // 64 KiB tiles
+
+// Grow-only device buffer; ensure() reports whether the address changed (a
+// graph captured with the old address no longer fits).
+struct GrowBuf {
+    DevBuf d;
+    bool ensure(size_t b) {
+        b = std::max<size_t>(b, 8);
+        if (d.p && b <= d.bytes) return false;
+        d.alloc(b + b / 4);
+        return true;
+    }
+    template <typename T>
+    T *ptr() const { return static_cast<T *>(d.p); }
+};
+
+// The buffers of the batched launches and the graph over them, kept in the
+// context so that a later call with the same launch shapes replays it:
+// every size the kernels need comes from device memory (unit ranges per
+// qubit count, BDesc), uploaded before each replay.
+struct BatchCache {
+    GrowBuf units, range, steps, passes, dops, mats, leaves, juo, upo, jdo, jn, desc;
+    GrowBuf scratch, partial, dist, samples, norms, queues;
+    std::vector<uint64_t> sig;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        sig.clear();
+    }
+    ~BatchCache() { drop_graph(); }
+};
+
+void batch_cache_free(BatchCache *b) { delete b; }
+
 namespace {
 
 template <typename T>
-struct HostDev {
-    std::vector<T> h;
-    DevBuf d;
-    void upload(hipStream_t s) {
-        d.alloc(std::max<size_t>(h.size(), 1) * sizeof(T));
-        if (!h.empty()) hip_check(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
-    }
-    T *ptr() { return static_cast<T *>(d.p); }
-};
+void upload(GrowBuf &g, const std::vector<T> &h, hipStream_t s, bool &moved) {
+    moved |= g.ensure(h.size() * sizeof(T));
+    if (!h.empty()) hip_check(hipMemcpyAsync(g.d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
+}
+
+BatchShape default_shape(uint32_t n, bool c64) {
+    BatchShape b;
+    const bool res = n <= resident_max(c64);
+    b.threads = 256;
+    b.tile_qubits = res ? n : tile_default(c64);
+    b.low_qubits = res ? 0 : 5;
+    b.max_ops = 0;
+    return b;
+}
+
+uint64_t shape_key(uint32_t n, uint32_t precision) { return (static_cast<uint64_t>(n) << 8) | precision; }
+
+// the most LDS a batched launch asks for: a 2^13-amplitude complex128 (or
+// 2^14 complex64) state and the sampler's chunk prefix
+constexpr size_t BATCH_LDS_MAX = (16u << 13) + 8 * BATCH_MAX_CHUNKS;
+
+template <typename V, int NT>
+void set_lds_attr() {
+    static std::once_flag once;  // the attribute is per kernel, once per process
+    std::call_once(once, [] {
+        hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch<V, NT>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      static_cast<int>(BATCH_LDS_MAX)),
+                  "batch attr");
+    });
+}
+
+template <typename V, int NT>
+int occupancy(size_t lds) {
+    set_lds_attr<V, NT>();
+    int occ = 0;
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(k_batch<V, NT>),
+                                                           NT, lds),
+              "occupancy");
+    return std::max(occ, 1);
+}
 
 template <typename V>
+int occupancy_for(uint32_t threads, size_t lds) {
+    switch (threads) {
+    case 256: return occupancy<V, 256>(lds);
+    case 512: return occupancy<V, 512>(lds);
+    case 1024: return occupancy<V, 1024>(lds);
+    default: fail(TUSQ_EINVAL, "batch workgroups have 256, 512 or 1024 threads");
+    }
+    return 1;
+}
+
+template <typename V, int NT>
+void launch_class_nt(dim3 grid, size_t lds, hipStream_t s, BatchCache &bc, uint32_t ci, uint64_t slot_elems,
+                     bool want_dist, uint32_t lds_elems) {
+    set_lds_attr<V, NT>();
+    hipLaunchKernelGGL((k_batch<V, NT>), grid, dim3(NT), lds, s, bc.units.ptr<BUnit>(),
+                       bc.range.ptr<uint32_t>() + 2 * ci, bc.queues.ptr<uint32_t>() + ci, bc.steps.ptr<BStep>(),
+                       bc.passes.ptr<BPass>(), bc.dops.ptr<DOp>(), bc.mats.ptr<V>(), bc.leaves.ptr<BLeaf>(),
+                       bc.scratch.ptr<V>(), slot_elems, want_dist ? bc.partial.ptr<double>() : nullptr,
+                       bc.samples.ptr<uint64_t>(), bc.norms.ptr<double>(), lds_elems);
+}
+
+template <typename V>
+void launch_class(uint32_t threads, dim3 grid, size_t lds, hipStream_t s, BatchCache &bc, uint32_t ci,
+                  uint64_t slot_elems, bool want_dist, uint32_t lds_elems) {
+    switch (threads) {
+    case 256: launch_class_nt<V, 256>(grid, lds, s, bc, ci, slot_elems, want_dist, lds_elems); break;
+    case 512: launch_class_nt<V, 512>(grid, lds, s, bc, ci, slot_elems, want_dist, lds_elems); break;
+    default: launch_class_nt<V, 1024>(grid, lds, s, bc, ci, slot_elems, want_dist, lds_elems); break;
+    }
+}
+
+struct ClassInfo {
+    uint32_t n;
+    BatchShape shape;
+    uint32_t unit_begin = 0, unit_end = 0;
+    uint32_t grid = 0, lds_elems = 0;
+    size_t lds_bytes = 0;
+    uint64_t slot_elems = 0;
+};
+
+// force: one shape for every job (the autotuner's probes)
+template <typename V>
 void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq_opts &o,
-                 std::vector<Result> &out) {
+                 std::vector<Result> &out, const BatchShape *force) {
     const size_t J = circs.size();
     const bool c64 = std::is_same<V, float2>::value;
-    const uint32_t KL = c64 ? 14 : 13;        // LDS-resident up to 2^KL amplitudes (128 KiB)
-    const uint32_t KT = c64 ? 13 : 12;        // tile qubits for larger states (64 KiB)
+    const uint32_t KL = resident_max(c64);
     for (const Circuit *c : circs)
         if (c->n > 16 || c->n < 1) fail(TUSQ_EUNSUPPORTED, "batched jobs need 1..16 qubits");
     if (o.traversal == TUSQ_CHECKPOINT || o.traversal == TUSQ_CACHING)
         fail(TUSQ_EUNSUPPORTED, "the batched path has no checkpoint or caching traversal");
     if (J == 0) { out.clear(); return; }
-    if (J > 65535) fail(TUSQ_EUNSUPPORTED, "at most 65535 jobs per batch");
+    if (J > (1u << 30)) fail(TUSQ_EUNSUPPORTED, "too many jobs in one batch");
     const bool want_dist = o.want & TUSQ_WANT_DIST;
     hip_check(hipSetDevice(ctx.device), "hipSetDevice");
     hipStream_t s = ctx.stream;
@@ -339,13 +468,31 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
     }
     const double t_ecm = now_seconds() - t0;
 
+    // launch shape per qubit count: forced, tuned, or the default
+    std::map<uint32_t, BatchShape> shapes;
+    for (const Circuit *c : circs) {
+        if (shapes.count(c->n)) continue;
+        BatchShape b = default_shape(c->n, c64);
+        if (force) {
+            b = *force;
+            if (c->n <= KL) { b.tile_qubits = c->n; b.low_qubits = 0; }
+        } else {
+            std::lock_guard<std::mutex> g(ctx.mu);
+            auto it = ctx.batch_tuned.find(shape_key(c->n, o.precision));
+            if (it != ctx.batch_tuned.end()) b = it->second;
+        }
+        if (!force && o.fusion_max_ops && c->n > KL) b.max_ops = o.fusion_max_ops;
+        shapes[c->n] = b;
+    }
+
     // 2. work units: leaf ranges of similar cost; one plan per unit
-    HostDev<BUnit> units;
-    HostDev<BStep> steps;
-    HostDev<BPass> passes;
-    HostDev<DOp> dops;
-    HostDev<V> mats;
-    HostDev<BLeaf> leaves;
+    std::vector<BUnit> units_h;
+    std::vector<BStep> steps_h;
+    std::vector<BPass> passes_h;
+    std::vector<DOp> dops_h;
+    std::vector<V> mats_h;
+    std::vector<BLeaf> leaves_h;
+    std::vector<uint32_t> leaf_job;
     std::vector<uint64_t> job_unit_off(J + 1, 0), unit_poff, job_dist_off(J + 1, 0), job_sample_off(J + 1, 0);
     std::vector<uint32_t> job_n(J);
     uint64_t partial_elems = 0;
@@ -371,13 +518,14 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
     }
     auto unit_opts = [&](const UnitPlan &up) {
         const Circuit &c = *circs[up.job];
+        const BatchShape &b = shapes.at(c.n);
         tusq_opts ou = o;
         ou.seed = o.seed + up.job;
         ou.leaf_begin = up.lb;
         ou.leaf_end = up.le;
-        ou.fusion_max_qubits = c.n <= KL ? c.n : KT;
-        ou.fusion_low_qubits = c.n <= KL ? 0 : 5;
-        if (c.n > KL && o.fusion_max_ops) ou.fusion_max_ops = o.fusion_max_ops;
+        ou.fusion_max_qubits = c.n <= KL ? c.n : b.tile_qubits;
+        ou.fusion_low_qubits = c.n <= KL ? 0 : b.low_qubits;
+        if (b.max_ops) ou.fusion_max_ops = b.max_ops;
         return ou;
     };
     // units are planned on host threads a window at a time (op lists only)
@@ -418,15 +566,15 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         U.n = c.n;
         U.resident = c.n <= KL;
         U.k = ou.fusion_max_qubits;
-        U.step_begin = static_cast<uint32_t>(steps.h.size());
+        U.step_begin = static_cast<uint32_t>(steps_h.size());
         U.partial_off = partial_elems;
         U.sample_base = job_sample_off[up.job];
         U.seed = o.seed + up.job;
         if (want_dist) partial_elems += 1ull << c.n;
         unit_poff.push_back(U.partial_off);
-        const uint32_t pass0 = static_cast<uint32_t>(passes.h.size());
-        const uint32_t op0 = static_cast<uint32_t>(dops.h.size());
-        const uint32_t mat0 = static_cast<uint32_t>(mats.h.size());
+        const uint32_t pass0 = static_cast<uint32_t>(passes_h.size());
+        const uint32_t op0 = static_cast<uint32_t>(dops_h.size());
+        const uint32_t mat0 = static_cast<uint32_t>(mats_h.size());
         for (const Pass &pp : p.passes) {
             BPass bp{};
             bp.k = pp.k;
@@ -435,16 +583,16 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
             bp.op_begin = op0 + pp.op_begin;
             bp.op_end = op0 + pp.op_end;
             for (uint32_t j2 = 0; j2 < pp.k; ++j2) bp.q[j2] = static_cast<uint8_t>(pp.q[j2]);
-            passes.h.push_back(bp);
+            passes_h.push_back(bp);
         }
         for (const Op &op : p.ops)
-            dops.h.push_back(DOp{static_cast<uint32_t>(op.a) | (static_cast<uint32_t>(op.b) << 8), mat0 + op.mat});
-        // nearest rounding for complex64: small batched jobs have no drift
-        // check to keep below its bound, and the norm-keeping rounding of the
-        // single-job path would add a serial host pass over every matrix
+            dops_h.push_back(DOp{static_cast<uint32_t>(op.a) | (static_cast<uint32_t>(op.b) << 8), mat0 + op.mat});
+        // nearest rounding for complex64: batched jobs have no recompute, and
+        // the norm-keeping rounding of the single-job path would add a serial
+        // host pass over every matrix; each job reports its norm drift
         for (const cd &m : p.mats) {
             using R = decltype(V{}.x);
-            mats.h.push_back(V{static_cast<R>(m.real()), static_cast<R>(m.imag())});
+            mats_h.push_back(V{static_cast<R>(m.real()), static_cast<R>(m.imag())});
         }
         uint64_t soff = 0;
         for (uint64_t l = 0; l < up.lb; ++l) soff += trees[up.job].shots[l];
@@ -464,15 +612,16 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
                 L.sample_off = soff;
                 L.leaf = static_cast<uint32_t>(sp.id);
                 soff += t.shots[sp.id];
-                b.arg = static_cast<uint32_t>(leaves.h.size());
-                leaves.h.push_back(L);
+                b.arg = static_cast<uint32_t>(leaves_h.size());
+                leaves_h.push_back(L);
+                leaf_job.push_back(static_cast<uint32_t>(up.job));
                 work += static_cast<double>(1ull << c.n);
             }
-            steps.h.push_back(b);
+            steps_h.push_back(b);
         }
-        U.step_end = static_cast<uint32_t>(steps.h.size());
+        U.step_end = static_cast<uint32_t>(steps_h.size());
         U.work = work;
-        units.h.push_back(U);
+        units_h.push_back(U);
         tusq_counters &ct = jc[up.job];
         const tusq_counters &pc = p.counters;
         ct.fwd_gates += pc.fwd_gates; ct.inv_gates += pc.inv_gates;
@@ -483,87 +632,122 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         ct.sweep_flops += pc.sweep_flops;
     }
     const double t_plan = now_seconds() - t1;
-    // largest units first
-    std::vector<uint32_t> order(units.h.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return units.h[a].work > units.h[b].work; });
-    {
-        std::vector<BUnit> sorted(units.h.size());
-        for (size_t i = 0; i < order.size(); ++i) sorted[i] = units.h[order[i]];
-        units.h.swap(sorted);
-    }
 
-    // 3. device buffers and the graph
-    units.upload(s);
-    steps.upload(s);
-    passes.upload(s);
-    dops.upload(s);
-    mats.upload(s);
-    leaves.upload(s);
-    HostDev<uint64_t> d_juo, d_upo, d_jdo;
-    HostDev<uint32_t> d_jn;
-    d_juo.h = job_unit_off;
-    d_upo.h = unit_poff;
-    d_jdo.h = job_dist_off;
-    d_jn.h = job_n;
-    d_juo.upload(s);
-    d_upo.upload(s);
-    d_jdo.upload(s);
-    d_jn.upload(s);
+    // 3. one persistent launch per qubit count (largest states first), its
+    // units largest first
+    std::vector<ClassInfo> classes;
+    for (auto it = shapes.rbegin(); it != shapes.rend(); ++it) {
+        ClassInfo ci;
+        ci.n = it->first;
+        ci.shape = it->second;
+        classes.push_back(ci);
+    }
+    {
+        std::vector<uint32_t> order(units_h.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::vector<uint32_t> cls_of(17, 0);
+        for (uint32_t c = 0; c < classes.size(); ++c) cls_of[classes[c].n] = c;
+        std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+            const uint32_t ca = cls_of[units_h[a].n], cb = cls_of[units_h[b].n];
+            if (ca != cb) return ca < cb;
+            return units_h[a].work > units_h[b].work;
+        });
+        std::vector<BUnit> sorted(units_h.size());
+        for (size_t i = 0; i < order.size(); ++i) sorted[i] = units_h[order[i]];
+        units_h.swap(sorted);
+        for (uint32_t c = 0, u = 0; c < classes.size(); ++c) {
+            classes[c].unit_begin = u;
+            while (u < units_h.size() && units_h[u].n == classes[c].n) ++u;
+            classes[c].unit_end = u;
+        }
+    }
     int cus = 0;
     hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx.device), "attr");
-    const uint32_t lds_elems = 1u << std::max(KL, KT);
-    const size_t lds_bytes = sizeof(V) * lds_elems + 8 * BATCH_MAX_CHUNKS;
-    const uint32_t grid = static_cast<uint32_t>(std::max(1, cus));
-    uint32_t maxn = 0;
-    for (auto n : job_n) maxn = std::max(maxn, n);
-    const uint64_t slot_elems = maxn > KL ? (1ull << maxn) : 1;
-    DevBuf scratch, partial, samples, dist, queue;
-    scratch.alloc(slot_elems * grid * sizeof(V));
-    if (want_dist) {
-        partial.alloc(std::max<uint64_t>(partial_elems, 1) * 8);
-        dist.alloc(std::max<uint64_t>(job_dist_off[J], 1) * 8);
+    uint64_t scratch_elems = 1;
+    std::vector<uint32_t> range_h;
+    std::vector<uint64_t> sig = {o.precision, want_dist ? 1u : 0u, classes.size()};
+    for (ClassInfo &ci : classes) {
+        const bool res = ci.n <= KL;
+        ci.lds_elems = 1u << (res ? ci.n : ci.shape.tile_qubits);
+        ci.lds_bytes = sizeof(V) * ci.lds_elems + 8 * BATCH_MAX_CHUNKS;
+        ci.slot_elems = res ? 0 : (1ull << ci.n);
+        const int occ = occupancy_for<V>(ci.shape.threads, ci.lds_bytes);
+        ci.grid = static_cast<uint32_t>(std::max(1, cus) * occ);
+        scratch_elems = std::max<uint64_t>(scratch_elems, ci.slot_elems * ci.grid);
+        range_h.push_back(ci.unit_begin);
+        range_h.push_back(ci.unit_end);
+        sig.insert(sig.end(), {ci.n, ci.shape.threads, ci.grid, ci.lds_bytes, ci.slot_elems});
     }
-    samples.alloc(std::max<uint64_t>(job_sample_off[J], 1) * 8);
-    queue.alloc(4);
-    hip_check(hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch<V>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes)),
-              "batch attr");
+
+    // 4. buffers (kept in the context, grown when a call needs more), the
+    // graph (replayed when the launch shapes and buffer addresses match)
+    std::lock_guard<std::mutex> bg(ctx.batch_mu);
+    if (!ctx.batch) ctx.batch = new BatchCache;
+    BatchCache &bc = *ctx.batch;
+    bool moved = false;
+    const BDesc desc_h{partial_elems, J};
+    upload(bc.units, units_h, s, moved);
+    upload(bc.range, range_h, s, moved);
+    upload(bc.steps, steps_h, s, moved);
+    upload(bc.passes, passes_h, s, moved);
+    upload(bc.dops, dops_h, s, moved);
+    upload(bc.mats, mats_h, s, moved);
+    upload(bc.leaves, leaves_h, s, moved);
+    upload(bc.juo, job_unit_off, s, moved);
+    upload(bc.upo, unit_poff, s, moved);
+    upload(bc.jdo, job_dist_off, s, moved);
+    upload(bc.jn, job_n, s, moved);
+    upload(bc.desc, std::vector<BDesc>{desc_h}, s, moved);
+    moved |= bc.scratch.ensure(scratch_elems * sizeof(V));
+    if (want_dist) {
+        moved |= bc.partial.ensure(std::max<uint64_t>(partial_elems, 1) * 8);
+        moved |= bc.dist.ensure(std::max<uint64_t>(job_dist_off[J], 1) * 8);
+    }
+    moved |= bc.samples.ensure(std::max<uint64_t>(job_sample_off[J], 1) * 8);
+    moved |= bc.norms.ensure(std::max<size_t>(leaves_h.size(), 1) * 8);
+    moved |= bc.queues.ensure(classes.size() * 4);
     hip_check(hipStreamSynchronize(s), "sync");
 
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "capture");
-    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, static_cast<uint32_t *>(queue.p), 0u);
-    if (want_dist)
-        hipLaunchKernelGGL(k_fill_batch, dim3(static_cast<unsigned>(std::min<uint64_t>((partial_elems + 255) / 256, 65535))),
-                           dim3(256), 0, s, static_cast<double *>(partial.p), partial_elems);
-    hipLaunchKernelGGL(k_batch<V>, dim3(grid), dim3(256), lds_bytes, s, units.ptr(),
-                       static_cast<uint32_t>(units.h.size()), static_cast<uint32_t *>(queue.p), steps.ptr(),
-                       passes.ptr(), dops.ptr(), mats.ptr(), leaves.ptr(), static_cast<V *>(scratch.p), slot_elems,
-                       want_dist ? static_cast<double *>(partial.p) : nullptr, static_cast<uint64_t *>(samples.p),
-                       lds_elems);
-    if (want_dist)
-        hipLaunchKernelGGL(k_batch_combine, dim3(64, static_cast<unsigned>(J)), dim3(256), 0, s,
-                           static_cast<const double *>(partial.p), d_juo.ptr(), d_upo.ptr(), d_jdo.ptr(),
-                           d_jn.ptr(), static_cast<uint32_t>(J), static_cast<double *>(dist.p));
-    hipError_t ce = hipStreamEndCapture(s, &graph);
-    hip_check(ce, "end capture");
-    hip_check(hipGetLastError(), "batch launch");
-    hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    const bool reuse = !moved && bc.exec && bc.sig == sig;
+    if (!reuse) {
+        bc.drop_graph();
+        hip_check(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "capture");
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, bc.queues.ptr<uint32_t>(),
+                           static_cast<uint32_t>(classes.size()));
+        if (want_dist)
+            hipLaunchKernelGGL(k_fill_batch, dim3(static_cast<unsigned>(4 * std::max(1, cus))), dim3(256), 0, s,
+                               bc.partial.ptr<double>(), bc.desc.ptr<const BDesc>());
+        for (uint32_t c = 0; c < classes.size(); ++c) {
+            const ClassInfo &ci = classes[c];
+            launch_class<V>(ci.shape.threads, dim3(ci.grid), ci.lds_bytes, s, bc, c, ci.slot_elems, want_dist,
+                            ci.lds_elems);
+        }
+        if (want_dist)
+            hipLaunchKernelGGL(k_batch_combine, dim3(static_cast<unsigned>(2 * std::max(1, cus))), dim3(256), 0, s,
+                               bc.partial.ptr<const double>(), bc.juo.ptr<const uint64_t>(),
+                               bc.upo.ptr<const uint64_t>(), bc.jdo.ptr<const uint64_t>(),
+                               bc.jn.ptr<const uint32_t>(), bc.desc.ptr<const BDesc>(), bc.dist.ptr<double>());
+        hipError_t ce = hipStreamEndCapture(s, &bc.graph);
+        hip_check(ce, "end capture");
+        hip_check(hipGetLastError(), "batch launch");
+        hip_check(hipGraphInstantiate(&bc.exec, bc.graph, nullptr, nullptr, 0), "graph instantiate");
+        bc.sig = sig;
+    }
     const double t2 = now_seconds();
-    hip_check(hipGraphLaunch(exec, s), "graph launch");
+    hip_check(hipGraphLaunch(bc.exec, s), "graph launch");
     hip_check(hipStreamSynchronize(s), "sync");
     const double t_dev = now_seconds() - t2;
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
 
-    // 4. results
+    // 5. results
     std::vector<double> hdist(want_dist ? job_dist_off[J] : 0);
     std::vector<uint64_t> hs(job_sample_off[J]);
+    std::vector<double> hn(leaves_h.size());
     if (want_dist && !hdist.empty())
-        hip_check(hipMemcpy(hdist.data(), dist.p, hdist.size() * 8, hipMemcpyDeviceToHost), "dist");
-    if (!hs.empty()) hip_check(hipMemcpy(hs.data(), samples.p, hs.size() * 8, hipMemcpyDeviceToHost), "samples");
+        hip_check(hipMemcpy(hdist.data(), bc.dist.d.p, hdist.size() * 8, hipMemcpyDeviceToHost), "dist");
+    if (!hs.empty()) hip_check(hipMemcpy(hs.data(), bc.samples.d.p, hs.size() * 8, hipMemcpyDeviceToHost), "samples");
+    if (!hn.empty()) hip_check(hipMemcpy(hn.data(), bc.norms.d.p, hn.size() * 8, hipMemcpyDeviceToHost), "norms");
+    std::vector<double> drift(J, 0.0);
+    for (size_t i = 0; i < hn.size(); ++i) drift[leaf_job[i]] = std::max(drift[leaf_job[i]], std::fabs(hn[i] - 1.0));
     out.resize(J);
     for (size_t j = 0; j < J; ++j) {
         Result &r = out[j];
@@ -574,15 +758,77 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
         r.counters.host_ecm_seconds = t_ecm;
         r.counters.host_plan_seconds = t_plan;
         r.counters.device_seconds = t_dev;
+        r.counters.max_norm_drift = drift[j];
+        r.counters.batch_graph_reused = reuse ? 1 : 0;
     }
+}
+
+void run_batch_shape(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq_opts &o,
+                     std::vector<Result> &out, const BatchShape *force) {
+    if (o.precision == TUSQ_C64) batch_typed<float2>(ctx, circs, o, out, force);
+    else if (o.precision == TUSQ_C128) batch_typed<double2>(ctx, circs, o, out, force);
+    else fail(TUSQ_EINVAL, "unknown precision");
 }
 
 }  // namespace
 
 void run_batch(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq_opts &o,
                std::vector<Result> &out) {
-    if (o.precision == TUSQ_C64) batch_typed<float2>(ctx, circs, o, out);
-    else batch_typed<double2>(ctx, circs, o, out);
+    run_batch_shape(ctx, circs, o, out, nullptr);
+}
+
+BatchShape batch_shape(Ctx &ctx, uint32_t n, uint32_t precision, bool *tuned) {
+    std::lock_guard<std::mutex> g(ctx.mu);
+    auto it = ctx.batch_tuned.find(shape_key(n, precision));
+    if (tuned) *tuned = it != ctx.batch_tuned.end();
+    if (it != ctx.batch_tuned.end()) return it->second;
+    return default_shape(n, precision == TUSQ_C64);
+}
+
+void batch_autotune(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq_opts &o,
+                    uint32_t probe_jobs) {
+    const bool c64 = o.precision == TUSQ_C64;
+    if (o.precision != TUSQ_C64 && o.precision != TUSQ_C128) fail(TUSQ_EINVAL, "unknown precision");
+    std::map<uint32_t, std::vector<const Circuit *>> by_n;
+    for (const Circuit *c : circs) {
+        if (c->n > 16 || c->n < 1) fail(TUSQ_EUNSUPPORTED, "batched jobs need 1..16 qubits");
+        auto &v = by_n[c->n];
+        if (v.size() < std::max<uint32_t>(probe_jobs, 1)) v.push_back(c);
+    }
+    tusq_opts po = o;
+    po.shots = std::min<uint64_t>(o.shots, 2000);
+    po.want = TUSQ_WANT_SAMPLES;
+    po.fusion_max_ops = 0;
+    for (auto &kv : by_n) {
+        const uint32_t n = kv.first;
+        {
+            std::lock_guard<std::mutex> g(ctx.mu);
+            if (ctx.batch_tuned.count(shape_key(n, o.precision))) continue;
+        }
+        std::vector<BatchShape> cand;
+        if (n <= resident_max(c64)) {
+            for (uint32_t th : {256u, 512u, 1024u}) cand.push_back(BatchShape{th, n, 0, 0});
+        } else {
+            const uint32_t kt = tile_default(c64);
+            for (uint32_t th : {256u, 1024u})
+                for (uint32_t k : {kt - 1, kt})
+                    for (uint32_t ops : {16u, 32u}) cand.push_back(BatchShape{th, k, 5, ops});
+            cand.push_back(BatchShape{1024, kt, 4, 32});
+        }
+        double best = 1e300;
+        BatchShape pick = cand[0];
+        for (const BatchShape &b : cand) {
+            std::vector<Result> out;
+            run_batch_shape(ctx, kv.second, po, out, &b);
+            const double t = out.empty() ? 1e300 : out[0].counters.device_seconds;
+            if (t < best) {
+                best = t;
+                pick = b;
+            }
+        }
+        std::lock_guard<std::mutex> g(ctx.mu);
+        ctx.batch_tuned[shape_key(n, o.precision)] = pick;
+    }
 }
 
 }  // namespace tusq

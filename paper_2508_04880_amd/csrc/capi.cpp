@@ -674,6 +674,40 @@ int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_o
     });
 }
 
+int tusq_batch_autotune(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *o,
+                        size_t n_jobs, uint32_t probe_jobs) {
+    return guarded([&] {
+        need(ctx && circs, "NULL argument");
+        check_opts(o);
+        std::vector<const Circuit *> cs(n_jobs);
+        for (size_t i = 0; i < n_jobs; ++i) {
+            need(circs[i] != nullptr, "NULL circuit in batch");
+            auto *cc = const_cast<tusq_circuit *>(circs[i]);
+            if (has_measure(cc->c))
+                fail(TUSQ_EUNSUPPORTED, "the batched path runs circuits without measurement layers");
+            cc->c.finalize();
+            cs[i] = &cc->c;
+        }
+        batch_autotune(*ctx->c, cs, *o, probe_jobs);
+    });
+}
+
+int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint32_t shape[4],
+                     int *tuned) {
+    return guarded([&] {
+        need(ctx && shape, "NULL argument");
+        need(n_qubits >= 1 && n_qubits <= 16, "batched jobs have 1..16 qubits");
+        need(precision == TUSQ_C64 || precision == TUSQ_C128, "unknown precision");
+        bool t = false;
+        const BatchShape b = batch_shape(*ctx->c, n_qubits, precision, &t);
+        shape[0] = b.threads;
+        shape[1] = b.tile_qubits;
+        shape[2] = b.low_qubits;
+        shape[3] = b.max_ops;
+        if (tuned) *tuned = t ? 1 : 0;
+    });
+}
+
 int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len) {
     return guarded([&] {
         need(r && out, "NULL argument");

@@ -727,6 +727,7 @@ Ctx::Ctx(int dev, uint64_t budget_) : device(dev) {
 
 Ctx::~Ctx() {
     (void)hipSetDevice(device);
+    batch_cache_free(batch);
     for (auto e : pool) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
 }

@@ -51,7 +51,16 @@ struct Result {
     tusq_counters counters{};
 };
 
-struct Serving;  // request loop state (serve.cpp)
+struct Serving;     // request loop state (serve.cpp)
+struct BatchCache;  // batched launches: reusable graph and its buffers (batch.hip)
+void batch_cache_free(BatchCache *b);
+
+// Launch shape of batched jobs of one qubit count: threads per workgroup,
+// tile qubits (the qubit count itself when the state stays in LDS), low
+// qubits always in a tile, dense ops per sweep (0 = the planner's default).
+struct BatchShape {
+    uint32_t threads = 256, tile_qubits = 0, low_qubits = 0, max_ops = 0;
+};
 
 struct Ctx {
     int device = 0;
@@ -63,6 +72,9 @@ struct Ctx {
     Serving *serving = nullptr;
     std::map<uint64_t, std::array<uint32_t, 4>> tuned;  // autotuner choices
     void *scratch = nullptr;  // this device's copy of the static scratch array
+    std::map<uint64_t, BatchShape> batch_tuned;  // (qubits << 8 | precision) -> shape
+    BatchCache *batch = nullptr;
+    std::mutex batch_mu;
 
     Ctx(int dev, uint64_t budget);
     ~Ctx();

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 7
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 9
 
 
 def test_product_binding_has_no_oracle_dependency():
@@ -51,6 +51,32 @@ CASES = [
         4, 80, 9, p1=0.05, p2=0.05, kinds=("RX", "RY", "RZ", "CX", "X", "Y", "Z", "H")), 6_000),
     ("bell", lambda: bell_pair(0.1, 0.2), 3_000),
 ]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,make", [
+    ("brickwork26_L100", lambda: brickwork(26, 100, 1e-3, 1e-2, 1)),
+    ("ising30_T20", lambda: ising(30, 20, 5e-4, 5e-3))])
+def test_full_size_tree_bit_exact_against_oracle(name, make):
+    """The two HBM-scale workloads at their full 10^6 shots: the engine's
+    tree (all significant leaves at 26 qubits; 101 pruned leaves at 30)
+    and its raw-ER stream equal the oracle's byte for byte."""
+    c = make()
+    S, seed = 1_000_000, 2
+    threads = min(os.cpu_count() or 1, 16)
+    oracle.set_threads(threads)
+    try:
+        ot = oracle.ecm(c, S, seed)
+    finally:
+        oracle.set_threads(1)
+    ec = tq.Circuit(c)
+    et = tq.Tree(ec, tq.tusq_opts_default(shots=S, seed=seed, host_threads=threads))
+    assert et.info()["n_leaves"] == ot.n_leaves
+    a, b = et.serialize(), ot.serialize()
+    assert len(a) == len(b) and a == b
+    del a, b
+    import hashlib
+    assert et.raw_er_hash() == hashlib.sha256(_raw_bytes(*ot.raw_events())).digest()
 
 
 @pytest.mark.parametrize("name,make,S", CASES, ids=[c[0] for c in CASES])
