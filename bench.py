@@ -76,8 +76,10 @@ def _args():
     p.add_argument("--batch-jobs", type=int, default=4096)
     p.add_argument("--batch-chunk", type=int, default=256)
     p.add_argument("--batch-precisions", default="c128,c64")
-    p.add_argument("--serve-count", type=int, default=60)
-    p.add_argument("--serve-nmax", type=int, default=28)
+    p.add_argument("--serve-count", type=int, default=300)
+    p.add_argument("--serve-warmup", type=int, default=20,
+                   help="serve: requests at the head of the stream left out of the statistics")
+    p.add_argument("--serve-nmax", type=int, default=30)
     p.add_argument("--serve-load", type=float, default=0.7)
     p.add_argument("--checkpoint-slots", type=int, default=0,
                    help="checkpoint traversal: most branch states kept (0 = no bound)")
@@ -538,9 +540,11 @@ def bench_serve(a, tq):
     per = (time.perf_counter() - t0) / len(warm)
     _log(f"[bench] serving burst of {len(warm)}: {per:.3f} s per request")
     rate = a.serve_load / per
-    reqs = serving_requests(a.serve_count, rate, seed=4, n_max=a.serve_nmax,
+    W = a.serve_warmup
+    reqs = serving_requests(W + a.serve_count, rate, seed=4, n_max=a.serve_nmax,
                             shots_exp=(4.0, 6.0))
-    _log(f"[bench] serving: capacity {1 / per:.2f} req/s, offered {rate:.2f} req/s")
+    _log(f"[bench] serving: capacity {1 / per:.2f} req/s, offered {rate:.2f} req/s, "
+         f"{W} warm-up + {a.serve_count} requests")
     prepared = [(rq, tq.Circuit(rq.circuit())) for rq in reqs]
     ids = [None] * len(reqs)
     start = time.perf_counter()
@@ -553,21 +557,29 @@ def bench_serve(a, tq):
             o = tq.tusq_opts_default(shots=rq.shots, seed=rq.seed, precision=rq.precision,
                                      want=2)
             ids[i] = tq.tusq_submit(ctx, ec, o)
+            if i % 10 == 0:
+                _log(f"[bench] submitted request {i} at {time.perf_counter() - start:.1f}s")
 
     th = threading.Thread(target=producer)
     th.start()
-    th.join()
-    lat, shots = [], 0
+    lat, shots, mix = [], 0, {}
     first_sub, last_fin = None, None
-    for i, ((rq, ec), j) in enumerate(zip(prepared, ids)):
-        r = tq.tusq_wait(ctx, j, rq.n)
+    for i, (rq, ec) in enumerate(prepared):
+        while ids[i] is None:
+            time.sleep(0.01)
+        r = tq.tusq_wait(ctx, ids[i], rq.n)
+        sub, adm, fin = tq.tusq_job_times(ctx, ids[i])
+        _log(f"[bench] serve request {i}: n={rq.n} {rq.family} {rq.precision} S={rq.shots} "
+             f"latency {fin - sub:.3f}s (queued {adm - sub:.3f}s)")
+        if i < W:
+            continue
         shots += len(r.samples())
-        sub, adm, fin = tq.tusq_job_times(ctx, j)
         lat.append(fin - sub)
-        _log(f"[bench] serve request {i}: n={rq.n} {rq.precision} S={rq.shots} "
-             f"latency {fin - sub:.3f}s")
+        key = f"n{rq.n // 5 * 5}-{rq.n // 5 * 5 + 4}"
+        mix.setdefault(key, []).append(fin - sub)
         first_sub = sub if first_sub is None else min(first_sub, sub)
         last_fin = fin if last_fin is None else max(last_fin, fin)
+    th.join()
     lat = np.array(lat)
     return {"metric": "served noisy jobs: p50/p99 latency and aggregate shots/sec",
             "value": round(float(np.percentile(lat, 50)), 4), "unit": "s (p50 latency)",
@@ -576,9 +588,11 @@ def bench_serve(a, tq):
             "p99_s": round(float(np.percentile(lat, 99)), 4),
             "aggregate_shots_per_s": round(shots / (last_fin - first_sub), 1),
             "offered_req_per_s": round(rate, 3), "capacity_req_per_s": round(1 / per, 3),
-            "config": {"workload": f"{a.serve_count} Poisson requests, n log-uniform "
-                                   f"12..{a.serve_nmax}, brickwork/Ising 50/50, S=10^U[4,6], "
-                                   f"c64/c128 50/50, load {a.serve_load}"}}
+            "p50_by_qubits_s": {k: round(float(np.percentile(v, 50)), 4)
+                                for k, v in sorted(mix.items())},
+            "config": {"workload": f"{a.serve_count} Poisson requests after {W} warm-up, "
+                                   f"n log-uniform 12..{a.serve_nmax}, brickwork/Ising 50/50, "
+                                   f"S=10^U[4,6], c64/c128 50/50, load {a.serve_load}"}}
 
 
 def mcm_circuit(n, layers, every, width, seed):

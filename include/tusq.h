@@ -313,7 +313,12 @@ int tusq_ctx_destroy(tusq_ctx *ctx);
 
 /* Run one job to completion: ECM on the host, then the depth-first walk on
  * the device on hip_stream (a hipStream_t; NULL = the context's stream).
- * Synchronises before returning.                                           */
+ * Synchronises before returning.  The FP64 distribution (TUSQ_WANT_DIST)
+ * stays in the device memory it was accumulated in, held by the result
+ * until tusq_result_destroy; tusq_result_distribution copies it to the
+ * host, tusq_result_distribution_device to caller device memory.  Samples,
+ * norms and counters are on the host.  (Served and batched jobs return
+ * their distribution on the host.)                                          */
 int tusq_run(tusq_ctx *ctx, const tusq_circuit *c, const tusq_opts *opts, void *hip_stream,
              tusq_result **out);
 /* Same, for a tree built earlier with tusq_ecm_build (host stages untimed). */

@@ -711,19 +711,26 @@ int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint3
 int tusq_result_distribution(const tusq_result *r, double *out, uint64_t len) {
     return guarded([&] {
         need(r && out, "NULL argument");
-        need(!r->r.dist.empty(), "result holds no distribution");
-        need(len == r->r.dist.size(), "len must be 2^n");
-        std::memcpy(out, r->r.dist.data(), len * 8);
+        need(r->r.has_dist(), "result holds no distribution");
+        need(len == (1ull << r->r.n), "len must be 2^n");
+        r->r.dist_copy(out);
     });
 }
 
 int tusq_result_distribution_device(const tusq_result *r, void *dptr, void *hip_stream) {
     return guarded([&] {
         need(r && dptr, "NULL argument");
-        need(!r->r.dist.empty(), "result holds no distribution");
+        need(r->r.has_dist(), "result holds no distribution");
         const auto s = static_cast<hipStream_t>(hip_stream);
-        hip_check(hipMemcpyAsync(dptr, r->r.dist.data(), r->r.dist.size() * 8, hipMemcpyHostToDevice, s),
-                  "distribution to device");
+        const size_t bytes = (1ull << r->r.n) * 8;
+        if (r->r.dist.empty()) {
+            hip_check(hipSetDevice(r->r.device), "hipSetDevice");
+            hip_check(hipMemcpyAsync(dptr, r->r.dist_dev->p, bytes, hipMemcpyDeviceToDevice, s),
+                      "distribution to device");
+        } else {
+            hip_check(hipMemcpyAsync(dptr, r->r.dist.data(), bytes, hipMemcpyHostToDevice, s),
+                      "distribution to device");
+        }
         hip_check(hipStreamSynchronize(s), "sync");
     });
 }

@@ -69,6 +69,24 @@ void *scratch_address(int dev) {
 }
 }  // namespace
 
+void Result::dist_to_host() {
+    if (!dist_dev || !dist_dev->p) return;
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    dist.resize(1ull << n);
+    hip_check(hipMemcpy(dist.data(), dist_dev->p, dist.size() * 8, hipMemcpyDeviceToHost), "dist readback");
+    dist_dev.reset();
+}
+
+void Result::dist_copy(double *out) const {
+    if (!dist.empty()) {
+        std::memcpy(out, dist.data(), dist.size() * 8);
+        return;
+    }
+    if (!dist_dev || !dist_dev->p) fail(TUSQ_EINVAL, "result holds no distribution");
+    hip_check(hipSetDevice(device), "hipSetDevice");
+    hip_check(hipMemcpy(out, dist_dev->p, (1ull << n) * 8, hipMemcpyDeviceToHost), "dist readback");
+}
+
 uint64_t Workspace::bytes() const {
     uint64_t b = 0;
     for (const DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats,
@@ -343,9 +361,16 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
         ctx.recycle(evs);
     }
     res.n = n;
+    res.device = ctx.device;
     if (want_dist && !ws.device_outputs) {
-        res.dist.resize(N);
-        hip_check(hipMemcpy(res.dist.data(), acc.p, N * 8, hipMemcpyDeviceToHost), "dist readback");
+        // the accumulator becomes the result's: the distribution stays in
+        // device memory until the caller asks for it
+        res.dist.clear();
+        res.dist_dev = std::make_shared<DevBuf>();
+        res.dist_dev->p = acc.p;
+        res.dist_dev->bytes = acc.bytes;
+        acc.p = nullptr;
+        acc.bytes = 0;
     }
     if (want_samples && total_shots && !ws.device_outputs) {
         res.samples.resize(total_shots);

@@ -6,6 +6,7 @@
 #include <array>
 #include <atomic>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -45,10 +46,17 @@ struct Workspace {
 
 struct Result {
     uint32_t n = 0;
-    std::vector<double> dist;
+    std::vector<double> dist;  // the distribution on the host, or empty ...
+    std::shared_ptr<DevBuf> dist_dev;  // ... while it stays in device memory
+    int device = 0;
     std::vector<uint64_t> samples;
     std::vector<double> norms;
     tusq_counters counters{};
+    bool has_dist() const { return !dist.empty() || (dist_dev && dist_dev->p); }
+    // copy a device-resident distribution to the host and release it
+    void dist_to_host();
+    // write the 2^n probabilities to host memory
+    void dist_copy(double *out) const;
 };
 
 struct Serving;     // request loop state (serve.cpp)

@@ -527,9 +527,9 @@ __device__ __forceinline__ void pp_op2(const V (&x)[1 << R], V (&y)[1 << R],
 // the lanes with bit H set take a's place in b and the others b's place in
 // a, i.e. element (lane L, bit B = c) moves to (lane L with bit H = c, bit
 // B = bit H of L).  Lane bits 4 and 5 use the row / half swaps
-// (permlane16/32_swap); lane bits 0 .. 3 fetch the partner lane with a
-// data-parallel move (quad permutation, or a rotation inside the 16-lane
-// row) and select by the lane's bit.
+// (permlane16/32_swap); lane bits 2 and 3 a rotation inside the 16-lane row
+// written under a bank mask; lane bits 0 and 1 fetch the partner lane with
+// a quad permutation and select by the lane's bit.
 template <int H>
 __device__ __forceinline__ void lane_exchange(uint32_t a, uint32_t b, uint32_t &na, uint32_t &nb) {
     if constexpr (H == 5) {
@@ -540,11 +540,23 @@ __device__ __forceinline__ void lane_exchange(uint32_t a, uint32_t b, uint32_t &
         const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
         na = r[0];
         nb = r[1];
+    } else if constexpr (H >= 2) {
+        // lane bits 2 and 3 are the bank bits of a 16-lane row: the DPP bank
+        // mask writes only the lanes with bit H set (or clear), the others
+        // keep the old value -- one row rotation per output word (by 4 / 12
+        // for bit 2, by 8 for bit 3)
+        constexpr int up = H == 2 ? 0x124 : 0x128;
+        constexpr int dn = H == 2 ? 0x12C : 0x128;
+        constexpr int hi_banks = H == 2 ? 0xA : 0xC;
+        constexpr int lo_banks = H == 2 ? 0x5 : 0x3;
+        na = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(a), static_cast<int>(b), up,
+                                                               0xF, hi_banks, false));
+        nb = static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(b), static_cast<int>(a), dn,
+                                                               0xF, lo_banks, false));
     } else {
-        // partner of lane L is L ^ (1 << H): quad_perm [1,0,3,2] / [2,3,0,1],
-        // row rotations by 4 and 12 (bit 2 set / clear) and by 8
-        constexpr int up = H == 0 ? 0xB1 : H == 1 ? 0x4E : H == 2 ? 0x124 : 0x128;
-        constexpr int dn = H == 0 ? 0xB1 : H == 1 ? 0x4E : H == 2 ? 0x12C : 0x128;
+        // partner of lane L is L ^ (1 << H): quad_perm [1,0,3,2] / [2,3,0,1]
+        constexpr int up = H == 0 ? 0xB1 : 0x4E;
+        constexpr int dn = up;
         const bool hi = (__lane_id() >> H) & 1u;
         const uint32_t fb = static_cast<uint32_t>(
             __builtin_amdgcn_mov_dpp(static_cast<int>(b), up, 0xF, 0xF, false));
