@@ -49,7 +49,7 @@ def _args():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="brick26",
-                   choices=["brick26", "ising30", "batch", "serve", "mcm"])
+                   choices=["brick26", "brick8", "ising30", "batch", "serve", "mcm"])
     p.add_argument("--leaves-per-step", type=int, default=8)
     p.add_argument("--shots", type=int, default=1_000_000)
     p.add_argument("--qubits", type=int, default=26)
@@ -408,6 +408,106 @@ def bench_brick26(a, tq):
     return out
 
 
+def bench_brick8(a, tq):
+    """The 8-qubit configuration whole: random brickwork, 20 layers, the
+    paper's depolarising noise, 10^4 shots, pruned (alpha = 1/100, beta =
+    100) and lossless; every leaf, both precisions, distribution and
+    samples.  shots/s = S / (median of 5 runs of tusq_run_tree, tree built
+    beforehand; the host ECM time is reported beside it); the oracle walks
+    the same trees on one core (a 4 KiB state: threads only add overhead)."""
+    import statistics
+    import numpy as np
+    import oracle
+    from workloads import brickwork
+    circ = brickwork(8, 20, 1e-3, 1e-2, 1)
+    ec = tq.Circuit(circ)
+    S, seed = 10_000, 2
+    ctx = tq.Context(0)
+    out = {"metric": "noisy shots/sec, whole job, 8-qubit brickwork (state resident in LDS)",
+           "unit": "shots/s", "n_gpus": 1, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": "random brickwork n=8 L=20 p1=1e-3 p2=1e-2 S=10000, dftt, "
+                                  "pruned and lossless, whole job"}}
+    for prune in (True, False):
+        key = "pruned" if prune else "lossless"
+        base = dict(shots=S, seed=seed, prune=int(prune))
+        t0 = time.perf_counter()
+        tree = tq.Tree(ec, tq.tusq_opts_default(**base))
+        ecm_s = time.perf_counter() - t0
+        rec = {"leaves": tree.info()["n_leaves"], "host_ecm_s": round(ecm_s, 4)}
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        ot = oracle.ecm(circ, S, seed, prune=prune)
+        od, osamp, oc, _ = oracle.run(circ, ot, seed)
+        o_s = time.perf_counter() - t0
+        rec["cpu_oracle"] = {"value": round(S / o_s, 1), "unit": "shots/s", "cores": 1,
+                             "kind": "oracle", "seconds": round(o_s, 3),
+                             "sample": "the whole job: its error characterisation and plain "
+                                       "DFTT walk, complex128, one core"}
+        for prec in ("c128", "c64"):
+            o = tq.tusq_opts_default(**base, precision=prec, want=3)
+            tq.tusq_run_tree(ctx, ec, tree, o)   # warm-up
+            times = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                r = tq.tusq_run_tree(ctx, ec, tree, o)
+                d = r.distribution()
+                times.append(time.perf_counter() - t0)
+            med = statistics.median(times)
+            smp = r.samples()
+            diff = np.abs(d - od)
+            rec[prec] = {"shots_per_s": round(S / med, 1), "seconds": round(med, 5),
+                         "error_vs_oracle": {"max_abs": float(diff.max()),
+                                             "total_variation": float(0.5 * diff.sum()),
+                                             "samples_equal": int((smp == osamp).sum()),
+                                             "samples": int(len(osamp))}}
+            _log(f"[bench] brick8 {key} {prec}: {rec[prec]}")
+        out[key] = rec
+    out["value"] = out["pruned"]["c128"]["shots_per_s"]
+    return out
+
+
+GOLDEN_ISING30 = os.path.join(ROOT, "tests", "golden", "ising30_leaves_1_3.json")
+
+
+def ising30_error_vs_oracle(tq, ctx, ec, tree, b128, b64, drift_bound):
+    """Both precisions on leaves [1, 3) against the oracle's figures for them
+    (stored by tests/golden/make_ising30_golden.py, which runs only the
+    oracle: 30 one-qubit marginals, 4096 + 64 probabilities, every sample
+    with its small CDF margins)."""
+    import base64
+    import numpy as np
+    try:
+        with open(GOLDEN_ISING30) as f:
+            g = json.load(f)
+    except OSError:
+        return None
+    idx = np.frombuffer(base64.b64decode(g["index_u64_b64"]), "<u8").astype(np.int64)
+    prob = np.frombuffer(base64.b64decode(g["prob_f64_b64"]), "<f8")
+    samples = np.frombuffer(base64.b64decode(g["samples_u32_b64"]), "<u4").astype(np.uint64)
+    marg = np.array([float.fromhex(x) for x in g["marginals"]])
+    small = dict(zip(g["small_margin_positions"], (float.fromhex(x) for x in g["small_margins"])))
+    out = {"leaves": [g["workload"]["leaf_begin"], g["workload"]["leaf_end"]]}
+    for prec, base in (("c128", b128), ("c64", dict(b64, drift_bound=drift_bound))):
+        o = tq.tusq_opts_default(**base, precision=prec, leaf_begin=out["leaves"][0],
+                                 leaf_end=out["leaves"][1], want=3)
+        r = tq.tusq_run_tree(ctx, ec, tree, o)
+        d, smp, ct = r.distribution(), r.samples(), r.counters()
+        n = 30
+        m = np.array([d.reshape(1 << (n - q - 1), 2, 1 << q)[:, 1, :].sum() for q in range(n)])
+        pe = np.abs(d[idx] - prob)
+        bad = np.nonzero(smp != samples)[0]
+        out[prec] = {"probe_max_abs": float(pe.max()),
+                     "probe_max_rel_to_largest": float(pe.max() / prob.max()),
+                     "marginal_max_abs": float(np.abs(m - marg).max()),
+                     "samples_differing": int(len(bad)),
+                     "samples_differing_beyond_margin": int(sum(
+                         1 for p in bad if small.get(int(p), 1.0) >= 1e-11)),
+                     "samples": int(len(samples)), "recomputes": int(ct["recomputes"]),
+                     "max_norm_drift": float(ct["max_norm_drift"])}
+        del d, r
+    return out
+
+
 def bench_ising30(a, tq):
     import numpy as np
     from workloads import ising
@@ -444,7 +544,9 @@ def bench_ising30(a, tq):
                               "identical_samples": float((s64 == s128).mean())
                               if len(s64) else 1.0}}
     best = max(c64.values(), key=lambda v: v["shots_per_s"])
+    err_oracle = ising30_error_vs_oracle(tq, ctx, ec, tree, b128, b64, a.drift_bound)
     return {"metric": "noisy shots/sec, 30-qubit Trotter Ising, complex64 vs complex128",
+            "error_vs_oracle": err_oracle,
             "value": best["shots_per_s"], "unit": "shots/s", "n_gpus": 1,
             "dtype": "c64", "data": "synthetic",
             "config": {"workload": f"Ising n=30 steps=20 p1=5e-4 p2=5e-3 S={a.shots}, "
@@ -460,9 +562,10 @@ def bench_ising30(a, tq):
 
 def bench_batch(a, tq):
     """Config-3 jobs through tusq_run_batch: each call plans its jobs on host
-    threads and runs all their trajectories in one persistent, graph-captured
-    launch.  Jobs go in calls of --batch-chunk (one launch each) so that the
-    run reports progress; the device time is the sum over launches."""
+    threads and runs all their trajectories in persistent launches (one per
+    qubit count) captured in one graph.  Jobs go in calls of --batch-chunk
+    so that the run reports progress; the device time is the sum over
+    calls, the wall time the elapsed time of them all (two in flight)."""
     from workloads import batch_job_params, batch_jobs
     params = batch_job_params(a.batch_jobs)
     circs = batch_jobs(params)
@@ -490,26 +593,37 @@ def bench_batch(a, tq):
             sh, tuned = tq.tusq_batch_shape(ctx, n, prec)
             shapes[n] = {"threads": sh[0], "tile_qubits": sh[1], "low_qubits": sh[2],
                          "ops_per_sweep": sh[3], "tuned": tuned}
-        for c0 in range(0, len(ecs), a.batch_chunk):
+        # two calls in flight: one call's host planning overlaps the other's
+        # device work (the device part of tusq_run_batch runs one call at a
+        # time); wall = the elapsed time of all calls together
+        from concurrent.futures import ThreadPoolExecutor
+
+        def one(c0):
             chunk = ecs[c0:c0 + a.batch_chunk]
-            o = tq.tusq_opts_default(shots=10_000, seed=100_000, precision=prec,
+            # job j of the whole set keeps seed 100000 + j
+            o = tq.tusq_opts_default(shots=10_000, seed=100_000 + c0, precision=prec,
                                      traversal=a.traversal, want=2)
             t0 = time.perf_counter()
             res = tq.tusq_run_batch(ctx, chunk, o)
-            wall = time.perf_counter() - t0
-            ct = res[0].counters()
-            tot["wall"] += wall
-            tot["device"] += ct["device_seconds"]
-            tot["ecm"] += ct["host_ecm_seconds"]
-            tot["plan"] += ct["host_plan_seconds"]
-            tot["shots"] += sum(len(r.samples()) for r in res)
-            cts = [r.counters() for r in res]     # per job (times: the whole call)
-            tot["leaves"] += sum(int(c["leaves"]) for c in cts)
-            tot["passes"] += sum(int(c["passes_fwd"] + c["passes_inv"]) for c in cts)
-            tot["reused"] += int(ct["batch_graph_reused"])
-            _log(f"[bench] batch {prec} jobs [{c0},{c0 + len(chunk)}): wall {wall:.2f}s "
-                 f"device {ct['device_seconds']:.2f}s host ECM {ct['host_ecm_seconds']:.2f}s "
-                 f"plan {ct['host_plan_seconds']:.2f}s")
+            return c0, chunk, res, time.perf_counter() - t0
+
+        t_all = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=2) as ex:
+            calls = ex.map(one, range(0, len(ecs), a.batch_chunk))
+            for c0, chunk, res, wall in calls:
+                ct = res[0].counters()
+                tot["device"] += ct["device_seconds"]
+                tot["ecm"] += ct["host_ecm_seconds"]
+                tot["plan"] += ct["host_plan_seconds"]
+                tot["shots"] += sum(len(r.samples()) for r in res)
+                cts = [r.counters() for r in res]     # per job (times: the whole call)
+                tot["leaves"] += sum(int(c["leaves"]) for c in cts)
+                tot["passes"] += sum(int(c["passes_fwd"] + c["passes_inv"]) for c in cts)
+                tot["reused"] += int(ct["batch_graph_reused"])
+                _log(f"[bench] batch {prec} jobs [{c0},{c0 + len(chunk)}): call {wall:.2f}s "
+                     f"device {ct['device_seconds']:.2f}s host ECM {ct['host_ecm_seconds']:.2f}s "
+                     f"plan {ct['host_plan_seconds']:.2f}s")
+        tot["wall"] = time.perf_counter() - t_all
         out[prec] = {"wall_s": round(tot["wall"], 3), "device_s": round(tot["device"], 3),
                      "host_ecm_s": round(tot["ecm"], 3), "host_plan_s": round(tot["plan"], 3),
                      "leaves": tot["leaves"], "sweeps": tot["passes"],
@@ -666,7 +780,7 @@ def main():
                           "design note only", "n_gpus": a.gpus}))
         sys.exit(2)
     import paper_2508_04880_amd as tq
-    fn = {"brick26": bench_brick26, "ising30": bench_ising30, "batch": bench_batch,
+    fn = {"brick26": bench_brick26, "brick8": bench_brick8, "ising30": bench_ising30, "batch": bench_batch,
           "serve": bench_serve, "mcm": bench_mcm}[a.workload]
     print(json.dumps(fn(a, tq)), flush=True)
 

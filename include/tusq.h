@@ -21,7 +21,13 @@
  *     only read or written during the call, except for *_device variants,
  *     which enqueue work on the caller's HIP stream.
  *   - Bit order: bit q of a basis index or of a sampled bitstring is
- *     qubit q (little endian).  n_qubits <= 34 on one device.
+ *     qubit q (little endian).  Circuits take up to 34 qubits; a run needs
+ *     its state (2^n x 16 B complex128, 2^n x 8 B complex64 plus a 2^n x
+ *     16 B complex128 recompute state) and, with TUSQ_WANT_DIST, a 2^n x 8
+ *     B accumulator in the context's budget (TUSQ_ENOMEM otherwise).  On
+ *     one 288 GB device 33 qubits fit in either precision (complex128: 128
+ *     GiB state + 64 GiB distribution; complex64: 64 + 128 + 64 GiB), 34
+ *     do not; the largest run tested is 30 qubits.
  *   - Threading: circuits, trees and results may be used from any thread
  *     but not concurrently; a context is thread safe for
  *     tusq_submit / tusq_poll / tusq_wait / tusq_cancel.
@@ -265,13 +271,13 @@ int tusq_tree_get_info(const tusq_tree *t, tusq_tree_info *out);
  * (u32 slot, u32 qubit, u8 pauli).  With buf == NULL only *len_out is set. */
 int tusq_tree_serialize(const tusq_tree *t, uint8_t *buf, size_t cap, size_t *len_out);
 /* Raw (pre-commutation) events sorted by (shot, channel); cap = entries. */
+int tusq_tree_raw_events(const tusq_tree *t, uint32_t *shot, uint32_t *channel,
+                         uint8_t *outcome, uint64_t cap, uint64_t *n_out);
 /* SHA-256 (FIPS 180-4) of those raw events, in that order, each as 9 bytes:
  * u32 shot, u32 channel (little endian), u8 outcome -- a fingerprint of the
  * error-sampling stage (Sec. III-A.1) for comparing runs and
  * implementations without moving the list.  Writes 32 bytes.            */
 int tusq_raw_er_hash(const tusq_tree *t, uint8_t *sha256_out);
-int tusq_tree_raw_events(const tusq_tree *t, uint32_t *shot, uint32_t *channel,
-                         uint8_t *outcome, uint64_t cap, uint64_t *n_out);
 int tusq_tree_destroy(tusq_tree *t);
 /* Schedule and fuse without a device; fills the host-side counters a run
  * with these options would report (gate / Pauli applications, sweeps).     */
@@ -385,7 +391,8 @@ int tusq_job_times(tusq_ctx *ctx, uint64_t job_id, double *submitted, double *ad
  * and whose buffers fit replays it (counters.batch_graph_reused).  Job i
  * uses seed opts->seed + i; outs[i] receives its result.  complex64 jobs
  * have no recompute: counters.max_norm_drift reports each job's largest
- * |norm - 1|.                                                              */
+ * |norm - 1|.  Several threads may call it on one context: their host
+ * stages run concurrently, their device work one call at a time.         */
 int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *opts,
                    size_t n_jobs, tusq_result **outs);
 
