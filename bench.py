@@ -414,7 +414,9 @@ def bench_brick8(a, tq):
     100) and lossless; every leaf, both precisions, distribution and
     samples.  shots/s = S / (median of 5 runs of tusq_run_tree, tree built
     beforehand; the host ECM time is reported beside it); the oracle walks
-    the same trees on one core (a 4 KiB state: threads only add overhead)."""
+    the same trees on one core (a 4 KiB state: threads only add overhead).
+    Each precision also runs the job through tusq_run_batch, whose units
+    walk the leaves in parallel with the state in LDS."""
     import statistics
     import numpy as np
     import oracle
@@ -460,6 +462,25 @@ def bench_brick8(a, tq):
                                              "total_variation": float(0.5 * diff.sum()),
                                              "samples_equal": int((smp == osamp).sum()),
                                              "samples": int(len(osamp))}}
+            # the same job through the batched path: its leaves cut into
+            # units that walk in parallel, the state in LDS, one launch
+            # (the call includes its host error characterisation)
+            ob = tq.tusq_opts_default(**base, precision=prec, want=3)
+            tq.tusq_run_batch(ctx, [ec], ob)
+            times = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                rb = tq.tusq_run_batch(ctx, [ec], ob)[0]
+                db = rb.distribution()
+                times.append(time.perf_counter() - t0)
+            medb = statistics.median(times)
+            diffb = np.abs(db - od)
+            rec[prec]["batched_path"] = {
+                "shots_per_s": round(S / medb, 1), "seconds": round(medb, 5),
+                "device_seconds": round(rb.counters()["device_seconds"], 5),
+                "error_vs_oracle": {"max_abs": float(diffb.max()),
+                                    "total_variation": float(0.5 * diffb.sum()),
+                                    "samples_equal": int((rb.samples() == osamp).sum())}}
             _log(f"[bench] brick8 {key} {prec}: {rec[prec]}")
         out[key] = rec
     out["value"] = out["pruned"]["c128"]["shots_per_s"]
@@ -582,12 +603,12 @@ def bench_batch(a, tq):
                "passes": 0, "reused": 0}
         shapes = {}
         if not a.no_autotune:
-            # launch shapes per qubit count, timed on 2 jobs of each (cached
-            # in the context for every call below)
+            # launch shapes per qubit count, timed on the 4 jobs of each with
+            # the most gates (cached in the context for every call below)
             t0 = time.perf_counter()
             tq.tusq_batch_autotune(ctx, ecs, tq.tusq_opts_default(shots=10_000, seed=100_000,
                                                                   precision=prec,
-                                                                  traversal=a.traversal), 2)
+                                                                  traversal=a.traversal), 4)
             _log(f"[bench] batch autotune {prec}: {time.perf_counter() - t0:.1f}s")
         for n in sorted({c.n for c in circs}):
             sh, tuned = tq.tusq_batch_shape(ctx, n, prec)

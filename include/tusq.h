@@ -400,8 +400,9 @@ int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_o
  * not tuned yet in this context, time candidate launch shapes -- threads
  * per workgroup (256 / 512 / 1024), and for states kept in global memory
  * the tile qubits, the low qubits always in a tile and the dense ops per
- * sweep -- on up to probe_jobs of its jobs (at most 2000 shots each) and
- * keep the fastest; tusq_run_batch then uses it for jobs of that size.     */
+ * sweep -- on its probe_jobs jobs with the most gates (at most 2000 shots
+ * each), each shape timed twice, and keep the fastest if it beats the
+ * default shape by 3 %; tusq_run_batch then uses it for jobs of that size. */
 int tusq_batch_autotune(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *opts,
                         size_t n_jobs, uint32_t probe_jobs);
 /* The launch shape tusq_run_batch uses for n-qubit jobs at a precision:

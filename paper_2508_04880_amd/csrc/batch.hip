@@ -789,11 +789,19 @@ void batch_autotune(Ctx &ctx, const std::vector<const Circuit *> &circs, const t
                     uint32_t probe_jobs) {
     const bool c64 = o.precision == TUSQ_C64;
     if (o.precision != TUSQ_C64 && o.precision != TUSQ_C128) fail(TUSQ_EINVAL, "unknown precision");
+    // probes: the jobs with the most gates of each qubit count (they carry
+    // most of the work)
     std::map<uint32_t, std::vector<const Circuit *>> by_n;
     for (const Circuit *c : circs) {
         if (c->n > 16 || c->n < 1) fail(TUSQ_EUNSUPPORTED, "batched jobs need 1..16 qubits");
-        auto &v = by_n[c->n];
-        if (v.size() < std::max<uint32_t>(probe_jobs, 1)) v.push_back(c);
+        by_n[c->n].push_back(c);
+    }
+    for (auto &kv : by_n) {
+        auto &v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [](const Circuit *a, const Circuit *b) {
+            return a->gates.size() > b->gates.size();
+        });
+        v.resize(std::min<size_t>(v.size(), std::max<uint32_t>(probe_jobs, 1)));
     }
     tusq_opts po = o;
     po.shots = std::min<uint64_t>(o.shots, 2000);
@@ -815,17 +823,28 @@ void batch_autotune(Ctx &ctx, const std::vector<const Circuit *> &circs, const t
                     for (uint32_t ops : {16u, 32u}) cand.push_back(BatchShape{th, k, 5, ops});
             cand.push_back(BatchShape{1024, kt, 4, 32});
         }
-        double best = 1e300;
-        BatchShape pick = cand[0];
+        // each candidate timed twice (the faster run counts); the default
+        // shape is kept unless a candidate beats it by 3 %
+        auto timed = [&](const BatchShape &b) {
+            double t = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                std::vector<Result> out;
+                run_batch_shape(ctx, kv.second, po, out, &b);
+                if (!out.empty()) t = std::min(t, out[0].counters.device_seconds);
+            }
+            return t;
+        };
+        BatchShape pick = default_shape(n, c64);
+        const double t_default = timed(pick);
+        double best = t_default;
         for (const BatchShape &b : cand) {
-            std::vector<Result> out;
-            run_batch_shape(ctx, kv.second, po, out, &b);
-            const double t = out.empty() ? 1e300 : out[0].counters.device_seconds;
+            const double t = timed(b);
             if (t < best) {
                 best = t;
                 pick = b;
             }
         }
+        if (best > 0.97 * t_default) pick = default_shape(n, c64);
         std::lock_guard<std::mutex> g(ctx.mu);
         ctx.batch_tuned[shape_key(n, o.precision)] = pick;
     }

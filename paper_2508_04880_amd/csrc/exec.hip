@@ -240,8 +240,9 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
                 (sizeof(V) << p.k) <= 64 * 1024)
                 return launch_sweep_pipe<V>(st, n, a, prog, mat, pipe_grid, s);
             if (one_tile_per_wg) return launch_sweep_reg<V>(st, n, a, prog, mat, plan.reg_qubits, s);
-            return launch_sweep_pp<V>(st, n, a, prog, mat, plan.reg_qubits,
-                                      static_cast<uint32_t>(ctx.cus), s);
+            uint32_t cus = static_cast<uint32_t>(ctx.cus);
+            if (ws.co_running && ws.co_running->load(std::memory_order_relaxed) > 1) cus -= cus / 8;
+            return launch_sweep_pp<V>(st, n, a, prog, mat, plan.reg_qubits, cus, s);
         }
         return launch_sweep<V>(st, n, a, dop, mat, s);
     };

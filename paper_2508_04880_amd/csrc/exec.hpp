@@ -40,6 +40,10 @@ struct Workspace {
     // acc and samples are the caller's device buffers: the run leaves the
     // distribution and samples there and copies neither back to the host
     bool device_outputs = false;
+    // jobs running on the device now (serving lanes); while others run, a
+    // persistent sweep leaves an eighth of the CUs' workgroup slots free so
+    // that their kernels start without waiting for it
+    const std::atomic<uint32_t> *co_running = nullptr;
     uint64_t bytes() const;
     void release();
 };

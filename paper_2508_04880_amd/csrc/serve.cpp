@@ -7,10 +7,12 @@
 // skipping jobs whose device memory (state, complex128 recompute buffer,
 // FP64 accumulator, sampler scratch, samples, plan) does not fit what the
 // context budget has left; a job admitted while others run overlaps with
-// them on the device.  Jobs run their schedule in chunks and stop at a chunk
-// boundary when cancelled.  Every job owns its buffers and the kernels'
-// reductions have a fixed order, so a job's result is the same alone or in
-// any mix.
+// them on the device (while several run, a job's persistent sweeps leave an
+// eighth of the workgroup slots to the others, so that a small job's kernels
+// do not wait for a large job's sweeps).  Jobs run their schedule in chunks
+// and stop at a chunk boundary when cancelled.  Every job owns its buffers
+// and the kernels' reductions have a fixed order, so a job's result is the
+// same alone or in any mix.
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
@@ -52,6 +54,7 @@ struct Serving {
     std::map<uint64_t, std::shared_ptr<Job>> jobs;
     std::deque<std::shared_ptr<Job>> to_plan, ready;
     std::vector<uint64_t> lane_charge;
+    std::atomic<uint32_t> running{0};  // jobs on the device now
     uint64_t next_id = 1;
     bool stop = false;
     std::vector<std::thread> threads;
@@ -137,6 +140,7 @@ struct Serving {
             hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
             return;
         Workspace ws;
+        ws.co_running = &running;
         for (;;) {
             std::shared_ptr<Job> j;
             {
@@ -152,6 +156,7 @@ struct Serving {
                         j = *it;
                         ready.erase(it);
                         lane_charge[id] = std::max<uint64_t>(ws.bytes(), j->need);
+                        running.fetch_add(1);
                         j->state = JS_RUNNING;
                         j->t_admit = now_seconds();
                         break;
@@ -184,6 +189,7 @@ struct Serving {
                 msg = e.msg;
                 (void)hipStreamSynchronize(s);
             }
+            running.fetch_sub(1);
             {
                 std::lock_guard<std::mutex> g(mu);
                 lane_charge[id] = ws.bytes();
