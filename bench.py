@@ -80,6 +80,10 @@ def _args():
     p.add_argument("--serve-warmup", type=int, default=20,
                    help="serve: requests at the head of the stream left out of the statistics")
     p.add_argument("--serve-nmax", type=int, default=30)
+    p.add_argument("--serve-seed", type=int, default=4, help="serve: request stream seed")
+    p.add_argument("--serve-rate", type=float, default=0.0,
+                   help="serve: offered requests per second (0: load x the capacity measured "
+                        "from a burst of 16 requests)")
     p.add_argument("--serve-load", type=float, default=0.7)
     p.add_argument("--checkpoint-slots", type=int, default=0,
                    help="checkpoint traversal: most branch states kept (0 = no bound)")
@@ -662,24 +666,28 @@ def bench_serve(a, tq):
     import numpy as np
     from workloads import serving_requests
     ctx = tq.Context(0)
-    # capacity: a burst of requests from the same distribution submitted at
-    # once (they overlap on the lanes as in service), completions per second
-    warm = serving_requests(16, 1.0, seed=41, n_max=a.serve_nmax, shots_exp=(4.0, 6.0))
-    wc = [tq.Circuit(rq.circuit()) for rq in warm]
-    t0 = time.perf_counter()
-    wid = [tq.tusq_submit(ctx, c, tq.tusq_opts_default(shots=rq.shots, seed=rq.seed,
-                                                       precision=rq.precision, want=2))
-           for rq, c in zip(warm, wc)]
-    for j, rq in zip(wid, warm):
-        tq.tusq_wait(ctx, j, rq.n)
-    per = (time.perf_counter() - t0) / len(warm)
-    _log(f"[bench] serving burst of {len(warm)}: {per:.3f} s per request")
-    rate = a.serve_load / per
+    if a.serve_rate > 0:
+        rate, per = a.serve_rate, None
+    else:
+        # capacity: a burst of requests from the same distribution submitted
+        # at once (they overlap on the lanes as in service), completions per
+        # second
+        warm = serving_requests(16, 1.0, seed=41, n_max=a.serve_nmax, shots_exp=(4.0, 6.0))
+        wc = [tq.Circuit(rq.circuit()) for rq in warm]
+        t0 = time.perf_counter()
+        wid = [tq.tusq_submit(ctx, c, tq.tusq_opts_default(shots=rq.shots, seed=rq.seed,
+                                                           precision=rq.precision, want=2))
+               for rq, c in zip(warm, wc)]
+        for i, (j, rq) in enumerate(zip(wid, warm)):
+            tq.tusq_wait(ctx, j, rq.n)
+            _log(f"[bench] burst request {i} done at {time.perf_counter() - t0:.1f}s")
+        per = (time.perf_counter() - t0) / len(warm)
+        _log(f"[bench] serving burst of {len(warm)}: {per:.3f} s per request")
+        rate = a.serve_load / per
     W = a.serve_warmup
-    reqs = serving_requests(W + a.serve_count, rate, seed=4, n_max=a.serve_nmax,
+    reqs = serving_requests(W + a.serve_count, rate, seed=a.serve_seed, n_max=a.serve_nmax,
                             shots_exp=(4.0, 6.0))
-    _log(f"[bench] serving: capacity {1 / per:.2f} req/s, offered {rate:.2f} req/s, "
-         f"{W} warm-up + {a.serve_count} requests")
+    _log(f"[bench] serving: offered {rate:.3f} req/s, {W} warm-up + {a.serve_count} requests")
     prepared = [(rq, tq.Circuit(rq.circuit())) for rq in reqs]
     ids = [None] * len(reqs)
     start = time.perf_counter()
@@ -697,7 +705,7 @@ def bench_serve(a, tq):
 
     th = threading.Thread(target=producer)
     th.start()
-    lat, shots, mix = [], 0, {}
+    lat, shots, mix, records = [], 0, {}, []
     first_sub, last_fin = None, None
     for i, (rq, ec) in enumerate(prepared):
         while ids[i] is None:
@@ -710,6 +718,8 @@ def bench_serve(a, tq):
             continue
         shots += len(r.samples())
         lat.append(fin - sub)
+        records.append([rq.n, rq.precision, rq.shots, round(fin - sub, 4), round(adm - sub, 4),
+                        len(r.samples())])
         key = f"n{rq.n // 5 * 5}-{rq.n // 5 * 5 + 4}"
         mix.setdefault(key, []).append(fin - sub)
         first_sub = sub if first_sub is None else min(first_sub, sub)
@@ -722,12 +732,19 @@ def bench_serve(a, tq):
             "p50_s": round(float(np.percentile(lat, 50)), 4),
             "p99_s": round(float(np.percentile(lat, 99)), 4),
             "aggregate_shots_per_s": round(shots / (last_fin - first_sub), 1),
-            "offered_req_per_s": round(rate, 3), "capacity_req_per_s": round(1 / per, 3),
+            "offered_req_per_s": round(rate, 4),
+            "capacity_req_per_s": round(1 / per, 4) if per else None,
+            "span_s": round(last_fin - first_sub, 2), "shots": shots,
+            # per timed request: n, precision, shots, latency, queued, samples
+            "requests": records,
             "p50_by_qubits_s": {k: round(float(np.percentile(v, 50)), 4)
                                 for k, v in sorted(mix.items())},
             "config": {"workload": f"{a.serve_count} Poisson requests after {W} warm-up, "
                                    f"n log-uniform 12..{a.serve_nmax}, brickwork/Ising 50/50, "
-                                   f"S=10^U[4,6], c64/c128 50/50, load {a.serve_load}"}}
+                                   f"S=10^U[4,6], c64/c128 50/50, "
+                                   + (f"offered {rate:.4g} req/s" if a.serve_rate > 0
+                                      else f"load {a.serve_load}"),
+                       "seed": a.serve_seed}}
 
 
 def mcm_circuit(n, layers, every, width, seed):

@@ -817,9 +817,11 @@ void batch_autotune(Ctx &ctx, const std::vector<const Circuit *> &circs, const t
         if (n <= resident_max(c64)) {
             for (uint32_t th : {256u, 512u, 1024u}) cand.push_back(BatchShape{th, n, 0, 0});
         } else {
+            // tiles of 2^(kt-1) .. 2^(kt+1) amplitudes (the largest, 128 KiB,
+            // leaves room for one workgroup per CU)
             const uint32_t kt = tile_default(c64);
             for (uint32_t th : {256u, 1024u})
-                for (uint32_t k : {kt - 1, kt})
+                for (uint32_t k : {kt - 1, kt, kt + 1})
                     for (uint32_t ops : {16u, 32u}) cand.push_back(BatchShape{th, k, 5, ops});
             cand.push_back(BatchShape{1024, kt, 4, 32});
         }

@@ -22,7 +22,7 @@ void hip_check(hipError_t e, const char *what) {
 
 DevBuf::~DevBuf() { release(); }
 void DevBuf::release() {
-    if (p && owned) (void)hipFree(p);
+    if (p && owned) (void)(stream ? hipFreeAsync(p, stream) : hipFree(p));
     p = nullptr;
     bytes = 0;
     owned = true;
@@ -30,7 +30,7 @@ void DevBuf::release() {
 void DevBuf::alloc(size_t b) {
     release();
     if (!b) return;
-    hip_check(hipMalloc(&p, b), "hipMalloc");
+    hip_check(stream ? hipMallocAsync(&p, b, stream) : hipMalloc(&p, b), "hipMalloc");
     bytes = b;
 }
 void DevBuf::ensure(size_t b) {
@@ -69,14 +69,6 @@ void *scratch_address(int dev) {
 }
 }  // namespace
 
-void Result::dist_to_host() {
-    if (!dist_dev || !dist_dev->p) return;
-    hip_check(hipSetDevice(device), "hipSetDevice");
-    dist.resize(1ull << n);
-    hip_check(hipMemcpy(dist.data(), dist_dev->p, dist.size() * 8, hipMemcpyDeviceToHost), "dist readback");
-    dist_dev.reset();
-}
-
 void Result::dist_copy(double *out) const {
     if (!dist.empty()) {
         std::memcpy(out, dist.data(), dist.size() * 8);
@@ -93,6 +85,11 @@ uint64_t Workspace::bytes() const {
                             &mats128, &prog, &ckpt, &mcm})
         b += d->bytes;
     return b;
+}
+void Workspace::set_stream(hipStream_t s) {
+    for (DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats, &mats128,
+                      &prog, &ckpt, &mcm})
+        d->stream = s;
 }
 void Workspace::release() {
     for (DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats, &mats128,
@@ -363,7 +360,12 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     }
     res.n = n;
     res.device = ctx.device;
-    if (want_dist && !ws.device_outputs) {
+    if (want_dist && !ws.device_outputs && ws.co_running) {
+        // a serving lane keeps its buffers for the next job: the
+        // distribution goes to the host on the lane's own stream
+        res.dist.resize(N);
+        hip_check(hipMemcpyAsync(res.dist.data(), acc.p, N * 8, hipMemcpyDeviceToHost, s), "dist readback");
+    } else if (want_dist && !ws.device_outputs) {
         // the accumulator becomes the result's: the distribution stays in
         // device memory until the caller asks for it
         res.dist.clear();
@@ -375,12 +377,16 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     }
     if (want_samples && total_shots && !ws.device_outputs) {
         res.samples.resize(total_shots);
-        hip_check(hipMemcpy(res.samples.data(), samples.p, total_shots * 8, hipMemcpyDeviceToHost),
+        hip_check(hipMemcpyAsync(res.samples.data(), samples.p, total_shots * 8, hipMemcpyDeviceToHost, s),
                   "samples readback");
     }
     res.norms.resize(le - lb);
     if (le > lb)
-        hip_check(hipMemcpy(res.norms.data(), norms.p, (le - lb) * 8, hipMemcpyDeviceToHost), "norms readback");
+        hip_check(hipMemcpyAsync(res.norms.data(), norms.p, (le - lb) * 8, hipMemcpyDeviceToHost, s),
+                  "norms readback");
+    // readbacks on the job's own stream (a blocking copy would go through
+    // the null stream, behind other jobs' work)
+    hip_check(hipStreamSynchronize(s), "sync");
     for (double v : res.norms) ct.max_norm_drift = std::max(ct.max_norm_drift, std::fabs(v - 1.0));
 }
 

@@ -20,6 +20,10 @@ struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     bool owned = true;  // false: a view of memory owned elsewhere, never freed
+    // set: allocate and free in stream order on it (hipMallocAsync /
+    // hipFreeAsync), so that growing a buffer does not wait for work that
+    // other streams have queued, as hipFree does
+    hipStream_t stream = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -46,6 +50,7 @@ struct Workspace {
     const std::atomic<uint32_t> *co_running = nullptr;
     uint64_t bytes() const;
     void release();
+    void set_stream(hipStream_t s);  // every buffer allocates in order on s
 };
 
 struct Result {
@@ -57,8 +62,6 @@ struct Result {
     std::vector<double> norms;
     tusq_counters counters{};
     bool has_dist() const { return !dist.empty() || (dist_dev && dist_dev->p); }
-    // copy a device-resident distribution to the host and release it
-    void dist_to_host();
     // write the 2^n probabilities to host memory
     void dist_copy(double *out) const;
 };

@@ -141,6 +141,7 @@ struct Serving {
             return;
         Workspace ws;
         ws.co_running = &running;
+        ws.set_stream(s);
         for (;;) {
             std::shared_ptr<Job> j;
             {
@@ -178,9 +179,6 @@ struct Serving {
             std::string msg;
             try {
                 execute_plan(ctx, j->tree, j->plan, j->o, s, j->res, &ws, &j->cancel);
-                // finished jobs hold no device memory: admission counts
-                // running jobs only
-                j->res.dist_to_host();
                 j->res.counters.host_ecm_seconds = j->ecm_s;
                 j->res.counters.host_plan_seconds = j->plan_s;
             } catch (const Error &e) {
