@@ -3,16 +3,17 @@
 //
 // A submitted job first gets its host work (error characterisation and
 // plan) on a planner thread.  Execution lanes, each with its own HIP stream
-// and reusable device workspace, take planned jobs in arrival order,
-// skipping jobs whose device memory (state, complex128 recompute buffer,
-// FP64 accumulator, sampler scratch, samples, plan) does not fit what the
-// context budget has left; a job admitted while others run overlaps with
-// them on the device (while several run, a job's persistent sweeps leave an
-// eighth of the workgroup slots to the others, so that a small job's kernels
-// do not wait for a large job's sweeps).  Jobs run their schedule in chunks
-// and stop at a chunk boundary when cancelled.  Every job owns its buffers
-// and the kernels' reductions have a fixed order, so a job's result is the
-// same alone or in any mix.
+// and reusable device workspace (allocated in stream order), take planned
+// jobs in arrival order, skipping jobs whose device memory (state,
+// complex128 recompute buffer, FP64 accumulator, sampler scratch, samples,
+// plan) does not fit what the context budget has left; two of the four
+// lanes take jobs of at most 22 qubits only.  A job admitted while others
+// run overlaps with them on the device (while several run, a job's
+// persistent sweeps leave an eighth of the workgroup slots to the others,
+// so that a small job's kernels do not wait for a large job's sweeps).  Jobs
+// run their schedule in chunks and stop at a chunk boundary when cancelled.
+// Every job owns its buffers and the kernels' reductions have a fixed
+// order, so a job's result is the same alone or in any mix.
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
@@ -29,6 +30,10 @@ namespace {
 enum : int { JS_QUEUED = 0, JS_RUNNING = 1, JS_DONE = 2, JS_FAILED = 3, JS_CANCELLED = 4 };
 constexpr unsigned N_LANES = 4;     // one per hardware queue of the device
 constexpr unsigned N_PLANNERS = 2;  // host threads for the ECM and planning
+// the last lanes take small jobs only, so that a small request never waits
+// behind large ones that hold every lane (a 30-qubit job runs for a minute)
+constexpr unsigned N_SMALL_LANES = 2;
+constexpr uint32_t SMALL_LANE_MAX_QUBITS = 22;
 }  // namespace
 
 struct Job {
@@ -149,8 +154,11 @@ struct Serving {
                 for (;;) {
                     if (stop) break;
                     // first planned job, in arrival order, that fits the budget
+                    // (and, on a small-job lane, is small)
                     const uint64_t others = used() - lane_charge[id];
+                    const bool small_only = id >= N_LANES - N_SMALL_LANES;
                     auto it = std::find_if(ready.begin(), ready.end(), [&](const std::shared_ptr<Job> &x) {
+                        if (small_only && x->c.n > SMALL_LANE_MAX_QUBITS) return false;
                         return others + std::max<uint64_t>(ws.bytes(), x->need) <= ctx.budget;
                     });
                     if (it != ready.end()) {

@@ -100,38 +100,43 @@ def test_cancel_queued_job():
     ctx.close()
 
 
-def test_short_jobs_overlap_a_long_one():
-    """Continuous batching: a long job is admitted first; short jobs that
-    arrive while it runs are admitted on the other lanes and finish before
-    it does (their device work overlaps it), and every result equals the
-    same job run alone, bit for bit."""
+def test_short_jobs_overlap_long_ones():
+    """Continuous batching: two long jobs (24 qubits) are admitted first and
+    hold both lanes that take large jobs; short jobs that arrive while they
+    run are admitted on the lanes kept for small jobs and finish before the
+    long ones do (their device work overlaps them), and every result equals
+    the same job run alone, bit for bit."""
     _say("[gpu] serving overlap")
     ctx = tq.Context(0)
-    long_c = brickwork(24, 40, 1e-3, 1e-2, 60)
-    long_o = tq.tusq_opts_default(shots=20_000, seed=61, leaf_end=600)
+    long_c = [brickwork(24, 40, 1e-3, 1e-2, 60 + i) for i in range(2)]
+    long_o = [tq.tusq_opts_default(shots=20_000, seed=61 + i, leaf_end=300) for i in range(2)]
     shorts = [(brickwork(10 + i, 10, 1e-3, 1e-2, 70 + i), "c128" if i % 2 else "c64", 5000)
               for i in range(6)]
-    lec = tq.Circuit(long_c)
+    lec = [tq.Circuit(c) for c in long_c]
     sec = [tq.Circuit(c) for c, _, _ in shorts]
     sopt = [tq.tusq_opts_default(shots=S, seed=80 + i, precision=p)
             for i, (_, p, S) in enumerate(shorts)]
-    lid = tq.tusq_submit(ctx, lec, long_o)
-    while tq.tusq_poll(ctx, lid) == 0:     # wait until the long job runs
-        time.sleep(0.005)
+    lids = [tq.tusq_submit(ctx, ec, o) for ec, o in zip(lec, long_o)]
+    for lid in lids:                      # wait until both long jobs run
+        while tq.tusq_poll(ctx, lid) == 0:
+            time.sleep(0.005)
     sids = [tq.tusq_submit(ctx, ec, o) for ec, o in zip(sec, sopt)]
     sres = [tq.tusq_wait(ctx, j, c.n) for j, (c, _, _) in zip(sids, shorts)]
-    lres = tq.tusq_wait(ctx, lid, long_c.n)
-    _, l_adm, l_fin = tq.tusq_job_times(ctx, lid)
+    lres = [tq.tusq_wait(ctx, lid, 24) for lid in lids]
+    l_times = [tq.tusq_job_times(ctx, lid) for lid in lids]
+    l_adm = max(t[1] for t in l_times)
+    l_fin = min(t[2] for t in l_times)
     for j in sids:
         sub, adm, fin = tq.tusq_job_times(ctx, j)
-        _say(f"[gpu]   short job: admitted {adm - l_adm:.3f}s after the long one, finished "
-             f"{l_fin - fin:.3f}s before it")
+        _say(f"[gpu]   short job: admitted {adm - sub:.3f}s after submission, finished "
+             f"{l_fin - fin:.3f}s before the first long job")
         assert l_adm <= sub and adm < l_fin and fin < l_fin
     for ec, o, r in zip(sec, sopt, sres):
         alone = tq.tusq_run(ctx, ec, o)
         assert same_bits(r.distribution(), alone.distribution())
         assert same_bits(r.samples(), alone.samples())
-    alone = tq.tusq_run(ctx, lec, long_o)
-    assert same_bits(lres.distribution(), alone.distribution())
-    assert same_bits(lres.samples(), alone.samples())
+    for ec, o, r in zip(lec, long_o, lres):
+        alone = tq.tusq_run(ctx, ec, o)
+        assert same_bits(r.distribution(), alone.distribution())
+        assert same_bits(r.samples(), alone.samples())
     ctx.close()
