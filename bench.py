@@ -39,7 +39,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
-KERNEL_SRC = os.path.join(ROOT, "paper_2508_04880_amd", "csrc", "kernels.hip")
+# the sweep kernel's source: kernels.hip and the device helpers it includes
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2508_04880_amd", "csrc", f)
+               for f in ("kernels.hip", "regops.hpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_pp_brickwork26_traffic.txt")
 
 
@@ -235,9 +237,12 @@ def measured_traffic(kernel):
                 if "=" in line and not line.startswith("#"):
                     k, v = line.strip().split("=", 1)
                     kv[k.strip()] = v.strip()
-        with open(KERNEL_SRC, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()[:16]
-        if kv.get("kernels_hip_sha256_16") != sha or kv.get("kernel") != kernel:
+        h = hashlib.sha256()
+        for path in KERNEL_SRCS:
+            with open(path, "rb") as f:
+                h.update(f.read())
+        sha = h.hexdigest()[:16]
+        if kv.get("kernel_src_sha256_16") != sha or kv.get("kernel") != kernel:
             return None
         fetch = float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) * 1024
         write = float(kv["write_kib_per_launch"]) * float(kv["write_scale"]) * 1024
@@ -617,7 +622,7 @@ def bench_batch(a, tq):
         for n in sorted({c.n for c in circs}):
             sh, tuned = tq.tusq_batch_shape(ctx, n, prec)
             shapes[n] = {"threads": sh[0], "tile_qubits": sh[1], "low_qubits": sh[2],
-                         "ops_per_sweep": sh[3], "tuned": tuned}
+                         "ops_per_sweep": sh[3], "register_programs": sh[4], "tuned": tuned}
         # two calls in flight: one call's host planning overlaps the other's
         # device work (the device part of tusq_run_batch runs one call at a
         # time); wall = the elapsed time of all calls together

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define TUSQ_ABI_VERSION 9u
+#define TUSQ_ABI_VERSION 10u
 
 /* status codes */
 #define TUSQ_OK 0
@@ -400,16 +400,21 @@ int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_o
  * not tuned yet in this context, time candidate launch shapes -- threads
  * per workgroup (256 / 512 / 1024), and for states kept in global memory
  * the tile qubits, the low qubits always in a tile and the dense ops per
- * sweep -- on its probe_jobs jobs with the most gates (at most 2000 shots
+ * sweep, op lists in LDS or register-blocked programs -- on its
+ * probe_jobs jobs with the most gates (at most 2000 shots
  * each), each shape timed twice, and keep the fastest if it beats the
- * default shape by 3 %; tusq_run_batch then uses it for jobs of that size. */
+ * default shape by 3 %; tusq_run_batch then uses it for jobs of that size.
+ * With the environment variable TUSQ_TUNE_LOG set, each shape's time goes
+ * to stderr. */
 int tusq_batch_autotune(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_opts *opts,
                         size_t n_jobs, uint32_t probe_jobs);
 /* The launch shape tusq_run_batch uses for n-qubit jobs at a precision:
  * shape[0] threads per workgroup, [1] tile qubits (n itself when the state
  * stays in LDS), [2] low qubits, [3] dense ops per sweep (0 = the planner's
- * default); returns 1 in *tuned when it came from the autotuner.          */
-int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint32_t shape[4],
+ * default), [4] 1 when states in global slots are swept by register-blocked
+ * programs (16 amplitudes per thread), 0 by op lists in LDS; returns 1 in
+ * *tuned when it came from the autotuner.                                  */
+int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint32_t shape[5],
                      int *tuned);
 
 /* ---- results --------------------------------------------------------------- */

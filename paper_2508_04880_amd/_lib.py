@@ -126,7 +126,7 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 # struct layouts below follow this version of include/tusq.h
-ABI_VERSION = 9
+ABI_VERSION = 10
 if lib.tusq_abi_version() != ABI_VERSION:
     raise ImportError(f"{LIB_PATH} has ABI version {lib.tusq_abi_version()}, the binding "
                       f"expects {ABI_VERSION}: rebuild the library")
@@ -450,10 +450,10 @@ def tusq_batch_autotune(ctx: Context, circuits, opts: tusq_opts, probe_jobs: int
 
 
 def tusq_batch_shape(ctx: Context, n: int, precision) -> tuple:
-    """(threads, tile qubits, low qubits, ops per sweep), tuned?"""
+    """(threads, tile qubits, low qubits, ops per sweep, register programs), tuned?"""
     if isinstance(precision, str):
         precision = PRECISIONS[precision]
-    out = (C.c_uint32 * 4)()
+    out = (C.c_uint32 * 5)()
     tuned = C.c_int()
     check(lib.tusq_batch_shape(ctx.h, C.c_uint32(n), C.c_uint32(precision), out, C.byref(tuned)))
     return tuple(out), bool(tuned.value)

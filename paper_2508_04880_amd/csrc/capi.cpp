@@ -692,7 +692,7 @@ int tusq_batch_autotune(tusq_ctx *ctx, const tusq_circuit *const *circs, const t
     });
 }
 
-int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint32_t shape[4],
+int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint32_t shape[5],
                      int *tuned) {
     return guarded([&] {
         need(ctx && shape, "NULL argument");
@@ -704,6 +704,7 @@ int tusq_batch_shape(tusq_ctx *ctx, uint32_t n_qubits, uint32_t precision, uint3
         shape[1] = b.tile_qubits;
         shape[2] = b.low_qubits;
         shape[3] = b.max_ops;
+        shape[4] = b.reg;
         if (tuned) *tuned = t ? 1 : 0;
     });
 }

@@ -253,9 +253,30 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     uint64_t sample_off = 0;
     std::vector<double> hnorm(1);
 
+    // queued-work windows of a serving lane: each step counts 2^n amplitudes
+    // of work; at the end of a window the host waits for the one before it
+    // (about 35 ms of 30-qubit sweeps)
+    constexpr uint64_t WINDOW_AMPS = 1ull << 31;
+    const bool windows = ws.window[0] && ws.window[1];
+    uint64_t window_work = 0;
+    bool window_pending[2] = {false, false};
+    unsigned window_cur = 0;
+    auto end_window = [&] {
+        const unsigned prev = window_cur ^ 1u;
+        if (window_pending[prev]) hip_check(hipEventSynchronize(ws.window[prev]), "window");
+        window_pending[prev] = false;
+        hip_check(hipEventRecord(ws.window[window_cur], s), "window");
+        window_pending[window_cur] = true;
+        window_cur = prev;
+    };
+
     const double t0 = now_seconds();
     hip_check(hipStreamSynchronize(s), "sync");
     for (size_t si = 0; si < plan.steps.size(); ++si) {
+        if (windows && (window_work += N) >= WINDOW_AMPS) {
+            window_work = 0;
+            end_window();
+        }
         if (o.debug_fail_at_step >= 0 && static_cast<size_t>(o.debug_fail_at_step) == si)
             fail(TUSQ_EDEVICE, "injected failure at schedule step " + std::to_string(si));
         // chunk boundary: a cancelled job stops here (work already queued on

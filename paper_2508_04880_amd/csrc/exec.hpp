@@ -48,6 +48,11 @@ struct Workspace {
     // persistent sweep leaves an eighth of the CUs' workgroup slots free so
     // that their kernels start without waiting for it
     const std::atomic<uint32_t> *co_running = nullptr;
+    // serving lanes: two events with which a run keeps at most two windows
+    // of work queued ahead on its stream, so that each launch sees how many
+    // jobs run at its own time and a small job's kernels never queue behind
+    // seconds of a large job's sweeps
+    hipEvent_t window[2] = {nullptr, nullptr};
     uint64_t bytes() const;
     void release();
     void set_stream(hipStream_t s);  // every buffer allocates in order on s
@@ -72,9 +77,11 @@ void batch_cache_free(BatchCache *b);
 
 // Launch shape of batched jobs of one qubit count: threads per workgroup,
 // tile qubits (the qubit count itself when the state stays in LDS), low
-// qubits always in a tile, dense ops per sweep (0 = the planner's default).
+// qubits always in a tile, dense ops per sweep (0 = the planner's default),
+// and for states in global slots whether the sweeps run register-blocked
+// programs (threads = 2^(tile qubits - 4)) or op lists in LDS.
 struct BatchShape {
-    uint32_t threads = 256, tile_qubits = 0, low_qubits = 0, max_ops = 0;
+    uint32_t threads = 256, tile_qubits = 0, low_qubits = 0, max_ops = 0, reg = 0;
 };
 
 struct Ctx {

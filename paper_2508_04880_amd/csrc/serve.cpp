@@ -8,9 +8,10 @@
 // complex128 recompute buffer, FP64 accumulator, sampler scratch, samples,
 // plan) does not fit what the context budget has left; two of the four
 // lanes take jobs of at most 22 qubits only.  A job admitted while others
-// run overlaps with them on the device (while several run, a job's
-// persistent sweeps leave an eighth of the workgroup slots to the others,
-// so that a small job's kernels do not wait for a large job's sweeps).  Jobs
+// run overlaps with them on the device: every lane keeps at most two
+// windows of work queued ahead, and while several jobs run its persistent
+// sweeps leave an eighth of the workgroup slots to the others, so that a
+// small job's kernels do not wait for a large job's sweeps.  Jobs
 // run their schedule in chunks and stop at a chunk boundary when cancelled.
 // Every job owns its buffers and the kernels' reductions have a fixed
 // order, so a job's result is the same alone or in any mix.
@@ -147,6 +148,9 @@ struct Serving {
         Workspace ws;
         ws.co_running = &running;
         ws.set_stream(s);
+        for (hipEvent_t &e : ws.window)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventBlockingSync) != hipSuccess)
+                e = nullptr;
         for (;;) {
             std::shared_ptr<Job> j;
             {
@@ -170,8 +174,14 @@ struct Serving {
                         j->t_admit = now_seconds();
                         break;
                     }
-                    // nothing fits: give back this lane's cached buffers
-                    if (!ready.empty() && ws.bytes()) {
+                    // nothing fits: give back this lane's cached buffers if
+                    // a job this lane may take waits for memory (a small-job
+                    // lane keeps them while only large jobs wait)
+                    const bool eligible_waits =
+                        std::any_of(ready.begin(), ready.end(), [&](const std::shared_ptr<Job> &x) {
+                            return !small_only || x->c.n <= SMALL_LANE_MAX_QUBITS;
+                        });
+                    if (eligible_waits && ws.bytes()) {
                         g.unlock();
                         ws.release();
                         g.lock();
@@ -203,6 +213,8 @@ struct Serving {
             finish(j, state, code, msg);
         }
         ws.release();
+        for (hipEvent_t e : ws.window)
+            if (e) (void)hipEventDestroy(e);
         (void)hipStreamDestroy(s);
     }
 };

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(tq.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
-    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 9
+    assert tq.lib.tusq_abi_version() == tq.ABI_VERSION == 10
 
 
 def test_product_binding_has_no_oracle_dependency():

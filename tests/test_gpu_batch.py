@@ -119,13 +119,16 @@ def test_batch_autotuned_shapes_match_oracle(ctx, precision):
     tq.tusq_batch_autotune(ctx, ecs, o, 2)
     kl = 14 if precision == "c64" else 13
     for c in circs:
-        (th, tile, low, ops), tuned = tq.tusq_batch_shape(ctx, c.n, precision)
+        (th, tile, low, ops, reg), tuned = tq.tusq_batch_shape(ctx, c.n, precision)
         assert tuned and th in (256, 512, 1024)
         if c.n <= kl:
-            assert tile == c.n and low == 0
+            assert tile == c.n and low == 0 and reg == 0
+        elif reg:
+            assert tile in (12, 13) and th == 1 << (tile - 4) and low in (4, 5) and ops in (0, 16)
         else:
             assert tile in (kl - 2, kl - 1, kl) and low in (4, 5) and ops in (0, 16, 32)
-        _say(f"[gpu]   n={c.n}: threads {th}, tile {tile}, low {low}, ops {ops}")
+        _say(f"[gpu]   n={c.n}: threads {th}, tile {tile}, low {low}, ops {ops}, "
+             f"register programs {reg}")
     res = tq.tusq_run_batch(ctx, ecs, o)
     worst, worst_tv, drift = 0.0, 0.0, 0.0
     for j, (c, r) in enumerate(zip(circs, res)):
