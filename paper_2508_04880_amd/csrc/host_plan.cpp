@@ -52,12 +52,19 @@ uint64_t shared_depth(uint32_t G, const Ev *a, uint64_t na, const Ev *b, uint64_
 using M2 = std::array<cd, 4>;
 using M4 = std::array<cd, 16>;
 
+// complex product written out: the same two products and sum as the
+// library's operator for finite operands, without its NaN/infinity recovery
+// call (the matrices here are finite)
+inline cd cm(const cd &a, const cd &b) {
+    return cd(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+
 M4 kron(const M2 &a, const M2 &b) {
     M4 r;
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int k = 0; k < 2; ++k)
-                for (int l = 0; l < 2; ++l) r[(2 * i + k) * 4 + (2 * j + l)] = a[2 * i + j] * b[2 * k + l];
+                for (int l = 0; l < 2; ++l) r[(2 * i + k) * 4 + (2 * j + l)] = cm(a[2 * i + j], b[2 * k + l]);
     return r;
 }
 M4 mul4(const M4 &a, const M4 &b) {
@@ -65,16 +72,42 @@ M4 mul4(const M4 &a, const M4 &b) {
     for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
             cd s = 0.0;
-            for (int k = 0; k < 4; ++k) s += a[4 * i + k] * b[4 * k + j];
+            for (int k = 0; k < 4; ++k) s += cm(a[4 * i + k], b[4 * k + j]);
             r[4 * i + j] = s;
         }
     return r;
 }
 M2 mul2(const M2 &a, const M2 &b) {
-    return M2{a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3], a[2] * b[0] + a[3] * b[2],
-              a[2] * b[1] + a[3] * b[3]};
+    return M2{cm(a[0], b[0]) + cm(a[1], b[2]), cm(a[0], b[1]) + cm(a[1], b[3]),
+              cm(a[2], b[0]) + cm(a[3], b[2]), cm(a[2], b[1]) + cm(a[3], b[3])};
 }
 const M2 I2m{1.0, 0.0, 0.0, 1.0};
+
+// Products with a Kronecker factor, the terms of mul4 that are not zero
+// (same operands, same order of summation): (A (x) I) M, (I (x) A) M and
+// G (A (x) B).  Basis index 2 * high + low; the first Kronecker factor acts
+// on the high bit.
+M4 mul_hi(const M2 &a, const M4 &m) {  // (A (x) I) M
+    M4 r;
+    for (int i = 0; i < 2; ++i)
+        for (int s = 0; s < 2; ++s)
+            for (int c = 0; c < 4; ++c)
+                r[4 * (2 * i + s) + c] = cm(a[2 * i], m[4 * s + c]) + cm(a[2 * i + 1], m[4 * (2 + s) + c]);
+    return r;
+}
+M4 mul_lo(const M2 &a, const M4 &m) {  // (I (x) A) M
+    M4 r;
+    for (int h = 0; h < 2; ++h)
+        for (int i = 0; i < 2; ++i)
+            for (int c = 0; c < 4; ++c)
+                r[4 * (2 * h + i) + c] = cm(a[2 * i], m[4 * (2 * h) + c]) + cm(a[2 * i + 1], m[4 * (2 * h + 1) + c]);
+    return r;
+}
+bool is_identity(const M2 &a) { return a[0] == 1.0 && a[1] == 0.0 && a[2] == 0.0 && a[3] == 1.0; }
+M4 mul_kron(const M4 &g, const M2 &a, const M2 &b) {  // G (A (x) B)
+    if (is_identity(a) && is_identity(b)) return g;
+    return mul4(g, kron(a, b));
+}
 M4 cx_matrix() {  // basis index 2 * control + target
     M4 r{};
     r[0 * 4 + 0] = 1.0;
@@ -83,6 +116,7 @@ M4 cx_matrix() {  // basis index 2 * control + target
     r[3 * 4 + 2] = 1.0;
     return r;
 }
+const M4 CX_MATRIX = cx_matrix();
 M4 swap_halves(const M4 &m) {  // same operator written for the qubit pair in the other order
     static const int p[4] = {0, 2, 1, 3};
     M4 r;
@@ -410,9 +444,15 @@ struct Fuser {
     // earlier op of identical (bitwise) matrix
     uint32_t pool(const cd *m, int d) {
         const size_t nb = sizeof(cd) * d * d;
-        uint64_t h = 1469598103934665603ull;  // FNV-1a over the bytes
-        const unsigned char *b = reinterpret_cast<const unsigned char *>(m);
-        for (size_t i = 0; i < nb; ++i) h = (h ^ b[i]) * 1099511628211ull;
+        // hash of the 64-bit words (equal matrices are then told apart
+        // from colliding ones by comparing the bytes)
+        uint64_t h = 0x9E3779B97F4A7C15ull * static_cast<uint64_t>(d);
+        for (size_t i = 0; i < nb / 8; ++i) {
+            uint64_t w;
+            std::memcpy(&w, reinterpret_cast<const unsigned char *>(m) + 8 * i, 8);
+            h = (h ^ w) * 0xff51afd7ed558ccdull;
+            h ^= h >> 29;
+        }
         auto range = plan.mat_index.equal_range(h);
         for (auto it = range.first; it != range.second; ++it)
             if (it->second.second == d && std::memcmp(plan.mats.data() + it->second.first, m, nb) == 0)
@@ -432,7 +472,8 @@ struct Fuser {
         bool two;
         bool is_gate;
         M2 m2;            // 1-qubit matrix (gate or Pauli)
-        M4 m4;            // 2-qubit gate, basis index 2 * bit(qa) + bit(qb)
+        const cd *m4;     // 2-qubit gate's 16 entries, row-major, basis index
+                          // 2 * bit(qa) + bit(qb): the circuit's or CX_MATRIX
     };
 
     // Tokens one sweep would take from `rest` if its tile started as the
@@ -441,12 +482,21 @@ struct Fuser {
     // max_qubits or the sweep holds max_ops dense ops; a token not taken
     // blocks its qubits), without building matrices.  Stops early once
     // nothing more can be taken.
+    // scratch of fuse and dry_run, reused from call to call
+    std::vector<BuildOp> f_ops;
+    std::vector<uint32_t> f_keep;
+    std::vector<uint8_t> dr_inq, dr_blocked, dr_one;
+    std::vector<int> dr_last;
     uint32_t dry_run(const std::vector<Item> &items, const std::vector<uint32_t> &rest,
                      const std::vector<uint8_t> &init, uint32_t nq0) {
         const uint32_t n = c.n;
-        std::vector<uint8_t> inq(init), blocked(n, 0);
-        std::vector<int> last(n, -1);
-        std::vector<uint8_t> one;  // per live-or-dead op: 1-qubit?
+        std::vector<uint8_t> &inq = dr_inq, &blocked = dr_blocked;
+        std::vector<int> &last = dr_last;
+        std::vector<uint8_t> &one = dr_one;  // per live-or-dead op: 1-qubit?
+        inq.assign(init.begin(), init.end());
+        blocked.assign(n, 0);
+        last.assign(n, -1);
+        one.clear();
         uint32_t nq = nq0, live = 0, taken = 0, nblk_in = 0;
         for (uint32_t idx : rest) {
             const Item &it = items[idx];
@@ -500,8 +550,10 @@ struct Fuser {
         const uint32_t low = std::min(fp.low_qubits, n);
         std::vector<int> last(n, -1);
         std::vector<uint8_t> inq(n, 0), blocked(n, 0), cand(n, 0);
+        std::vector<BuildOp> &ops = f_ops;
+        std::vector<uint32_t> &keep = f_keep;
         while (!rest.empty()) {
-            std::vector<BuildOp> ops;
+            ops.clear();
             std::fill(last.begin(), last.end(), -1);
             std::fill(inq.begin(), inq.end(), 0);
             std::fill(blocked.begin(), blocked.end(), 0);
@@ -534,7 +586,7 @@ struct Fuser {
                 }
             }
             uint32_t live = 0, gates = 0, paulis = 0;
-            std::vector<uint32_t> keep;
+            keep.clear();
             bool full = false;
             for (uint32_t idx : rest) {
                 const Item &it = items[idx];
@@ -558,8 +610,8 @@ struct Fuser {
                     if (l >= 0) {
                         BuildOp &o = ops[l];
                         if (o.qb == NONE) o.m2 = mul2(it.m2, o.m2);
-                        else if (o.qa == it.qa) o.m4 = mul4(kron(it.m2, I2m), o.m4);
-                        else o.m4 = mul4(kron(I2m, it.m2), o.m4);
+                        else if (o.qa == it.qa) o.m4 = mul_hi(it.m2, o.m4);
+                        else o.m4 = mul_lo(it.m2, o.m4);
                     } else {
                         ops.push_back(BuildOp{it.qa, NONE, true, it.m2, {}});
                         last[it.qa] = static_cast<int>(ops.size()) - 1;
@@ -567,7 +619,8 @@ struct Fuser {
                     }
                 } else {
                     const int la = last[it.qa], lb = last[it.qb];
-                    const M4 &g = it.m4;
+                    M4 g;
+                    std::copy(it.m4, it.m4 + 16, g.begin());
                     if (la >= 0 && la == lb) {
                         BuildOp &o = ops[la];
                         o.m4 = mul4(o.qa == it.qa ? g : swap_halves(g), o.m4);
@@ -575,7 +628,7 @@ struct Fuser {
                         M2 a = I2m, b = I2m;
                         if (la >= 0 && ops[la].qb == NONE) { a = ops[la].m2; ops[la].live = false; --live; }
                         if (lb >= 0 && ops[lb].qb == NONE) { b = ops[lb].m2; ops[lb].live = false; --live; }
-                        ops.push_back(BuildOp{it.qa, it.qb, true, {}, mul4(g, kron(a, b))});
+                        ops.push_back(BuildOp{it.qa, it.qb, true, {}, mul_kron(g, a, b)});
                         last[it.qa] = last[it.qb] = static_cast<int>(ops.size()) - 1;
                         ++live;
                     }
@@ -637,10 +690,7 @@ void token_items(const Circuit &c, const Ev *ev, const std::vector<Tok> &toks, u
             if (is_two_qubit(g.kind)) {
                 it.two = true;
                 it.qb = g.q[1];
-                if (g.kind == TUSQ_UNITARY2)
-                    std::copy(c.umats.begin() + g.umat, c.umats.begin() + g.umat + 16, it.m4.begin());
-                else
-                    it.m4 = cx_matrix();
+                it.m4 = g.kind == TUSQ_UNITARY2 ? c.umats.data() + g.umat : CX_MATRIX.data();
                 ops += 4;
             } else {
                 it.two = false;
