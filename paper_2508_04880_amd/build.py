@@ -29,6 +29,11 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # pointer phis and move it to scratch memory
              "-mllvm", "-simplifycfg-sink-common=false",
              "-Wall", "-Wno-unused-result"]
+# per-source additions: the sweep kernels' program dispatch branches on
+# wave-uniform instruction words only, so its control flow needs no
+# structurizing; structurized, every lane exchange (an in-place permlane /
+# DPP swap) first copied the whole register tile
+HIP_SOURCE_FLAGS = {"kernels.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
              # complex products by the plain formula: the same values for
              # finite operands, without a library call per product
@@ -49,7 +54,7 @@ def build(verbose: bool = False) -> str:
     jobs = []
     for s in HIP_SOURCES:
         if os.path.exists(os.path.join(CSRC, s)):
-            jobs.append([hipcc, *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", "-c",
+            jobs.append([hipcc, *HIP_FLAGS, *HIP_SOURCE_FLAGS.get(s, []), f"-I{INCLUDE}", f"-I{CSRC}", "-c",
                          os.path.join(CSRC, s), "-o", os.path.join(BUILD, s + ".o")])
     for s in CXX_SOURCES:
         if os.path.exists(os.path.join(CSRC, s)):
