@@ -29,11 +29,13 @@ HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              # pointer phis and move it to scratch memory
              "-mllvm", "-simplifycfg-sink-common=false",
              "-Wall", "-Wno-unused-result"]
-# per-source additions: the sweep kernels' program dispatch branches on
-# wave-uniform instruction words only, so its control flow needs no
-# structurizing; structurized, every lane exchange (an in-place permlane /
-# DPP swap) first copied the whole register tile
-HIP_SOURCE_FLAGS = {"kernels.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
+# per-source additions: the sweep kernels' and the batched walk's program
+# dispatch branches on wave-uniform instruction words only, so its control
+# flow needs no structurizing; structurized, every lane exchange (an
+# in-place permlane / DPP swap) first copied the whole register tile, and
+# the batched register programs held 220 VGPRs instead of 140
+HIP_SOURCE_FLAGS = {"kernels.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"],
+                    "batch.hip": ["-mllvm", "-structurizecfg-skip-uniform-regions"]}
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-Wno-unused-parameter",
              # complex products by the plain formula: the same values for
              # finite operands, without a library call per product
