@@ -39,9 +39,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector
-# the sweep kernel's source: kernels.hip and the device helpers it includes
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2508_04880_amd", "csrc", f)
-               for f in ("kernels.hip", "regops.hpp")]
+# what the sweep kernel's code depends on: kernels.hip, the device helpers
+# it includes, and the build script that holds its compiler flags
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2508_04880_amd", *f)
+               for f in (("csrc", "kernels.hip"), ("csrc", "regops.hpp"), ("build.py",))]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_pp_brickwork26_traffic.txt")
 
 
