@@ -401,8 +401,8 @@ int tusq_run_batch(tusq_ctx *ctx, const tusq_circuit *const *circs, const tusq_o
  * per workgroup (256 / 512 / 1024), and for states kept in global memory
  * the tile qubits, the low qubits always in a tile and the dense ops per
  * sweep, op lists in LDS or register-blocked programs -- on its
- * probe_jobs jobs with the most gates (at most 2000 shots
- * each), each shape timed twice, and keep the fastest if it beats the
+ * probe_jobs jobs with the most gates (at the call's shot count, at most
+ * 10^4), each shape timed twice, and keep the fastest if it beats the
  * default shape by 3 %; tusq_run_batch then uses it for jobs of that size.
  * With the environment variable TUSQ_TUNE_LOG set, each shape's time goes
  * to stderr. */

@@ -915,8 +915,12 @@ void batch_autotune(Ctx &ctx, const std::vector<const Circuit *> &circs, const t
         });
         v.resize(std::min<size_t>(v.size(), std::max<uint32_t>(probe_jobs, 1)));
     }
+    // probes at the call's shot count (at most 10^4): the tree's leaf count
+    // decides how many units a launch has, and a probe with a fifth of the
+    // shots picked op lists for 15-qubit complex64 jobs that ran the real
+    // jobs 2.2x slower than the register programs
     tusq_opts po = o;
-    po.shots = std::min<uint64_t>(o.shots, 2000);
+    po.shots = std::min<uint64_t>(o.shots, 10000);
     po.want = TUSQ_WANT_SAMPLES;
     po.fusion_max_ops = 0;
     for (auto &kv : by_n) {
