@@ -79,6 +79,17 @@ void Result::dist_copy(double *out) const {
     hip_check(hipMemcpy(out, dist_dev->p, (1ull << n) * 8, hipMemcpyDeviceToHost), "dist readback");
 }
 
+Workspace::~Workspace() {
+    if (host_word && host_word_owned) (void)hipHostFree(host_word);
+}
+double *Workspace::pinned_word() {
+    if (!host_word) {
+        hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_word), 64, hipHostMallocDefault), "hipHostMalloc");
+        host_word_owned = true;
+    }
+    return host_word;
+}
+
 uint64_t Workspace::bytes() const {
     uint64_t b = 0;
     for (const DevBuf *d : {&psi, &psi128, &acc, &csum, &prefix, &norms, &samples, &dops, &mats,
@@ -251,7 +262,7 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     ct.max_norm_drift = 0.0;
     uint64_t passes_since_exact = 0;
     uint64_t sample_off = 0;
-    std::vector<double> hnorm(1);
+    double *hnorm = c64 ? ws.pinned_word() : nullptr;
 
     // queued-work windows of a serving lane: each step counts 2^n amplitudes
     // of work; at the end of a window the host waits for the one before it
@@ -323,7 +334,7 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
                 // drift control: FP64 norm of the complex64 state first
                 hip_check(launch_leaf<V>(st, n, lc, nullptr, 0.0, static_cast<double *>(csum.p),
                                          static_cast<double *>(prefix.p), nrm, s), "norm");
-                hip_check(hipMemcpyAsync(hnorm.data(), nrm, 8, hipMemcpyDeviceToHost, s), "norm readback");
+                hip_check(hipMemcpyAsync(hnorm, nrm, 8, hipMemcpyDeviceToHost, s), "norm readback");
                 hip_check(hipStreamSynchronize(s), "sync");
                 const double drift = std::fabs(hnorm[0] - 1.0);
                 ct.max_norm_drift = std::max(ct.max_norm_drift, drift);
@@ -883,6 +894,8 @@ void execute_plan_static(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_o
     if (want_dist) ws.acc.borrow(dist, N * 8);
     if (want_samples) ws.samples.borrow(samples, samples_len * 8);
     ws.device_outputs = true;
+    double norm_word = 0.0;  // pageable: this run allocates nothing
+    ws.host_word = &norm_word;
     tusq_opts oo = o;
     oo.profile = 0;  // no event pool growth
     if (c64) run_typed<float2>(ctx, t, plan, oo, s, res, ws, nullptr);

@@ -53,6 +53,17 @@ struct Workspace {
     // jobs run at its own time and a small job's kernels never queue behind
     // seconds of a large job's sweeps
     hipEvent_t window[2] = {nullptr, nullptr};
+    // host word for the per-leaf norm readback of complex64 runs: pinned
+    // memory allocated on first use (a copy into pageable memory goes
+    // through a staging buffer), or one the caller lends (the
+    // no-allocation run lends an ordinary host word)
+    double *host_word = nullptr;
+    bool host_word_owned = false;
+    Workspace() = default;
+    Workspace(const Workspace &) = delete;
+    Workspace &operator=(const Workspace &) = delete;
+    ~Workspace();
+    double *pinned_word();
     uint64_t bytes() const;
     void release();
     void set_stream(hipStream_t s);  // every buffer allocates in order on s
