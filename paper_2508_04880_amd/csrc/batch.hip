@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(NT) k_batch(const BUnit *__restrict__ units,
                     // groups run the program in every round (a group with no
                     // tile left runs it on idle registers) so that the
                     // re-layout barriers match.  The host guarantees
-                    // 6 <= k <= the class's tile qubits and a program.
+                    // R <= k <= the class's tile qubits and a program.
                     const uint32_t k = P.k;
                     const uint32_t gsz = 1u << (k - R), groups = nt / gsz;
                     const uint32_t g = tid / gsz, ltid = tid % gsz;
@@ -687,11 +687,9 @@ void batch_typed(Ctx &ctx, const std::vector<const Circuit *> &circs, const tusq
                 bp.prog_inv_end = prog0 + pp.inv_end;
             }
             // the register-blocked launch runs every sweep of a slot state as
-            // a program on whole thread groups: check what it relies on (at
-            // least 6 tile qubits keep the LDS swizzle, which XORs the low 4
-            // or 5 bits of a tile index, inside the group's part)
+            // a program on whole thread groups: check what it relies on
             if (c.n > KL && shapes.at(c.n).reg &&
-                (pp.k < 6 || pp.k > shapes.at(c.n).tile_qubits ||
+                (pp.k < BATCH_REG_QUBITS || pp.k > shapes.at(c.n).tile_qubits ||
                  pp.fwd_end <= pp.fwd_begin || pp.inv_end <= pp.inv_begin))
                 fail(TUSQ_EINVAL, "internal: a batched sweep has no register program for its tile");
             for (uint32_t j2 = 0; j2 < pp.k; ++j2) bp.q[j2] = static_cast<uint8_t>(pp.q[j2]);
