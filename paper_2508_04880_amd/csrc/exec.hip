@@ -80,12 +80,13 @@ void Result::dist_copy(double *out) const {
 }
 
 Workspace::~Workspace() {
-    if (host_word && host_word_owned) (void)hipHostFree(host_word);
+    if (word_ctx) word_ctx->give_word(host_word);
 }
-double *Workspace::pinned_word() {
+double *Workspace::readback_word(Ctx &ctx) {
     if (!host_word) {
-        hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_word), 64, hipHostMallocDefault), "hipHostMalloc");
-        host_word_owned = true;
+        host_word = ctx.take_word();
+        if (host_word) word_ctx = &ctx;
+        else host_word = &spare;
     }
     return host_word;
 }
@@ -262,7 +263,7 @@ void run_typed(Ctx &ctx, const Tree &t, const Plan &plan, const tusq_opts &o, hi
     ct.max_norm_drift = 0.0;
     uint64_t passes_since_exact = 0;
     uint64_t sample_off = 0;
-    double *hnorm = c64 ? ws.pinned_word() : nullptr;
+    double *hnorm = c64 ? ws.readback_word(ctx) : nullptr;
 
     // queued-work windows of a serving lane: each step counts 2^n amplitudes
     // of work; at the end of a window the host waits for the one before it
@@ -787,13 +788,31 @@ Ctx::Ctx(int dev, uint64_t budget_) : device(dev) {
     hip_check(hipMemGetInfo(&fr, &tot), "hipMemGetInfo");
     budget = budget_ ? budget_ : static_cast<uint64_t>(fr);
     hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "stream");
+    // one word per 64 bytes
+    hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_words), HOST_WORDS * 64, hipHostMallocDefault),
+              "hipHostMalloc");
+    for (uint32_t i = HOST_WORDS; i-- > 0;) free_words.push_back(i);
 }
 
 Ctx::~Ctx() {
     (void)hipSetDevice(device);
+    if (host_words) (void)hipHostFree(host_words);
     batch_cache_free(batch);
     for (auto e : pool) (void)hipEventDestroy(e);
     if (stream) (void)hipStreamDestroy(stream);
+}
+
+double *Ctx::take_word() {
+    std::lock_guard<std::mutex> g(mu);
+    if (free_words.empty()) return nullptr;
+    const uint32_t i = free_words.back();
+    free_words.pop_back();
+    return host_words + 8 * i;
+}
+
+void Ctx::give_word(double *w) {
+    std::lock_guard<std::mutex> g(mu);
+    free_words.push_back(static_cast<uint32_t>((w - host_words) / 8));
 }
 
 hipEvent_t Ctx::event() {

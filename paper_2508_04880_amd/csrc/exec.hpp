@@ -37,6 +37,8 @@ struct DevBuf {
 
 // Device buffers of one running job, reusable by the next job on the same
 // execution lane (they only grow).
+struct Ctx;
+
 struct Workspace {
     DevBuf psi, psi128, acc, csum, prefix, norms, samples, dops, mats, mats128, prog;
     DevBuf ckpt;  // checkpoint traversal: saved branch states; caching: cached nodes
@@ -53,17 +55,18 @@ struct Workspace {
     // jobs run at its own time and a small job's kernels never queue behind
     // seconds of a large job's sweeps
     hipEvent_t window[2] = {nullptr, nullptr};
-    // host word for the per-leaf norm readback of complex64 runs: pinned
-    // memory allocated on first use (a copy into pageable memory goes
-    // through a staging buffer), or one the caller lends (the
-    // no-allocation run lends an ordinary host word)
+    // host word for the per-leaf norm readback of complex64 runs: one of
+    // the context's pinned words, taken on first use (a copy into pageable
+    // memory goes through a staging buffer), else `spare`; the
+    // no-allocation run lends an ordinary host word
     double *host_word = nullptr;
-    bool host_word_owned = false;
+    Ctx *word_ctx = nullptr;  // set while host_word is the context's
+    double spare = 0.0;
     Workspace() = default;
     Workspace(const Workspace &) = delete;
     Workspace &operator=(const Workspace &) = delete;
     ~Workspace();
-    double *pinned_word();
+    double *readback_word(Ctx &ctx);
     uint64_t bytes() const;
     void release();
     void set_stream(hipStream_t s);  // every buffer allocates in order on s
@@ -108,11 +111,19 @@ struct Ctx {
     std::map<uint64_t, BatchShape> batch_tuned;  // (qubits << 8 | precision) -> shape
     BatchCache *batch = nullptr;
     std::mutex batch_mu;
+    // pinned host words for complex64 norm readbacks, allocated with the
+    // context: a host allocation during a run can wait for every stream's
+    // queued work, which would stall a job behind the others on the device
+    static constexpr uint32_t HOST_WORDS = 64;
+    double *host_words = nullptr;
+    std::vector<uint32_t> free_words;  // under mu
 
     Ctx(int dev, uint64_t budget);
     ~Ctx();
     hipEvent_t event();
     void recycle(std::vector<hipEvent_t> &evs);
+    double *take_word();  // nullptr when all are taken
+    void give_word(double *w);
 };
 
 // Size of the file-scope device array behind execute_plan_static: the
