@@ -444,12 +444,14 @@ struct Fuser {
     // earlier op of identical (bitwise) matrix
     uint32_t pool(const cd *m, int d) {
         const size_t nb = sizeof(cd) * d * d;
-        // hash of the 64-bit words (equal matrices are then told apart
-        // from colliding ones by comparing the bytes)
+        // hash of 8 of the 64-bit words, spread over entries and real and
+        // imaginary parts (equal matrices are told apart from colliding
+        // ones by comparing all the bytes)
+        static const uint8_t pick4[8] = {0, 5, 10, 15, 16, 21, 26, 31};
         uint64_t h = 0x9E3779B97F4A7C15ull * static_cast<uint64_t>(d);
-        for (size_t i = 0; i < nb / 8; ++i) {
+        for (size_t i = 0; i < 8; ++i) {
             uint64_t w;
-            std::memcpy(&w, reinterpret_cast<const unsigned char *>(m) + 8 * i, 8);
+            std::memcpy(&w, reinterpret_cast<const unsigned char *>(m) + 8 * (d == 4 ? pick4[i] : i), 8);
             h = (h ^ w) * 0xff51afd7ed558ccdull;
             h ^= h >> 29;
         }
@@ -485,39 +487,31 @@ struct Fuser {
     // scratch of fuse and dry_run, reused from call to call
     std::vector<BuildOp> f_ops;
     std::vector<uint32_t> f_keep;
-    std::vector<uint8_t> dr_inq, dr_blocked, dr_one;
-    std::vector<int> dr_last;
+    std::vector<uint8_t> dr_one;
     uint32_t dry_run(const std::vector<Item> &items, const std::vector<uint32_t> &rest,
                      const std::vector<uint8_t> &init, uint32_t nq0) {
         const uint32_t n = c.n;
-        std::vector<uint8_t> &inq = dr_inq, &blocked = dr_blocked;
-        std::vector<int> &last = dr_last;
+        // the tile's and the blocked qubits as bit masks (n <= 34)
+        uint64_t inm = 0, blm = 0;
+        for (uint32_t q = 0; q < n; ++q)
+            if (init[q]) inm |= 1ull << q;
+        int last[64];
+        std::fill(last, last + n, -1);
         std::vector<uint8_t> &one = dr_one;  // per live-or-dead op: 1-qubit?
-        inq.assign(init.begin(), init.end());
-        blocked.assign(n, 0);
-        last.assign(n, -1);
         one.clear();
-        uint32_t nq = nq0, live = 0, taken = 0, nblk_in = 0;
+        uint32_t nq = nq0, live = 0, taken = 0;
         for (uint32_t idx : rest) {
             const Item &it = items[idx];
-            const bool blk = blocked[it.qa] || (it.two && blocked[it.qb]);
-            const uint32_t need = nq + (inq[it.qa] ? 0 : 1) + (it.two && !inq[it.qb] ? 1 : 0);
-            if (blk || need > fp.max_qubits) {
-                for (uint32_t q : {it.qa, it.two ? it.qb : it.qa})
-                    if (!blocked[q]) {
-                        blocked[q] = 1;
-                        if (inq[q]) ++nblk_in;
-                    }
+            const uint64_t m = (1ull << it.qa) | (it.two ? 1ull << it.qb : 0ull);
+            const uint32_t need = nq + static_cast<uint32_t>(__builtin_popcountll(m & ~inm));
+            if ((blm & m) || need > fp.max_qubits) {
+                blm |= m;
                 // a full tile whose qubits are all blocked takes nothing more
-                if (nq == fp.max_qubits && nblk_in == nq) break;
+                if (nq == fp.max_qubits && static_cast<uint32_t>(__builtin_popcountll(blm & inm)) == nq) break;
                 continue;
             }
-            for (uint32_t q : {it.qa, it.two ? it.qb : it.qa})
-                if (!inq[q]) {
-                    inq[q] = 1;
-                    ++nq;
-                    if (blocked[q]) ++nblk_in;
-                }
+            inm |= m;
+            nq = need;
             ++taken;
             if (!it.two) {
                 if (last[it.qa] < 0) {
@@ -588,17 +582,33 @@ struct Fuser {
             uint32_t live = 0, gates = 0, paulis = 0;
             keep.clear();
             bool full = false;
-            for (uint32_t idx : rest) {
+            const uint32_t cap = whole ? n : fp.max_qubits;
+            uint32_t nblk_in = 0;  // tile qubits blocked so far
+            auto block = [&](uint32_t q) {
+                if (!blocked[q]) {
+                    blocked[q] = 1;
+                    if (inq[q]) ++nblk_in;
+                }
+            };
+            for (size_t r = 0; r < rest.size(); ++r) {
+                // nothing later can be taken once the sweep holds its op limit
+                // or its tile is full with every tile qubit blocked: the rest
+                // waits for the next sweep as it is
+                if (full || (nq == cap && nblk_in == nq)) {
+                    keep.insert(keep.end(), rest.begin() + static_cast<std::ptrdiff_t>(r), rest.end());
+                    break;
+                }
+                const uint32_t idx = rest[r];
                 const Item &it = items[idx];
                 const bool blk = blocked[it.qa] || (it.two && blocked[it.qb]);
                 bool take = false;
-                if (!blk && !full) {
+                if (!blk) {
                     uint32_t need = nq + (inq[it.qa] ? 0 : 1) + (it.two && !inq[it.qb] ? 1 : 0);
-                    if (need <= (whole ? n : fp.max_qubits)) take = true;
+                    if (need <= cap) take = true;
                 }
                 if (!take) {
-                    blocked[it.qa] = 1;
-                    if (it.two) blocked[it.qb] = 1;
+                    block(it.qa);
+                    if (it.two) block(it.qb);
                     keep.push_back(idx);
                     continue;
                 }
