@@ -789,8 +789,11 @@ Ctx::Ctx(int dev, uint64_t budget_) : device(dev) {
     budget = budget_ ? budget_ : static_cast<uint64_t>(fr);
     hip_check(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking), "stream");
     // one word per 64 bytes
-    hip_check(hipHostMalloc(reinterpret_cast<void **>(&host_words), HOST_WORDS * 64, hipHostMallocDefault),
-              "hipHostMalloc");
+    const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&host_words), HOST_WORDS * 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(stream);  // the destructor does not run for a throwing constructor
+        hip_check(e, "hipHostMalloc");
+    }
     for (uint32_t i = HOST_WORDS; i-- > 0;) free_words.push_back(i);
 }
 
